@@ -1,0 +1,165 @@
+"""Benchmark of the fused thermal two-component Shan-Chen LB step on one GPU.
+
+A step is one pass of the whole update (pull streaming with bounce-back and
+anti-bounce-back, moments, pseudopotentials, forces, collision, store) over
+the lattice; the timed region runs --steps steps plus one FP64 observable
+reduction at the end. Inputs are seeded synthetic emulsions (see
+``workloads``), resident in HBM before timing starts.
+
+Prints one JSON line with MLUPS (10^6 node updates per second), the HBM
+roofline figures of the step kernel, and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+METRIC = "MLUPS and % HBM roofline (FP32 vs FP16-storage); adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per node update: the 27 populations read once and
+# written once, plus one byte of solid flag when the lattice has solid cells.
+BYTES_PER_POP = {"fp64": 8, "fp32": 4}
+KERNEL_SOURCES = ("paper_2109_12565_amd/csrc/lb_kernels.hpp", "paper_2109_12565_amd/csrc/tlb.hip")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w: dict, sample_steps: int) -> dict:
+    """FP64 oracle (single-threaded C) on the full lattice of the workload
+    for a few steps; MLUPS over the step loop only."""
+    from oracle.oracle import ModelParams, Oracle
+
+    ora = Oracle(ModelParams(**w["params"]), w["rho_a"], w["rho_b"], w["temp"],
+                 solid=w["solid"], t_bottom=w["t_bottom"])
+    t0 = time.perf_counter()
+    ora.step(sample_steps)
+    dt = time.perf_counter() - t0
+    lups = w["lx"] * w["ly"] * sample_steps
+    return {"value": lups / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{sample_steps} steps of the full {w['lx']}x{w['ly']} lattice, FP64, "
+                      f"{dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--config", default="large", choices=sorted(workloads.CONFIGS))
+    ap.add_argument("--precision", default="fp32", choices=sorted(BYTES_PER_POP))
+    ap.add_argument("--cpu-steps", type=int, default=2,
+                    help="oracle steps for the CPU baseline (0 to skip)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before warmup, run 3 plain device copies of this many MiB (a known "
+                         "traffic reference for hardware counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    import torch
+
+    from paper_2109_12565_amd import Simulation
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    w = workloads.CONFIGS[args.config]()
+    print(f"# bench: {w['name']} {args.precision} warmup={args.warmup} steps={args.steps}",
+          file=sys.stderr, flush=True)
+    sim = Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+                     t_bottom=w["t_bottom"], precision=args.precision)
+    sim.step(args.warmup)
+    sim.observables()
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    obs = sim.observables()   # FP64 reductions (synchronises the stream)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    step_ms = e0.elapsed_time(e1)          # the K step launches only
+    total_ms = e0.elapsed_time(e2)         # whole job: steps + observables
+
+    nodes = w["lx"] * w["ly"]
+    mlups = nodes * args.steps / (total_ms * 1e-3) / 1e6
+    per_launch_s = step_ms * 1e-3 / args.steps
+    bpn = 54 * BYTES_PER_POP[args.precision] + (1 if w["solid"] is not None else 0)
+    achieved = bpn * nodes / per_launch_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "lb_step_kernel", "bytes_per_node": bpn, "nodes_per_launch": nodes,
+            "launch_us": round(per_launch_s * 1e6, 2)}
+    traffic = measured_traffic(w["name"], args.precision)
+    if traffic is not None:
+        roof["traffic"] = round(traffic / per_launch_s / 1e9, 1)
+        roof["traffic_bytes_per_launch"] = traffic
+
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total_ms / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64"}[args.precision], "data": "synthetic",
+        "config": {"workload": w["name"], "lx": w["lx"], "ly": w["ly"], "storage": args.precision,
+                   "droplets": int(w["n_droplets"]), "solid_cells": 0 if w["solid"] is None
+                   else int((w["solid"] != 0).sum()), "observables": "once at the end",
+                   "seed": w["seed"]},
+        "roofline": roof,
+        "check": {"mass_a": obs["mass_a"], "mass_b": obs["mass_b"], "nu": obs["nu"],
+                  "wall_s": round(wall, 3)},
+    }
+    if args.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+    sim.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

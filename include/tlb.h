@@ -1,0 +1,156 @@
+/*
+ * tlb.h - C ABI of the MI355X (gfx950) library for the thermal two-component
+ * Shan-Chen lattice Boltzmann update of TLBfind (arXiv:2109.12565, Sec. 2).
+ *
+ * The library evolves, on one GPU, the 2D model of Sec. 2: two D2Q9 BGK fluid
+ * components (Sec. 2.1 Eqs. (1)-(3)) coupled by the cross force (Eq. (7)) and
+ * by self forces with short-range attraction (Eq. (10)) and mid-range
+ * repulsion on a 25-point stencil (Eq. (11), weights of Fig. 1(b)); D2Q9
+ * temperature populations (Sec. 2.3 Eqs. (16)-(18)) advected by the
+ * hydrodynamic velocity and feeding back through Boussinesq buoyancy
+ * (Eq. (22)); solid walls below and above the channel with wetting densities
+ * (Sec. 2.2.1) and half-way bounce-back (Sec. 2.2), walls held at fixed
+ * temperatures (Sec. 3.2.3); periodic x.
+ *
+ * Lattice and arrays. The lattice has lx columns (x, periodic) and ly rows
+ * (y). Every host field array is ly*lx doubles, row-major with x fastest.
+ * The wall planes lie half a cell below row 0 and half a cell above row
+ * ly-1. Populations are indexed in this direction order (c_x, c_y):
+ *   0 (0,0)  1 (1,0)  2 (0,1)  3 (-1,0)  4 (0,-1)
+ *   5 (1,1)  6 (-1,1) 7 (-1,-1) 8 (1,-1)
+ * and population arrays are [27][ly][lx]: f_A (0..8), f_B (9..17), g (18..26).
+ *
+ * Time. After tlb_init the state is at t = 0; tlb_step(n) advances to t + n.
+ * Fields and observables at time t are the moments of the pre-collision
+ * populations f(t) and the hydrodynamic velocity u^H(t) (Sec. 2.1: rho u^H =
+ * rho u + F/2).
+ *
+ * Return codes: every function returns TLB_OK (0) or a negative code. No C++
+ * exception crosses the ABI. The message of the last failure is returned by
+ * tlb_last_error.
+ *
+ * Threading and streams: one handle is used by one host thread at a time.
+ * All device work of a handle is enqueued on the stream given at init (or
+ * on a stream the library creates); tlb_step only enqueues work, the calls
+ * that return data to the host synchronise that stream.
+ */
+#ifndef TLB_H
+#define TLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum tlb_status {
+  TLB_OK = 0,
+  TLB_EINVAL = -1,   /* bad argument: NULL pointer, size, tau <= 1/2, precision */
+  TLB_ENOMEM = -2,   /* device or host allocation failed */
+  TLB_EDEVICE = -3,  /* a HIP call failed (message in tlb_last_error) */
+  TLB_ENUMERIC = -4, /* NaN or Inf in the FP64 mass reduction */
+  TLB_ESTATE = -5    /* call not valid in the handle's current state */
+};
+
+/* Storage type of the populations in device memory. Collisions are computed
+ * in FP64 for TLB_FP64 and in FP32 otherwise. */
+enum tlb_precision {
+  TLB_FP64 = 0,
+  TLB_FP32 = 1
+};
+
+/* Model constants (Sec. 2; values of Appendix A in parentheses). */
+typedef struct tlb_params {
+  int32_t lx, ly;        /* lattice size: lx >= 1, ly >= 1 */
+  int32_t precision;     /* enum tlb_precision */
+  int32_t reserved;      /* set to 0 */
+  double tau;            /* fluid relaxation time, > 1/2 (1.0) */
+  double tau_g;          /* thermal relaxation time, > 1/2 (1.0) */
+  double rho0;           /* pseudopotential reference density, > 0 (0.83) */
+  double g12;            /* cross coupling G_12 of Eq. (7) (0.405) */
+  double g_a[2];         /* attraction G^a_11, G^a_22 of Eq. (10) (-9.0, -8.0) */
+  double g_r[2];         /* repulsion G^r_11, G^r_22 of Eq. (11) (8.1, 7.1) */
+  double alpha_g;        /* buoyancy alpha*g of Eq. (22) */
+  double t_top;          /* top wall temperature */
+  double rho_wall[2];    /* wetting densities of both components at solid
+                            nodes (Sec. 2.2.1) (0.612, 0.612) */
+  double dt_nominal;     /* Delta T in the Nusselt normalisation, != 0 */
+} tlb_params;
+
+/* Observables at time `step` (Sec. 3.1, Sec. 3.3.2 Eq. (24)); sums and means
+ * run over fluid nodes and are accumulated in FP64:
+ *   mass_a, mass_b  sum of rho_A, rho_B
+ *   sum_t           sum of T
+ *   nu              (<u^H_y T> - kappa <dT/dy>) / (kappa dt_nominal / ly),
+ *                   kappa = (tau_g - 1/2)/3, dT/dy by central differences
+ *                   with the mirror value 2 T_w - T at a solid neighbour
+ *   nu_top          2 ly / dt_nominal * mean over fluid nodes of row ly-1 of
+ *                   (T - t_top): the top-wall heat flux in Nusselt units
+ *   ke              mean of |u^H|^2 */
+typedef struct tlb_obs {
+  int64_t step;
+  double mass_a, mass_b, sum_t, nu, nu_top, ke;
+} tlb_obs;
+
+typedef struct tlb_handle tlb_handle;
+
+/* Create a handle and set the state at t = 0 to the equilibria of the given
+ * densities, temperature and velocity (Sec. 2.1 Eq. (3), Sec. 2.3 Eq. (18)).
+ *   out        receives the handle (set to NULL on failure)
+ *   p          model constants (copied)
+ *   rho_a, rho_b, temp   host, ly*lx: initial densities and temperature
+ *   ux0, uy0   host, ly*lx, or NULL for a fluid at rest
+ *   solid      host, ly*lx, or NULL for flat walls only: 0 fluid node,
+ *              1 solid node held at the bottom temperature of its column,
+ *              2 solid node held at t_top
+ *   t_bottom   host, lx: bottom wall temperature per column
+ *   hip_stream hipStream_t to run on, or NULL for a library-owned stream
+ * Host arrays are read during the call only. Device memory is owned by the
+ * handle until tlb_destroy. Errors: TLB_EINVAL, TLB_ENOMEM, TLB_EDEVICE. */
+int tlb_init(tlb_handle **out, const tlb_params *p, const double *rho_a,
+             const double *rho_b, const double *temp, const double *ux0,
+             const double *uy0, const uint8_t *solid, const double *t_bottom,
+             void *hip_stream);
+
+/* Advance nsteps >= 0 time steps of Eqs. (1) and (16): per node, pull
+ * streaming with bounce-back / anti-bounce-back at solid links, moments,
+ * forces, velocity shift (Eq. (6)) and BGK collision. Enqueues only. */
+int tlb_step(tlb_handle *h, int64_t nsteps);
+
+/* Observables at the current time (synchronises the stream). Returns
+ * TLB_ENUMERIC if a component mass is not finite. */
+int tlb_observables(tlb_handle *h, tlb_obs *out);
+
+/* Fields at the current time into host arrays of ly*lx doubles (any may be
+ * NULL): densities, hydrodynamic velocity u^H and temperature. Solid nodes
+ * report the wall densities, zero velocity and their wall temperature.
+ * Synchronises the stream. */
+int tlb_get_fields(tlb_handle *h, double *rho_a, double *rho_b, double *ux,
+                   double *uy, double *temp);
+
+/* Post-collision populations f*(t) of the current time (the state the next
+ * step streams) as host doubles [27][ly][lx]; zero at solid nodes.
+ * Synchronises the stream. */
+int tlb_get_populations(tlb_handle *h, double *out);
+
+/* Replace the bottom wall temperature (host, lx values); takes effect for
+ * the following steps and observable evaluations. */
+int tlb_set_bottom_temperature(tlb_handle *h, const double *t_bottom);
+
+/* Current time step. Returns -1 for a NULL handle. */
+int64_t tlb_time(const tlb_handle *h);
+
+/* Free the handle and its device memory. NULL is accepted. */
+int tlb_destroy(tlb_handle *h);
+
+/* Message of the last failure on h (or of the calling thread's last failed
+ * tlb_init when h is NULL); empty string if none. Valid until the next call
+ * on the same handle. */
+const char *tlb_last_error(const tlb_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TLB_H */

@@ -73,6 +73,7 @@ def _load():
         lib.ora_populations.argtypes = [ctypes.c_void_p, dp, dp, dp]
         lib.ora_post_collision.argtypes = [ctypes.c_void_p, dp, dp, dp]
         lib.ora_observables.argtypes = [ctypes.c_void_p, dp]
+        lib.ora_load_post_collision.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.c_int64]
         _lib = lib
     return _lib
 
@@ -169,6 +170,15 @@ class Oracle:
         out = np.empty((27, ly, lx))
         _load().ora_post_collision(self._h, _dp(out[0:9]), _dp(out[9:18]), _dp(out[18:27]))
         return out
+
+    def load_post_collision(self, pop, t: int) -> "Oracle":
+        """Set the state to the streaming of post-collision populations
+        ``pop`` ([27, ly, lx]: f*_A, f*_B, g*) and the time to ``t``."""
+        pop = np.ascontiguousarray(pop, dtype=np.float64)
+        if pop.shape != (27, *self.shape):
+            raise ValueError("populations must be [27, ly, lx]")
+        _load().ora_load_post_collision(self._h, _dp(pop[0:9]), _dp(pop[9:18]), _dp(pop[18:27]), int(t))
+        return self
 
     def observables(self) -> dict:
         out = np.empty(6)

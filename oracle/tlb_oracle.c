@@ -526,3 +526,17 @@ void ora_observables(ora_state *s, double *out) {
   out[4] = ntop ? 2.0 * ly / s->p.dt_nominal * (top / (double)ntop) : 0.0;
   out[5] = ke * inv;
 }
+
+/* Replace the state by the streaming of the given post-collision
+ * populations (three [9][ly][lx] arrays) and set the time to t: the state
+ * becomes f(t) = stream(f*(t-1)). Used to check one step of another
+ * implementation from its own post-collision state. */
+void ora_load_post_collision(ora_state *s, const double *fa, const double *fb,
+                             const double *g, int64_t t) {
+  size_t b = sizeof(double) * 9 * (size_t)s->n;
+  memcpy(s->fs[0], fa, b);
+  memcpy(s->fs[1], fb, b);
+  memcpy(s->gs, g, b);
+  stream(s);
+  s->t = t;
+}

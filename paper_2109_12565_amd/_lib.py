@@ -1,0 +1,219 @@
+"""ctypes binding of the C ABI in ``include/tlb.h`` (argument marshalling only).
+
+Every step of the lattice Boltzmann update runs in the HIP library
+``lib/libtlb.so``; this module converts numpy arrays to the plain pointers the
+ABI takes and turns return codes into exceptions. It never computes any part
+of the method and there is no fallback: if the library is missing, loading
+fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libtlb.so")
+
+TLB_OK, TLB_EINVAL, TLB_ENOMEM, TLB_EDEVICE, TLB_ENUMERIC, TLB_ESTATE = 0, -1, -2, -3, -4, -5
+PRECISIONS = {"fp64": 0, "fp32": 1}
+
+# Every symbol the header declares (checked by the CPU test suite).
+EXPORTS = (
+    "tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_populations",
+    "tlb_set_bottom_temperature", "tlb_time", "tlb_destroy", "tlb_last_error",
+)
+
+
+class TlbError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"[{code}] {message}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("lx", ctypes.c_int32), ("ly", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("tau_g", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("g12", ctypes.c_double),
+        ("g_a", ctypes.c_double * 2), ("g_r", ctypes.c_double * 2),
+        ("alpha_g", ctypes.c_double), ("t_top", ctypes.c_double),
+        ("rho_wall", ctypes.c_double * 2), ("dt_nominal", ctypes.c_double),
+    ]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("mass_a", ctypes.c_double), ("mass_b", ctypes.c_double),
+                ("sum_t", ctypes.c_double), ("nu", ctypes.c_double), ("nu_top", ctypes.c_double),
+                ("ke", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load ``libtlb.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"HIP library not built: {path} is missing (run `python -m paper_2109_12565_amd.build`)")
+    # torch ships its own HIP runtime and opens it under a file name that does
+    # not match the SONAME of the system copy this library links; loading
+    # torch first makes both resolve to torch's copy, so the process holds a
+    # single HIP runtime and torch's streams are valid handles here.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    vp = ctypes.c_void_p
+    lib.tlb_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), dp, dp, dp, dp, dp,
+                             ctypes.POINTER(ctypes.c_uint8), dp, vp]
+    lib.tlb_step.argtypes = [vp, ctypes.c_int64]
+    lib.tlb_observables.argtypes = [vp, ctypes.POINTER(Obs)]
+    lib.tlb_get_fields.argtypes = [vp, dp, dp, dp, dp, dp]
+    lib.tlb_get_populations.argtypes = [vp, dp]
+    lib.tlb_set_bottom_temperature.argtypes = [vp, dp]
+    lib.tlb_time.argtypes = [vp]
+    lib.tlb_time.restype = ctypes.c_int64
+    lib.tlb_destroy.argtypes = [vp]
+    lib.tlb_last_error.argtypes = [vp]
+    lib.tlb_last_error.restype = ctypes.c_char_p
+    for name in ("tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_populations",
+                 "tlb_set_bottom_temperature", "tlb_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _field(a, shape, name):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if a.shape != shape:
+        raise ValueError(f"{name}: expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _current_stream():
+    """torch's current HIP stream on the current device, or None."""
+    try:
+        import torch
+    except ImportError:
+        return None
+    if not torch.cuda.is_available():
+        return None
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Simulation:
+    """A lattice state on the GPU behind one ``tlb_handle``.
+
+    ``params`` holds the model constants named as in ``tlb_params`` (tau,
+    tau_g, rho0, g12, g_a, g_r, alpha_g, t_top, rho_wall, dt_nominal).
+    Field arrays are (ly, lx) with x fastest. By default the work runs on
+    torch's current stream.
+    """
+
+    def __init__(self, params: dict, rho_a, rho_b, temp, *, solid=None, t_bottom=None,
+                 ux0=None, uy0=None, precision: str = "fp32", stream="torch"):
+        self._lib = load_library()
+        self._h = ctypes.c_void_p()
+        rho_a = np.ascontiguousarray(np.asarray(rho_a, dtype=np.float64))
+        if rho_a.ndim != 2:
+            raise ValueError("rho_a must be 2-D (ly, lx)")
+        ly, lx = rho_a.shape
+        self.shape = (ly, lx)
+        rho_b = _field(rho_b, self.shape, "rho_b")
+        temp = _field(temp, self.shape, "temp")
+        ux0 = _field(ux0, self.shape, "ux0")
+        uy0 = _field(uy0, self.shape, "uy0")
+        if (ux0 is None) != (uy0 is None):
+            raise ValueError("give both ux0 and uy0 or neither")
+        sol = None
+        if solid is not None:
+            sol = np.ascontiguousarray(np.asarray(solid, dtype=np.uint8))
+            if sol.shape != self.shape:
+                raise ValueError(f"solid: expected shape {self.shape}, got {sol.shape}")
+        if t_bottom is None:
+            t_bottom = 1.0
+        t_bottom = np.ascontiguousarray(np.broadcast_to(np.asarray(t_bottom, np.float64), (lx,)))
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        p = Params()
+        p.lx, p.ly, p.precision, p.reserved = lx, ly, PRECISIONS[precision], 0
+        p.tau, p.tau_g = params["tau"], params["tau_g"]
+        p.rho0, p.g12 = params["rho0"], params["g12"]
+        p.g_a[0], p.g_a[1] = params["g_a"]
+        p.g_r[0], p.g_r[1] = params["g_r"]
+        p.alpha_g, p.t_top = params["alpha_g"], params["t_top"]
+        p.rho_wall[0], p.rho_wall[1] = params["rho_wall"]
+        p.dt_nominal = params["dt_nominal"]
+        self.params = p
+        self.precision = precision
+        s = _current_stream() if stream == "torch" else stream
+        rc = self._lib.tlb_init(ctypes.byref(self._h), ctypes.byref(p), _dp(rho_a), _dp(rho_b),
+                                _dp(temp), _dp(ux0), _dp(uy0),
+                                None if sol is None else sol.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                _dp(t_bottom), ctypes.c_void_p(s) if s else None)
+        if rc != TLB_OK:
+            raise TlbError(rc, self._lib.tlb_last_error(None).decode())
+
+    def _check(self, rc):
+        if rc != TLB_OK:
+            raise TlbError(rc, self._lib.tlb_last_error(self._h).decode())
+
+    @property
+    def t(self) -> int:
+        return int(self._lib.tlb_time(self._h))
+
+    def step(self, n: int = 1) -> "Simulation":
+        self._check(self._lib.tlb_step(self._h, int(n)))
+        return self
+
+    def observables(self) -> dict:
+        o = Obs()
+        self._check(self._lib.tlb_observables(self._h, ctypes.byref(o)))
+        return {k: getattr(o, k) for k, _ in Obs._fields_}
+
+    def fields(self) -> dict:
+        ly, lx = self.shape
+        out = {k: np.empty((ly, lx)) for k in ("rho_a", "rho_b", "ux", "uy", "temp")}
+        self._check(self._lib.tlb_get_fields(self._h, *(_dp(out[k]) for k in
+                                                       ("rho_a", "rho_b", "ux", "uy", "temp"))))
+        return out
+
+    def populations(self) -> np.ndarray:
+        """Post-collision f*_A, f*_B, g* of the current time, [27, ly, lx]."""
+        ly, lx = self.shape
+        out = np.empty((27, ly, lx))
+        self._check(self._lib.tlb_get_populations(self._h, _dp(out)))
+        return out
+
+    def set_bottom_temperature(self, t_bottom) -> None:
+        tb = np.ascontiguousarray(np.broadcast_to(np.asarray(t_bottom, np.float64), (self.shape[1],)))
+        self._check(self._lib.tlb_set_bottom_temperature(self._h, _dp(tb)))
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.tlb_destroy(h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,590 @@
+// Device code of the thermal two-component Shan-Chen lattice Boltzmann step
+// (arXiv:2109.12565, Sec. 2) for gfx950.
+//
+// One fused kernel does the whole time step t -> t+1 for a strip of BX
+// columns and a chunk of rows of the lattice:
+//
+//   pull     f(x, t+1) = f*(x - c_i, t) from the post-collision buffer
+//            (Eqs. (1), (16)); a link whose source is solid is bounced back
+//            (half-way, Sec. 2.2) for f and anti-bounced for g, holding the
+//            wall temperature;
+//   moments  rho_A, rho_B, j, T (Eqs. (4), (5), (17));
+//   psi      rho/rho0 (Eq. (8)) and rho0 (1 - exp(-rho/rho0)) (Eq. (12)),
+//            staged in an LDS ring of 6 rows x (BX + 4) columns: the 25-point
+//            stencil of Eq. (11) needs 2 rows and 2 columns of halo;
+//   forces   Eqs. (7), (10), (11) from LDS plus buoyancy (Eq. (22));
+//   collide  velocity shift (Eq. (6)), u^H = u + F/(2 rho), BGK towards
+//            f^eq(rho_l, u_l) (Eq. (3)) and g^eq(T, u^H) (Eq. (18));
+//   store    27 aligned, coalesced stores into the other buffer.
+//
+// The strip marches upward one row per iteration. Iteration r pulls f_A, f_B
+// at row r (kept in registers for two iterations), writes that row's
+// densities and pseudopotentials to the ring, waits once at a barrier, and
+// completes row r - 2, whose 5 x 5 neighbourhood is then in the ring. Rows
+// are therefore pulled once from HBM; only the 4 halo columns per strip and
+// the 4 halo rows per chunk are pulled twice. The ring has 6 slots, so a
+// single barrier per row separates the writes of row r + 1 from the reads of
+// row r - 2.
+//
+// Memory layout: population p (0..26) of node (x, y) lives at
+// buf[p * pop_stride + y * pitch + x]; pitch is a multiple of 64 elements so
+// every wavefront row access is aligned.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tlbk {
+
+// ---------------------------------------------------------------- lattice
+// D2Q9 velocities (Sec. 2.1, Fig. 1(b)) in the library's direction order.
+template <int I> struct Dir;
+template <> struct Dir<0> { static constexpr int cx = 0,  cy = 0,  opp = 0; };
+template <> struct Dir<1> { static constexpr int cx = 1,  cy = 0,  opp = 3; };
+template <> struct Dir<2> { static constexpr int cx = 0,  cy = 1,  opp = 4; };
+template <> struct Dir<3> { static constexpr int cx = -1, cy = 0,  opp = 1; };
+template <> struct Dir<4> { static constexpr int cx = 0,  cy = -1, opp = 2; };
+template <> struct Dir<5> { static constexpr int cx = 1,  cy = 1,  opp = 7; };
+template <> struct Dir<6> { static constexpr int cx = -1, cy = 1,  opp = 8; };
+template <> struct Dir<7> { static constexpr int cx = -1, cy = -1, opp = 5; };
+template <> struct Dir<8> { static constexpr int cx = 1,  cy = -1, opp = 6; };
+
+__host__ __device__ constexpr int dir_cx(int i) {
+  return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int dir_cy(int i) {
+  return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0);
+}
+// D2Q9 weights as a function of |c|^2: 4/9, 1/9, 1/36.
+template <typename C> __host__ __device__ constexpr C w_c2(int c2) {
+  return c2 == 0 ? C(4) / C(9) : (c2 == 1 ? C(1) / C(9) : (c2 == 2 ? C(1) / C(36) : C(0)));
+}
+template <typename C> __host__ __device__ constexpr C w_dir(int i) {
+  return w_c2<C>(dir_cx(i) * dir_cx(i) + dir_cy(i) * dir_cy(i));
+}
+// 25-point weights p(|c|^2) of Fig. 1(b) (NN + NNN shells).
+template <typename C> __host__ __device__ constexpr C p_c2(int c2) {
+  return c2 == 0 ? C(247) / C(420)
+       : c2 == 1 ? C(4) / C(63)
+       : c2 == 2 ? C(4) / C(135)
+       : c2 == 4 ? C(1) / C(180)
+       : c2 == 5 ? C(2) / C(945)
+       : c2 == 8 ? C(1) / C(15120)
+       : C(0);
+}
+
+// Link-mask bits: bit 0 = node itself is solid, bit i (1..8) = the source
+// node x - c_i of direction i is solid (ghost wall row or solid cell).
+constexpr uint32_t kSelfSolid = 1u;
+// Directions whose source lies below (c_y = +1) / above (c_y = -1).
+constexpr uint32_t kFromBelow = (1u << 2) | (1u << 5) | (1u << 6);
+constexpr uint32_t kFromAbove = (1u << 4) | (1u << 7) | (1u << 8);
+
+// ---------------------------------------------------------------- storage
+template <typename T_> struct Store {
+  using T = T_;
+  using C = T_;
+  __device__ static C load(const T* p) { return *p; }
+  __device__ static void store(T* p, C v) { *p = v; }
+};
+
+// ---------------------------------------------------------------- arguments
+template <typename C>
+struct StepArgs {
+  const void* src;          // post-collision populations f*(t) (or f(0))
+  void* dst;                // receives f*(t+1)
+  const uint16_t* link;     // [ly*lx] link masks (solid cells present only)
+  const uint8_t* solid;     // [ly*lx] 0 fluid, 1 bottom-held, 2 top-held
+  const C* t_bottom;        // [lx]
+  double* partials;         // [gridDim.x*gridDim.y][8] observable sums
+  double* fields;           // [5][ly][lx] rho_a, rho_b, ux, uy, T
+  int lx, ly, pitch, rows_per_block;
+  long long pop_stride;     // ly * pitch
+  C inv_tau, inv_tau_g, tau, rho0, inv_rho0, g12;
+  C ga0, ga1, gr0, gr1;
+  C alpha_g, t_top, rho_wall0, rho_wall1;
+};
+
+// Kernel variants.
+enum : unsigned {
+  kModeInit = 1u,     // read f(0) at the node itself instead of pulling
+  kModeStore = 2u,    // write f*(t+1)
+  kModeObserve = 4u,  // accumulate observable sums into partials
+  kModeFields = 8u,   // write the fields
+  kModeSolid = 16u    // solid cells present: use the link masks
+};
+
+template <typename C> __device__ inline C psi_exp(C rho, C rho0, C inv_rho0) {
+  // rho0 (1 - exp(-rho/rho0)) of Eq. (12), evaluated as -rho0 expm1(-rho/rho0)
+  // to keep full relative precision at small rho.
+  return -rho0 * expm1(-rho * inv_rho0);
+}
+__device__ inline float psi_exp(float rho, float rho0, float inv_rho0) {
+  return -rho0 * expm1f(-rho * inv_rho0);
+}
+
+// Link mask of node (x, r), 0 <= r < ly.
+template <unsigned kMode, typename C>
+__device__ inline uint32_t link_mask(const StepArgs<C>& a, int x, int r) {
+  if constexpr ((kMode & kModeSolid) != 0) {
+    return a.link[(size_t)r * a.lx + x];
+  } else {
+    return (r == 0 ? kFromBelow : 0u) | (r == a.ly - 1 ? kFromAbove : 0u);
+  }
+}
+
+// Element offset (within one population plane) and population index of the
+// value pulled for direction I at node (x, r); xm/xp are the wrapped x-1 and
+// x+1.
+template <int I, unsigned kMode>
+__device__ inline void pull_site(uint32_t lm, int x, int xm, int xp, int r, int pitch,
+                                 int& pop, int& off) {
+  if constexpr ((kMode & kModeInit) != 0) {
+    pop = I;
+    off = r * pitch + x;
+  } else {
+    constexpr int cx = Dir<I>::cx, cy = Dir<I>::cy;
+    const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
+    const bool bounce = (lm >> I) & 1u;
+    pop = bounce ? Dir<I>::opp : I;
+    off = bounce ? r * pitch + x : (r - cy) * pitch + sx;
+  }
+}
+
+// Pull f_A and f_B at fluid node (x, r).
+template <class St, unsigned kMode, typename C>
+__device__ inline void pull_fluid(const StepArgs<C>& a, const typename St::T* __restrict__ src,
+                                  uint32_t lm, int x, int xm, int xp, int r, C (&fa)[9],
+                                  C (&fb)[9]) {
+  const long long ps = a.pop_stride;
+#define TLB_PULL_F(I)                                                  \
+  {                                                                    \
+    int pop, off;                                                      \
+    pull_site<I, kMode>(lm, x, xm, xp, r, a.pitch, pop, off);          \
+    fa[I] = St::load(src + (long long)pop * ps + off);                 \
+    fb[I] = St::load(src + (long long)(pop + 9) * ps + off);           \
+  }
+  TLB_PULL_F(0) TLB_PULL_F(1) TLB_PULL_F(2) TLB_PULL_F(3) TLB_PULL_F(4)
+  TLB_PULL_F(5) TLB_PULL_F(6) TLB_PULL_F(7) TLB_PULL_F(8)
+#undef TLB_PULL_F
+}
+
+// Wall temperature of the solid source of direction I seen from (x, r).
+template <int I, unsigned kMode, typename C>
+__device__ inline C source_wall_temperature(const StepArgs<C>& a, int x, int xm, int xp, int r) {
+  constexpr int cx = Dir<I>::cx, cy = Dir<I>::cy;
+  const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
+  const int sr = r - cy;
+  if (sr < 0) return a.t_bottom[sx];
+  if (sr >= a.ly) return a.t_top;
+  if constexpr ((kMode & kModeSolid) != 0) {
+    return a.solid[(size_t)sr * a.lx + sx] == 1 ? a.t_bottom[sx] : a.t_top;
+  }
+  return a.t_top;
+}
+
+// Pull g at fluid node (x, r) with anti-bounce-back at solid sources:
+// g_i = -g*_{opp i}(x) + 2 w_i T_w.
+template <class St, unsigned kMode, typename C>
+__device__ inline void pull_thermal(const StepArgs<C>& a, const typename St::T* __restrict__ src,
+                                    uint32_t lm, int x, int xm, int xp, int r, C (&g)[9]) {
+  const long long ps = a.pop_stride;
+#define TLB_PULL_G(I)                                                            \
+  {                                                                              \
+    int pop, off;                                                                \
+    pull_site<I, kMode>(lm, x, xm, xp, r, a.pitch, pop, off);                    \
+    C v = St::load(src + (long long)(pop + 18) * ps + off);                      \
+    if constexpr ((kMode & kModeInit) == 0 && I != 0) {                          \
+      if ((lm >> I) & 1u)                                                        \
+        v = C(2) * w_dir<C>(I) * source_wall_temperature<I, kMode>(a, x, xm, xp, r) - v; \
+    }                                                                            \
+    g[I] = v;                                                                    \
+  }
+  TLB_PULL_G(0) TLB_PULL_G(1) TLB_PULL_G(2) TLB_PULL_G(3) TLB_PULL_G(4)
+  TLB_PULL_G(5) TLB_PULL_G(6) TLB_PULL_G(7) TLB_PULL_G(8)
+#undef TLB_PULL_G
+}
+
+template <typename C> __device__ inline C sum9(const C (&f)[9]) {
+  return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+}
+
+// Wall temperature of a solid node (x, y) inside the lattice.
+template <typename C>
+__device__ inline C solid_temperature(const StepArgs<C>& a, int x, int y) {
+  return a.solid[(size_t)y * a.lx + x] == 1 ? a.t_bottom[x] : a.t_top;
+}
+
+// Temperature of the neighbour (x, r) of a fluid node whose temperature is
+// t_here, for the central difference of dT/dy: T itself if fluid, else the
+// mirror value 2 T_w - t_here (wall plane half-way).
+template <class St, unsigned kMode, typename C>
+__device__ inline C neighbour_temperature(const StepArgs<C>& a, const typename St::T* __restrict__ src,
+                                          int x, int xm, int xp, int r, C t_here) {
+  if (r < 0) return C(2) * a.t_bottom[x] - t_here;
+  if (r >= a.ly) return C(2) * a.t_top - t_here;
+  const uint32_t lm = link_mask<kMode>(a, x, r);
+  if (lm & kSelfSolid) return C(2) * solid_temperature(a, x, r) - t_here;
+  C g[9];
+  pull_thermal<St, kMode>(a, src, lm, x, xm, xp, r, g);
+  return sum9(g);
+}
+
+// ---------------------------------------------------------------- kernel
+template <class St, int BX, unsigned kMode>
+__global__ __launch_bounds__(BX) void lb_step_kernel(StepArgs<typename St::C> a) {
+  using C = typename St::C;
+  using T = typename St::T;
+  constexpr int W = BX + 4;   // ring row width: strip plus 2 halo columns each side
+  constexpr int R = 6;        // ring rows
+  __shared__ C s_rho[2][R][W];
+  __shared__ C s_psi[2][R][W];
+
+  const T* __restrict__ src = static_cast<const T*>(a.src);
+  T* __restrict__ dst = static_cast<T*>(a.dst);
+  const int lx = a.lx, ly = a.ly;
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * BX;
+  const int y0 = blockIdx.y * a.rows_per_block;
+  const int y1 = min(y0 + a.rows_per_block, ly);
+
+  // own column (idle threads of a ragged strip still fill their ring slot,
+  // with a wrapped column, so the halo of the last valid column is right)
+  const int xo = x0 + tid;
+  const bool own_valid = xo < lx;
+  const int xw = xo % lx;
+  const int xwm = xw == 0 ? lx - 1 : xw - 1;
+  const int xwp = xw == lx - 1 ? 0 : xw + 1;
+
+  // halo slots 0, 1, BX+2, BX+3: one thread in each quarter of the block
+  constexpr int kQuarter = BX / 4;
+  const bool is_halo = (tid % kQuarter) == 0;
+  const int hq = tid / kQuarter;
+  const int hslot = hq < 2 ? hq : BX + hq;
+  const int hx = ((x0 - 2 + hslot) % lx + lx) % lx;
+  const int hxm = hx == 0 ? lx - 1 : hx - 1;
+  const int hxp = hx == lx - 1 ? 0 : hx + 1;
+
+  const C psi_w0 = psi_exp(a.rho_wall0, a.rho0, a.inv_rho0);
+  const C psi_w1 = psi_exp(a.rho_wall1, a.rho0, a.inv_rho0);
+
+  C fa0[9], fb0[9], fa1[9], fb1[9], fa2[9], fb2[9];
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  // Density of node (x, r) (wall values at ghost rows and solid nodes).
+  auto density = [&](int x, int xm, int xp, int r, C (&fa)[9], C (&fb)[9], C& ra, C& rb) {
+    if (r < 0 || r >= ly) {
+      ra = a.rho_wall0;
+      rb = a.rho_wall1;
+      return;
+    }
+    const uint32_t lm = link_mask<kMode>(a, x, r);
+    if ((kMode & kModeSolid) != 0 && (lm & kSelfSolid)) {
+      ra = a.rho_wall0;
+      rb = a.rho_wall1;
+      return;
+    }
+    pull_fluid<St, kMode>(a, src, lm, x, xm, xp, r, fa, fb);
+    ra = sum9(fa);
+    rb = sum9(fb);
+  };
+
+  const int r_first = y0 - 2;
+  const int n_iter = (y1 - y0) + 4;
+  for (int k = 0; k < n_iter; ++k) {
+    const int r = r_first + k;
+    const int slot = k % R;
+    {
+      C ra, rb;
+      density(xw, xwm, xwp, r, fa2, fb2, ra, rb);
+      s_rho[0][slot][tid + 2] = ra;
+      s_rho[1][slot][tid + 2] = rb;
+      s_psi[0][slot][tid + 2] = (r < 0 || r >= ly) ? psi_w0 : psi_exp(ra, a.rho0, a.inv_rho0);
+      s_psi[1][slot][tid + 2] = (r < 0 || r >= ly) ? psi_w1 : psi_exp(rb, a.rho0, a.inv_rho0);
+    }
+    if (is_halo) {
+      C ha[9], hb[9], ra, rb;
+      density(hx, hxm, hxp, r, ha, hb, ra, rb);
+      s_rho[0][slot][hslot] = ra;
+      s_rho[1][slot][hslot] = rb;
+      s_psi[0][slot][hslot] = (r < 0 || r >= ly) ? psi_w0 : psi_exp(ra, a.rho0, a.inv_rho0);
+      s_psi[1][slot][hslot] = (r < 0 || r >= ly) ? psi_w1 : psi_exp(rb, a.rho0, a.inv_rho0);
+    }
+    __syncthreads();
+
+    const int y = r - 2;  // row completed in this iteration
+    if (k >= 4 && own_valid) {
+      const uint32_t lm = link_mask<kMode>(a, xw, y);
+      const long long ps = a.pop_stride;
+      const int off = y * a.pitch + xo;
+      if ((kMode & kModeSolid) != 0 && (lm & kSelfSolid)) {
+        if constexpr ((kMode & kModeStore) != 0) {
+#pragma unroll
+          for (int p = 0; p < 27; ++p) St::store(dst + p * ps + off, C(0));
+        }
+        if constexpr ((kMode & kModeFields) != 0) {
+          const size_t n = (size_t)lx * ly, q = (size_t)y * lx + xo;
+          a.fields[q] = (double)a.rho_wall0;
+          a.fields[n + q] = (double)a.rho_wall1;
+          a.fields[2 * n + q] = 0.0;
+          a.fields[3 * n + q] = 0.0;
+          a.fields[4 * n + q] = (double)solid_temperature(a, xo, y);
+        }
+      } else {
+        // ---- moments (rows kept from two iterations ago)
+        const C ra = sum9(fa0), rb = sum9(fb0);
+        const C jx = ((fa0[1] - fa0[3]) + (fa0[5] - fa0[7]) + (fa0[8] - fa0[6])) +
+                     ((fb0[1] - fb0[3]) + (fb0[5] - fb0[7]) + (fb0[8] - fb0[6]));
+        const C jy = ((fa0[2] - fa0[4]) + (fa0[5] - fa0[7]) + (fa0[6] - fa0[8])) +
+                     ((fb0[2] - fb0[4]) + (fb0[5] - fb0[7]) + (fb0[6] - fb0[8]));
+        C g[9];
+        pull_thermal<St, kMode>(a, src, lm, xw, xwm, xwp, y, g);
+        const C temp = sum9(g);
+
+        // ---- forces from the ring (rows y-2..y+2 are slots k-4..k)
+        const int s0 = tid + 2;
+        int rs[5];
+#pragma unroll
+        for (int d = 0; d < 5; ++d) rs[d] = (k + 2 + d) % R;  // d = dy + 2
+        C fA[2] = {C(0), C(0)}, fB[2] = {C(0), C(0)};
+        // component self forces: attraction (NN, w) and repulsion (25, p)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+          C ax = 0, ay = 0, qx = 0, qy = 0;  // NN sums (w), 25-point sums (p)
+#pragma unroll
+          for (int dy = -2; dy <= 2; ++dy) {
+#pragma unroll
+            for (int dx = 1; dx <= 2; ++dx) {
+              const int c2 = dx * dx + dy * dy;
+              const C diff = s_psi[l][rs[dy + 2]][s0 + dx] - s_psi[l][rs[dy + 2]][s0 - dx];
+              qx += (p_c2<C>(c2) * C(dx)) * diff;
+              if (c2 <= 2) ax += (w_c2<C>(c2) * C(dx)) * diff;
+            }
+          }
+#pragma unroll
+          for (int dx = -2; dx <= 2; ++dx) {
+#pragma unroll
+            for (int dy = 1; dy <= 2; ++dy) {
+              const int c2 = dx * dx + dy * dy;
+              const C diff = s_psi[l][rs[dy + 2]][s0 + dx] - s_psi[l][rs[2 - dy]][s0 + dx];
+              qy += (p_c2<C>(c2) * C(dy)) * diff;
+              if (c2 <= 2) ay += (w_c2<C>(c2) * C(dy)) * diff;
+            }
+          }
+          const C psi_here = s_psi[l][rs[2]][s0];
+          const C ga = l == 0 ? a.ga0 : a.ga1;
+          const C gr = l == 0 ? a.gr0 : a.gr1;
+          C& Fx = l == 0 ? fA[0] : fB[0];
+          C& Fy = l == 0 ? fA[1] : fB[1];
+          Fx = -psi_here * (ga * ax + gr * qx);
+          Fy = -psi_here * (ga * ay + gr * qy);
+        }
+        // cross force (NN, w, psi = rho / rho0): acts on l from the other one
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+          const int m = 1 - l;
+          C sx = 0, sy = 0;
+#pragma unroll
+          for (int dy = -1; dy <= 1; ++dy) {
+            const int c2 = 1 + dy * dy;
+            sx += w_c2<C>(c2) * (s_rho[m][rs[dy + 2]][s0 + 1] - s_rho[m][rs[dy + 2]][s0 - 1]);
+          }
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int c2 = 1 + dx * dx;
+            sy += w_c2<C>(c2) * (s_rho[m][rs[3]][s0 + dx] - s_rho[m][rs[1]][s0 + dx]);
+          }
+          const C rl = l == 0 ? ra : rb;
+          const C pre = -a.g12 * rl * a.inv_rho0 * a.inv_rho0;
+          C& Fx = l == 0 ? fA[0] : fB[0];
+          C& Fy = l == 0 ? fA[1] : fB[1];
+          Fx += pre * sx;
+          Fy += pre * sy;
+        }
+        // buoyancy (Eq. (22))
+        fA[1] += ra * a.alpha_g * temp;
+        fB[1] += rb * a.alpha_g * temp;
+
+        // ---- velocities
+        const C rho = ra + rb;
+        const C inv_rho = C(1) / rho;
+        const C ux = jx * inv_rho, uy = jy * inv_rho;
+        const C Fx = fA[0] + fB[0], Fy = fA[1] + fB[1];
+        const C hx = ux + C(0.5) * Fx * inv_rho;
+        const C hy = uy + C(0.5) * Fy * inv_rho;
+
+        if constexpr ((kMode & kModeStore) != 0) {
+          const C tA = a.tau / ra, tB = a.tau / rb;
+          const C uax = ux + fA[0] * tA, uay = uy + fA[1] * tA;
+          const C ubx = ux + fB[0] * tB, uby = uy + fB[1] * tB;
+          const C ua2 = uax * uax + uay * uay;
+          const C ub2 = ubx * ubx + uby * uby;
+          const C uh2 = hx * hx + hy * hy;
+          // BGK relaxation written as f^eq + (1 - 1/tau)(f - f^eq): exactly
+          // f^eq at tau = 1. The rest population's equilibrium is the zeroth
+          // moment minus the other eight, so the stored populations sum to
+          // rho (and T) up to unbiased rounding: the weights rounded to the
+          // storage type do not sum to 1 and would otherwise create mass at
+          // every collision.
+          const C ka = C(1) - a.inv_tau, kg = C(1) - a.inv_tau_g;
+          C sa = 0, sb = 0, sg = 0;
+#define TLB_COLLIDE(I)                                                                     \
+  {                                                                                        \
+    constexpr int cx = Dir<I>::cx, cy = Dir<I>::cy;                                       \
+    constexpr C w = w_dir<C>(I);                                                           \
+    const C cua = C(cx) * uax + C(cy) * uay;                                               \
+    const C cub = C(cx) * ubx + C(cy) * uby;                                               \
+    const C cuh = C(cx) * hx + C(cy) * hy;                                                 \
+    const C ea = w * ra * (C(1) + C(3) * cua + C(4.5) * cua * cua - C(1.5) * ua2);         \
+    const C eb = w * rb * (C(1) + C(3) * cub + C(4.5) * cub * cub - C(1.5) * ub2);         \
+    const C eg = w * temp * (C(1) + C(3) * cuh + C(4.5) * cuh * cuh - C(1.5) * uh2);       \
+    sa += ea;                                                                              \
+    sb += eb;                                                                              \
+    sg += eg;                                                                              \
+    St::store(dst + I * ps + off, ea + ka * (fa0[I] - ea));                                \
+    St::store(dst + (I + 9) * ps + off, eb + ka * (fb0[I] - eb));                          \
+    St::store(dst + (I + 18) * ps + off, eg + kg * (g[I] - eg));                           \
+  }
+          TLB_COLLIDE(1) TLB_COLLIDE(2) TLB_COLLIDE(3) TLB_COLLIDE(4)
+          TLB_COLLIDE(5) TLB_COLLIDE(6) TLB_COLLIDE(7) TLB_COLLIDE(8)
+#undef TLB_COLLIDE
+          {
+            const C ea = ra - sa, eb = rb - sb, eg = temp - sg;
+            St::store(dst + off, ea + ka * (fa0[0] - ea));
+            St::store(dst + 9 * ps + off, eb + ka * (fb0[0] - eb));
+            St::store(dst + 18 * ps + off, eg + kg * (g[0] - eg));
+          }
+        }
+        if constexpr ((kMode & kModeFields) != 0) {
+          const size_t n = (size_t)lx * ly, q = (size_t)y * lx + xo;
+          a.fields[q] = (double)ra;
+          a.fields[n + q] = (double)rb;
+          a.fields[2 * n + q] = (double)hx;
+          a.fields[3 * n + q] = (double)hy;
+          a.fields[4 * n + q] = (double)temp;
+        }
+        if constexpr ((kMode & kModeObserve) != 0) {
+          const C tn = neighbour_temperature<St, kMode>(a, src, xw, xwm, xwp, y + 1, temp);
+          const C ts = neighbour_temperature<St, kMode>(a, src, xw, xwm, xwp, y - 1, temp);
+          acc[0] += (double)ra;
+          acc[1] += (double)rb;
+          acc[2] += (double)temp;
+          acc[3] += (double)hy * (double)temp;
+          acc[4] += 0.5 * ((double)tn - (double)ts);
+          acc[5] += (double)hx * (double)hx + (double)hy * (double)hy;
+          if (y == ly - 1) acc[6] += (double)temp - (double)a.t_top;
+        }
+      }
+    }
+    // rotate the kept rows: row r-1 -> slot 0, row r -> slot 1
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      fa0[i] = fa1[i];
+      fb0[i] = fb1[i];
+      fa1[i] = fa2[i];
+      fb1[i] = fb2[i];
+    }
+  }
+
+  if constexpr ((kMode & kModeObserve) != 0) {
+    // block reduction of the 7 sums in a fixed order (deterministic)
+    __shared__ double s_acc[BX / 64][8];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      double v = acc[j];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+      if ((tid & 63) == 0) s_acc[tid >> 6][j] = v;
+    }
+    __syncthreads();
+    if (tid < 7) {
+      double v = 0;
+      for (int w = 0; w < BX / 64; ++w) v += s_acc[w][tid];
+      a.partials[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 8 + tid] = v;
+    }
+  }
+}
+
+// Final observable reduction: one block sums the per-block partials in a
+// fixed order and forms the observables of the header's definitions.
+struct ObsArgs {
+  const double* partials;
+  int nblocks;
+  double n_fluid, n_top;
+  double kappa, dt_nominal, ly;
+  double* out;   // [6] mass_a, mass_b, sum_t, nu, nu_top, ke
+};
+
+__global__ __launch_bounds__(256) void lb_reduce_observables(ObsArgs a) {
+  __shared__ double s[7][256];
+  const int tid = threadIdx.x;
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = tid; b < a.nblocks; b += 256)
+    for (int j = 0; j < 7; ++j) v[j] += a.partials[(size_t)b * 8 + j];
+  for (int j = 0; j < 7; ++j) s[j][tid] = v[j];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h)
+      for (int j = 0; j < 7; ++j) s[j][tid] += s[j][tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double inv = a.n_fluid > 0 ? 1.0 / a.n_fluid : 0.0;
+    a.out[0] = s[0][0];
+    a.out[1] = s[1][0];
+    a.out[2] = s[2][0];
+    a.out[3] = (s[3][0] * inv - a.kappa * s[4][0] * inv) / (a.kappa * a.dt_nominal / a.ly);
+    a.out[4] = a.n_top > 0 ? 2.0 * a.ly / a.dt_nominal * (s[6][0] / a.n_top) : 0.0;
+    a.out[5] = s[5][0] * inv;
+  }
+}
+
+// Equilibrium start state f(0) = f^eq(rho_l, u0), g(0) = g^eq(T, u0) written
+// at each node (the init variant of the step kernel reads it in place).
+template <class St>
+__global__ __launch_bounds__(256) void lb_init_equilibrium(
+    typename St::T* __restrict__ buf, const double* __restrict__ rho_a,
+    const double* __restrict__ rho_b, const double* __restrict__ temp,
+    const double* __restrict__ ux0, const double* __restrict__ uy0,
+    const uint8_t* __restrict__ solid, int lx, int ly, int pitch, long long pop_stride) {
+  using C = typename St::C;
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= lx) return;
+  const size_t q = (size_t)y * lx + x;
+  const int off = y * pitch + x;
+  const bool is_solid = solid != nullptr && solid[q] != 0;
+  const C ux = ux0 ? (C)ux0[q] : C(0), uy = uy0 ? (C)uy0[q] : C(0);
+  const C u2 = ux * ux + uy * uy;
+  const C dens[3] = {(C)rho_a[q], (C)rho_b[q], (C)temp[q]};
+  C sum[3] = {C(0), C(0), C(0)};
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const C cu = C(dir_cx(i)) * ux + C(dir_cy(i)) * uy;
+    const C shape = w_dir<C>(i) * (C(1) + C(3) * cu + C(4.5) * cu * cu - C(1.5) * u2);
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const C v = dens[s] * shape;
+      sum[s] += v;
+      St::store(buf + (long long)(i + 9 * s) * pop_stride + off, is_solid ? C(0) : v);
+    }
+  }
+  // rest population: zeroth moment minus the other eight (exact mass)
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+    St::store(buf + (long long)(9 * s) * pop_stride + off, is_solid ? C(0) : dens[s] - sum[s]);
+}
+
+// Copy populations out as doubles [27][ly][lx] (drops the row padding).
+template <class St>
+__global__ __launch_bounds__(256) void lb_export_populations(
+    const typename St::T* __restrict__ buf, double* __restrict__ out, int lx, int ly, int pitch,
+    long long pop_stride) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  const int p = blockIdx.z;
+  if (x >= lx) return;
+  out[((size_t)p * ly + y) * lx + x] = (double)St::load(buf + p * pop_stride + y * pitch + x);
+}
+
+}  // namespace tlbk

@@ -1,0 +1,408 @@
+// Host side of the C ABI declared in include/tlb.h: parameter checks, device
+// memory, launch geometry, and the step / observable / export sequences.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/tlb.h"
+#include "lb_kernels.hpp"
+
+namespace {
+
+thread_local char g_init_error[512];
+
+struct Launch {
+  int bx;              // columns (threads) per block
+  int rows;            // rows per block chunk
+  dim3 grid;
+};
+
+}  // namespace
+
+struct tlb_handle {
+  tlb_params p{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int pitch = 0;
+  long long pop_stride = 0;
+  size_t elem = 0;                 // bytes per stored population value
+  void* buf[2] = {nullptr, nullptr};
+  int cur = 0;                     // buf[cur] = f*(t); buf[1-cur] = f*(t-1) or f(0)
+  int64_t t = 0;
+  bool has_solid = false;
+  uint16_t* link = nullptr;
+  uint8_t* solid = nullptr;
+  void* t_bottom = nullptr;        // C-typed copy of the bottom temperature
+  double* partials = nullptr;
+  double* obs = nullptr;           // [6]
+  double* fields = nullptr;        // [5][ly][lx], allocated on first use
+  double* export_buf = nullptr;    // [27][ly][lx], allocated on first use
+  double n_fluid = 0, n_top = 0;
+  Launch launch{};
+  char err[512] = {0};
+};
+
+namespace {
+
+int fail(tlb_handle* h, int code, const char* fmt, ...) {
+  char* dst = h ? h->err : g_init_error;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(dst, 512, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define TLB_HIP(h, expr)                                                           \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail((h), TLB_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+bool is_fp64(const tlb_handle* h) { return h->p.precision == TLB_FP64; }
+
+Launch choose_launch(int lx, int ly) {
+  Launch l;
+  l.bx = lx >= 1024 ? 256 : 64;
+  int rows = 64;
+  if (const char* env = std::getenv("TLB_ROWS_PER_BLOCK")) {
+    int v = std::atoi(env);
+    if (v >= 1 && v <= 4096) rows = v;
+  }
+  l.rows = rows < ly ? rows : ly;
+  l.grid = dim3((lx + l.bx - 1) / l.bx, (ly + l.rows - 1) / l.rows, 1);
+  return l;
+}
+
+template <typename C>
+tlbk::StepArgs<C> make_args(const tlb_handle* h, const void* src, void* dst) {
+  tlbk::StepArgs<C> a{};
+  const tlb_params& p = h->p;
+  a.src = src;
+  a.dst = dst;
+  a.link = h->link;
+  a.solid = h->solid;
+  a.t_bottom = static_cast<const C*>(h->t_bottom);
+  a.partials = h->partials;
+  a.fields = h->fields;
+  a.lx = p.lx;
+  a.ly = p.ly;
+  a.pitch = h->pitch;
+  a.rows_per_block = h->launch.rows;
+  a.pop_stride = h->pop_stride;
+  a.inv_tau = C(1.0 / p.tau);
+  a.inv_tau_g = C(1.0 / p.tau_g);
+  a.tau = C(p.tau);
+  a.rho0 = C(p.rho0);
+  a.inv_rho0 = C(1.0 / p.rho0);
+  a.g12 = C(p.g12);
+  a.ga0 = C(p.g_a[0]);
+  a.ga1 = C(p.g_a[1]);
+  a.gr0 = C(p.g_r[0]);
+  a.gr1 = C(p.g_r[1]);
+  a.alpha_g = C(p.alpha_g);
+  a.t_top = C(p.t_top);
+  a.rho_wall0 = C(p.rho_wall[0]);
+  a.rho_wall1 = C(p.rho_wall[1]);
+  return a;
+}
+
+template <class St, int BX, unsigned kMode>
+void launch_step(const tlb_handle* h, const tlbk::StepArgs<typename St::C>& a) {
+  hipLaunchKernelGGL((tlbk::lb_step_kernel<St, BX, kMode>), h->launch.grid, dim3(BX), 0,
+                     h->stream, a);
+}
+
+// Dispatch on block width and on the presence of solid cells.
+template <class St, unsigned kMode>
+void launch_mode(const tlb_handle* h, const void* src, void* dst) {
+  auto a = make_args<typename St::C>(h, src, dst);
+  if (h->has_solid) {
+    if (h->launch.bx == 256) launch_step<St, 256, kMode | tlbk::kModeSolid>(h, a);
+    else launch_step<St, 64, kMode | tlbk::kModeSolid>(h, a);
+  } else {
+    if (h->launch.bx == 256) launch_step<St, 256, kMode>(h, a);
+    else launch_step<St, 64, kMode>(h, a);
+  }
+}
+
+template <unsigned kMode>
+void launch_any(const tlb_handle* h, const void* src, void* dst) {
+  if (is_fp64(h)) launch_mode<tlbk::Store<double>, kMode>(h, src, dst);
+  else launch_mode<tlbk::Store<float>, kMode>(h, src, dst);
+}
+
+// Re-run the step that produced f*(t) without storing, to evaluate the
+// moments, forces and u^H of time t (observables and/or fields).
+template <unsigned kMode>
+int evaluate_time_level(tlb_handle* h) {
+  const void* src = h->buf[1 - h->cur];
+  if (h->t == 0) launch_any<kMode | tlbk::kModeInit>(h, src, nullptr);
+  else launch_any<kMode>(h, src, nullptr);
+  TLB_HIP(h, hipGetLastError());
+  return TLB_OK;
+}
+
+bool finite_positive(double v) { return std::isfinite(v) && v > 0; }
+
+}  // namespace
+
+extern "C" {
+
+int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const double* rho_b,
+             const double* temp, const double* ux0, const double* uy0, const uint8_t* solid,
+             const double* t_bottom, void* hip_stream) {
+  g_init_error[0] = 0;
+  if (!out) return fail(nullptr, TLB_EINVAL, "tlb_init: out is NULL");
+  *out = nullptr;
+  if (!p || !rho_a || !rho_b || !temp || !t_bottom)
+    return fail(nullptr, TLB_EINVAL, "tlb_init: NULL params or field array");
+  if (p->lx < 1 || p->ly < 1 || (long long)p->lx * p->ly > (1LL << 30))
+    return fail(nullptr, TLB_EINVAL, "tlb_init: bad lattice size %d x %d", p->lx, p->ly);
+  if (p->precision != TLB_FP64 && p->precision != TLB_FP32)
+    return fail(nullptr, TLB_EINVAL, "tlb_init: unknown precision %d", p->precision);
+  if (!(p->tau > 0.5) || !(p->tau_g > 0.5) || !finite_positive(p->rho0) || !(p->dt_nominal != 0) ||
+      !std::isfinite(p->dt_nominal))
+    return fail(nullptr, TLB_EINVAL, "tlb_init: need tau > 1/2, tau_g > 1/2, rho0 > 0, dt_nominal != 0");
+
+  tlb_handle* h = new (std::nothrow) tlb_handle();
+  if (!h) return fail(nullptr, TLB_ENOMEM, "tlb_init: host allocation failed");
+  h->p = *p;
+  const int lx = p->lx, ly = p->ly;
+  const size_t n = (size_t)lx * ly;
+
+  // host-side pre-processing: solid flags and link masks
+  std::vector<uint8_t> sol(n, 0);
+  if (solid) {
+    for (size_t q = 0; q < n; ++q) {
+      if (solid[q] > 2) {
+        delete h;
+        return fail(nullptr, TLB_EINVAL, "tlb_init: solid flag %d at %zu (0, 1 or 2 expected)",
+                    (int)solid[q], q);
+      }
+      sol[q] = solid[q];
+      h->has_solid |= solid[q] != 0;
+    }
+  }
+  std::vector<uint16_t> link;
+  if (h->has_solid) {
+    link.assign(n, 0);
+    for (int y = 0; y < ly; ++y)
+      for (int x = 0; x < lx; ++x) {
+        uint16_t m = sol[(size_t)y * lx + x] ? 1 : 0;
+        for (int i = 1; i < 9; ++i) {
+          const int sx = ((x - tlbk::dir_cx(i)) % lx + lx) % lx;
+          const int sy = y - tlbk::dir_cy(i);
+          const bool s = sy < 0 || sy >= ly || sol[(size_t)sy * lx + sx] != 0;
+          if (s) m |= (uint16_t)(1u << i);
+        }
+        link[(size_t)y * lx + x] = m;
+      }
+  }
+  for (size_t q = 0; q < n; ++q) h->n_fluid += sol[q] == 0;
+  for (int x = 0; x < lx; ++x) h->n_top += sol[(size_t)(ly - 1) * lx + x] == 0;
+
+  h->pitch = (lx + 63) / 64 * 64;
+  h->pop_stride = (long long)h->pitch * ly;
+  h->elem = is_fp64(h) ? sizeof(double) : sizeof(float);
+  h->launch = choose_launch(lx, ly);
+
+  int rc = TLB_OK;
+  auto cleanup_fail = [&](int code) {
+    tlb_destroy(h);
+    return code;
+  };
+  if (hip_stream) {
+    h->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    hipError_t e = hipStreamCreate(&h->stream);
+    if (e != hipSuccess) {
+      fail(nullptr, TLB_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+      delete h;
+      return TLB_EDEVICE;
+    }
+    h->own_stream = true;
+  }
+
+#define INIT_HIP(expr)                                                                  \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      fail(nullptr, e_ == hipErrorOutOfMemory ? TLB_ENOMEM : TLB_EDEVICE, "%s: %s", #expr, \
+           hipGetErrorString(e_));                                                      \
+      return cleanup_fail(e_ == hipErrorOutOfMemory ? TLB_ENOMEM : TLB_EDEVICE);       \
+    }                                                                                   \
+  } while (0)
+
+  const size_t buf_bytes = (size_t)27 * h->pop_stride * h->elem;
+  INIT_HIP(hipMalloc(&h->buf[0], buf_bytes));
+  INIT_HIP(hipMalloc(&h->buf[1], buf_bytes));
+  INIT_HIP(hipMemsetAsync(h->buf[0], 0, buf_bytes, h->stream));
+  INIT_HIP(hipMemsetAsync(h->buf[1], 0, buf_bytes, h->stream));
+  const size_t nblocks = (size_t)h->launch.grid.x * h->launch.grid.y;
+  INIT_HIP(hipMalloc(&h->partials, nblocks * 8 * sizeof(double)));
+  INIT_HIP(hipMalloc(&h->obs, 8 * sizeof(double)));
+  INIT_HIP(hipMalloc(&h->t_bottom, lx * h->elem));
+  INIT_HIP(hipMalloc(&h->solid, n));
+  INIT_HIP(hipMemcpyAsync(h->solid, sol.data(), n, hipMemcpyHostToDevice, h->stream));
+  if (h->has_solid) {
+    INIT_HIP(hipMalloc(&h->link, n * sizeof(uint16_t)));
+    INIT_HIP(hipMemcpyAsync(h->link, link.data(), n * sizeof(uint16_t), hipMemcpyHostToDevice,
+                            h->stream));
+  }
+  rc = tlb_set_bottom_temperature(h, t_bottom);
+  if (rc != TLB_OK) {
+    snprintf(g_init_error, sizeof g_init_error, "%s", h->err);
+    return cleanup_fail(rc);
+  }
+
+  // initial fields -> f(0) in buf[1] -> f*(0) in buf[0]
+  double* d_fields = nullptr;
+  const int nf = (ux0 && uy0) ? 5 : 3;
+  INIT_HIP(hipMalloc(&d_fields, nf * n * sizeof(double)));
+  const double* srcs[5] = {rho_a, rho_b, temp, ux0, uy0};
+  for (int k = 0; k < nf; ++k)
+    INIT_HIP(hipMemcpyAsync(d_fields + k * n, srcs[k], n * sizeof(double), hipMemcpyHostToDevice,
+                            h->stream));
+  dim3 g2((lx + 255) / 256, ly, 1);
+  const double* dux = nf == 5 ? d_fields + 3 * n : nullptr;
+  const double* duy = nf == 5 ? d_fields + 4 * n : nullptr;
+  if (is_fp64(h))
+    hipLaunchKernelGGL(tlbk::lb_init_equilibrium<tlbk::Store<double>>, g2, dim3(256), 0, h->stream,
+                       static_cast<double*>(h->buf[1]), d_fields, d_fields + n, d_fields + 2 * n,
+                       dux, duy, h->solid, lx, ly, h->pitch, h->pop_stride);
+  else
+    hipLaunchKernelGGL(tlbk::lb_init_equilibrium<tlbk::Store<float>>, g2, dim3(256), 0, h->stream,
+                       static_cast<float*>(h->buf[1]), d_fields, d_fields + n, d_fields + 2 * n,
+                       dux, duy, h->solid, lx, ly, h->pitch, h->pop_stride);
+  INIT_HIP(hipGetLastError());
+  launch_any<tlbk::kModeInit | tlbk::kModeStore>(h, h->buf[1], h->buf[0]);
+  INIT_HIP(hipGetLastError());
+  INIT_HIP(hipStreamSynchronize(h->stream));
+  INIT_HIP(hipFree(d_fields));
+#undef INIT_HIP
+  h->cur = 0;
+  h->t = 0;
+  *out = h;
+  return TLB_OK;
+}
+
+int tlb_step(tlb_handle* h, int64_t nsteps) {
+  if (!h) return fail(nullptr, TLB_EINVAL, "tlb_step: NULL handle");
+  if (nsteps < 0) return fail(h, TLB_EINVAL, "tlb_step: nsteps < 0");
+  for (int64_t s = 0; s < nsteps; ++s) {
+    launch_any<tlbk::kModeStore>(h, h->buf[h->cur], h->buf[1 - h->cur]);
+    h->cur = 1 - h->cur;
+    h->t += 1;
+  }
+  TLB_HIP(h, hipGetLastError());
+  return TLB_OK;
+}
+
+int tlb_observables(tlb_handle* h, tlb_obs* out) {
+  if (!h || !out) return fail(h, TLB_EINVAL, "tlb_observables: NULL argument");
+  int rc = evaluate_time_level<tlbk::kModeObserve>(h);
+  if (rc != TLB_OK) return rc;
+  tlbk::ObsArgs oa{};
+  oa.partials = h->partials;
+  oa.nblocks = (int)(h->launch.grid.x * h->launch.grid.y);
+  oa.n_fluid = h->n_fluid;
+  oa.n_top = h->n_top;
+  oa.kappa = (h->p.tau_g - 0.5) / 3.0;
+  oa.dt_nominal = h->p.dt_nominal;
+  oa.ly = h->p.ly;
+  oa.out = h->obs;
+  hipLaunchKernelGGL(tlbk::lb_reduce_observables, dim3(1), dim3(256), 0, h->stream, oa);
+  TLB_HIP(h, hipGetLastError());
+  double v[6];
+  TLB_HIP(h, hipMemcpyAsync(v, h->obs, sizeof v, hipMemcpyDeviceToHost, h->stream));
+  TLB_HIP(h, hipStreamSynchronize(h->stream));
+  out->step = h->t;
+  out->mass_a = v[0];
+  out->mass_b = v[1];
+  out->sum_t = v[2];
+  out->nu = v[3];
+  out->nu_top = v[4];
+  out->ke = v[5];
+  if (!std::isfinite(v[0]) || !std::isfinite(v[1]))
+    return fail(h, TLB_ENUMERIC, "tlb_observables: non-finite mass at step %lld", (long long)h->t);
+  return TLB_OK;
+}
+
+int tlb_get_fields(tlb_handle* h, double* rho_a, double* rho_b, double* ux, double* uy,
+                   double* temp) {
+  if (!h) return fail(nullptr, TLB_EINVAL, "tlb_get_fields: NULL handle");
+  const size_t n = (size_t)h->p.lx * h->p.ly;
+  if (!h->fields) TLB_HIP(h, hipMalloc(&h->fields, 5 * n * sizeof(double)));
+  int rc = evaluate_time_level<tlbk::kModeFields>(h);
+  if (rc != TLB_OK) return rc;
+  double* outs[5] = {rho_a, rho_b, ux, uy, temp};
+  for (int k = 0; k < 5; ++k)
+    if (outs[k])
+      TLB_HIP(h, hipMemcpyAsync(outs[k], h->fields + k * n, n * sizeof(double),
+                                hipMemcpyDeviceToHost, h->stream));
+  TLB_HIP(h, hipStreamSynchronize(h->stream));
+  return TLB_OK;
+}
+
+int tlb_get_populations(tlb_handle* h, double* out) {
+  if (!h || !out) return fail(h, TLB_EINVAL, "tlb_get_populations: NULL argument");
+  const int lx = h->p.lx, ly = h->p.ly;
+  const size_t total = (size_t)27 * lx * ly;
+  if (!h->export_buf) TLB_HIP(h, hipMalloc(&h->export_buf, total * sizeof(double)));
+  dim3 g((lx + 255) / 256, ly, 27);
+  if (is_fp64(h))
+    hipLaunchKernelGGL(tlbk::lb_export_populations<tlbk::Store<double>>, g, dim3(256), 0, h->stream,
+                       static_cast<const double*>(h->buf[h->cur]), h->export_buf, lx, ly, h->pitch,
+                       h->pop_stride);
+  else
+    hipLaunchKernelGGL(tlbk::lb_export_populations<tlbk::Store<float>>, g, dim3(256), 0, h->stream,
+                       static_cast<const float*>(h->buf[h->cur]), h->export_buf, lx, ly, h->pitch,
+                       h->pop_stride);
+  TLB_HIP(h, hipGetLastError());
+  TLB_HIP(h, hipMemcpyAsync(out, h->export_buf, total * sizeof(double), hipMemcpyDeviceToHost,
+                            h->stream));
+  TLB_HIP(h, hipStreamSynchronize(h->stream));
+  return TLB_OK;
+}
+
+int tlb_set_bottom_temperature(tlb_handle* h, const double* t_bottom) {
+  if (!h || !t_bottom) return fail(h, TLB_EINVAL, "tlb_set_bottom_temperature: NULL argument");
+  const int lx = h->p.lx;
+  if (is_fp64(h)) {
+    TLB_HIP(h, hipMemcpyAsync(h->t_bottom, t_bottom, lx * sizeof(double), hipMemcpyHostToDevice,
+                              h->stream));
+    TLB_HIP(h, hipStreamSynchronize(h->stream));
+  } else {
+    std::vector<float> tb(t_bottom, t_bottom + lx);
+    TLB_HIP(h, hipMemcpyAsync(h->t_bottom, tb.data(), lx * sizeof(float), hipMemcpyHostToDevice,
+                              h->stream));
+    TLB_HIP(h, hipStreamSynchronize(h->stream));
+  }
+  return TLB_OK;
+}
+
+int64_t tlb_time(const tlb_handle* h) { return h ? h->t : -1; }
+
+int tlb_destroy(tlb_handle* h) {
+  if (!h) return TLB_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  void* ptrs[] = {h->buf[0], h->buf[1], h->link,   h->solid,      h->t_bottom,
+                  h->partials, h->obs,  h->fields, h->export_buf};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return TLB_OK;
+}
+
+const char* tlb_last_error(const tlb_handle* h) { return h ? h->err : g_init_error; }
+
+}  // extern "C"

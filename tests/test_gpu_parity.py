@@ -1,0 +1,224 @@
+"""GPU (HIP, gfx950) versus the FP64 oracle, element by element.
+
+Tolerances: FP64 storage <= 1e-12 relative after 200 steps; FP32 storage
+<= 1e-5 relative after 1000 steps for densities, temperature and populations
+(small-case geometry). The relative error of a field is max|gpu - oracle| /
+max|oracle|; velocities are normalised by the largest oracle velocity
+component, and for FP32 they get 3e-5: u is a difference of populations of
+size ~0.1-0.6 stored with 24-bit mantissas, so its absolute error sits near
+1e-7 at every step (measured flat from step 100 to 2000), while max|u| decays
+to ~7e-3 as the droplets settle.
+
+At full benchmark sizes the oracle cannot run many steps, so there the GPU's
+own post-collision state is handed to the oracle, both advance one step, and
+every element is compared; properties that hold at any size (per-component
+mass, bitwise x-translation equivariance) cover the long runs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle.oracle import ModelParams, Oracle
+from paper_2109_12565_amd import Simulation
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("rho_a", "rho_b", "temp")
+
+
+def rel(a, b):
+    d = np.abs(a - b).max()
+    s = np.abs(b).max()
+    return d / s if s > 0 else d
+
+
+def field_errors(got, ref):
+    errs = {k: rel(got[k], ref[k]) for k in FIELDS}
+    umax = max(np.abs(ref["ux"]).max(), np.abs(ref["uy"]).max(), 1e-300)
+    for k in ("ux", "uy"):
+        errs[k] = np.abs(got[k] - ref[k]).max() / umax
+    return errs
+
+
+def pop_errors(got, ref):
+    return {"f_a": rel(got[0:9], ref[0:9]), "f_b": rel(got[9:18], ref[9:18]),
+            "g": rel(got[18:27], ref[18:27])}
+
+
+def run_pair(case, steps, precision, **kw):
+    p = dict(case["params"])
+    sim = Simulation(p, case["rho_a"], case["rho_b"], case["temp"], solid=case.get("solid"),
+                     t_bottom=case.get("t_bottom"), precision=precision, **kw)
+    ora = Oracle(ModelParams(**p), case["rho_a"], case["rho_b"], case["temp"],
+                 solid=case.get("solid"), t_bottom=case.get("t_bottom"))
+    sim.step(steps)
+    ora.step(steps)
+    return sim, ora
+
+
+def posts_case(lx=96, ly=48, seed=7):
+    rng = np.random.default_rng(seed)
+    solid = workloads.bottom_posts(np.random.Generator(np.random.PCG64(seed)), lx, ly)
+    solid[-3:, 10:18] = 2
+    inside = workloads.paint_discs(lx, ly, [(30.5, 24.0), (70.0, 28.5)], 9.0)
+    return dict(
+        params=dict(workloads.BASE_PARAMS, alpha_g=1e-3),
+        rho_a=np.where(inside, 1.36, 0.08) + rng.uniform(-0.01, 0.01, (ly, lx)),
+        rho_b=np.where(inside, 0.08, 1.36) + rng.uniform(-0.01, 0.01, (ly, lx)),
+        temp=workloads.conduction_profile(lx, ly) + rng.uniform(-1e-3, 1e-3, (ly, lx)),
+        solid=solid, t_bottom=workloads.bottom_temperature_noise(lx, seed=5))
+
+
+# ------------------------------------------------------------ FP64 parity
+
+
+def test_fp64_small_200_steps_fields_populations_observables():
+    w = workloads.small()
+    sim, ora = run_pair(w, 200, "fp64")
+    errs = field_errors(sim.fields(), ora.fields())
+    print("fp64 small fields", errs)
+    assert max(errs.values()) <= 1e-12, errs
+    perr = pop_errors(sim.populations(), ora.post_collision())
+    print("fp64 small populations", perr)
+    assert max(perr.values()) <= 1e-12, perr
+    og, oo = sim.observables(), ora.observables()
+    assert og["step"] == 200
+    for k in ("mass_a", "mass_b", "sum_t", "ke", "nu", "nu_top"):
+        assert og[k] == pytest.approx(oo[k], rel=1e-11, abs=1e-14), (k, og[k], oo[k])
+
+
+def test_fp64_posts_ragged_lattice_and_varying_wall_temperature():
+    """96 x 48 (row pitch padded to 128: a ragged last strip), bottom posts,
+    a rough patch flagged at the top temperature, per-column T_b."""
+    c = posts_case()
+    sim, ora = run_pair(c, 150, "fp64")
+    errs = field_errors(sim.fields(), ora.fields())
+    print("fp64 posts fields", errs)
+    assert max(errs.values()) <= 1e-12, errs
+    perr = pop_errors(sim.populations(), ora.post_collision())
+    assert max(perr.values()) <= 1e-12, perr
+    og, oo = sim.observables(), ora.observables()
+    for k in ("mass_a", "mass_b", "sum_t", "ke", "nu", "nu_top"):
+        assert og[k] == pytest.approx(oo[k], rel=1e-11, abs=1e-14), (k, og[k], oo[k])
+
+
+def test_fp64_time_zero_and_initial_velocity():
+    """t = 0 (the init variant) and a start with a velocity field."""
+    w = workloads.small()
+    rng = np.random.default_rng(2)
+    ux = rng.uniform(-0.02, 0.02, w["rho_a"].shape)
+    uy = rng.uniform(-0.02, 0.02, w["rho_a"].shape)
+    p = w["params"]
+    sim = Simulation(p, w["rho_a"], w["rho_b"], w["temp"], ux0=ux, uy0=uy, precision="fp64")
+    ora = Oracle(ModelParams(**p), w["rho_a"], w["rho_b"], w["temp"], ux0=ux, uy0=uy)
+    errs = field_errors(sim.fields(), ora.fields())
+    assert max(errs.values()) <= 1e-13, errs
+    perr = pop_errors(sim.populations(), ora.post_collision())
+    assert max(perr.values()) <= 1e-13, perr
+    sim.step(37)
+    ora.step(37)
+    errs = field_errors(sim.fields(), ora.fields())
+    assert max(errs.values()) <= 1e-12, errs
+
+
+@pytest.mark.parametrize("lx,ly", [(5, 3), (64, 1), (100, 45), (130, 70)])
+def test_fp64_edge_shapes(lx, ly):
+    """Tiny lattices (x wrap inside one strip, a single row between the
+    walls), and shapes that leave ragged strips and row chunks."""
+    rng = np.random.default_rng(lx * 1000 + ly)
+    case = dict(params=dict(workloads.BASE_PARAMS, alpha_g=2e-3),
+                rho_a=rng.uniform(0.1, 1.3, (ly, lx)), rho_b=rng.uniform(0.1, 1.3, (ly, lx)),
+                temp=rng.uniform(0, 1, (ly, lx)), t_bottom=rng.uniform(0.9, 1.1, lx))
+    sim, ora = run_pair(case, 25, "fp64")
+    errs = field_errors(sim.fields(), ora.fields())
+    assert max(errs.values()) <= 1e-12, errs
+    perr = pop_errors(sim.populations(), ora.post_collision())
+    assert max(perr.values()) <= 1e-12, perr
+
+
+def test_zero_steps_is_identity():
+    w = workloads.small()
+    sim = Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], precision="fp64")
+    before = sim.populations()
+    sim.step(0)
+    assert sim.t == 0
+    assert np.array_equal(before, sim.populations())
+
+
+# ------------------------------------------------------------ FP32 parity
+
+
+def test_fp32_small_1000_steps():
+    w = workloads.small()
+    sim, ora = run_pair(w, 1000, "fp32")
+    errs = field_errors(sim.fields(), ora.fields())
+    print("fp32 small 1000 fields", errs)
+    assert max(errs[k] for k in FIELDS) <= 1e-5, errs
+    assert max(errs["ux"], errs["uy"]) <= 3e-5, errs
+    perr = pop_errors(sim.populations(), ora.post_collision())
+    print("fp32 small 1000 populations", perr)
+    assert max(perr.values()) <= 1e-5, perr
+    og, oo = sim.observables(), ora.observables()
+    for k in ("mass_a", "mass_b", "sum_t"):
+        assert og[k] == pytest.approx(oo[k], rel=1e-5), (k, og[k], oo[k])
+
+
+def test_fp32_posts_300_steps():
+    c = posts_case(lx=128, ly=64, seed=11)
+    sim, ora = run_pair(c, 300, "fp32")
+    errs = field_errors(sim.fields(), ora.fields())
+    print("fp32 posts fields", errs)
+    assert max(errs[k] for k in FIELDS) <= 1e-5, errs
+    assert max(errs["ux"], errs["uy"]) <= 3e-5, errs
+
+
+@pytest.mark.parametrize("name", ["mid", "large"])
+def test_fp32_full_size_one_step_from_gpu_state(name):
+    """Benchmark lattices in the benchmark's launch configuration: after 20
+    GPU steps, the oracle streams the GPU's post-collision state and both
+    take one more step; every population and field is compared."""
+    w = workloads.CONFIGS[name]()
+    p = w["params"]
+    sim = Simulation(p, w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+                     t_bottom=w["t_bottom"], precision="fp32")
+    sim.step(20)
+    state = sim.populations()
+    sim.step(1)
+    got_pop = sim.populations()
+    got_fields = sim.fields()
+    ora = Oracle(ModelParams(**p), w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+                 t_bottom=w["t_bottom"])
+    ora.load_post_collision(state, 21)
+    errs = field_errors(got_fields, ora.fields())
+    print(name, "one-step fields", errs)
+    assert max(errs.values()) <= 1e-5, errs
+    ref = ora.post_collision()
+    perr = pop_errors(got_pop, ref)
+    print(name, "one-step populations", perr)
+    assert max(perr.values()) <= 1e-5, perr
+
+
+@pytest.mark.parametrize("name", ["mid"])
+def test_fp32_full_size_mass_and_translation_over_1000_steps(name):
+    """Per-component mass is conserved over 1000 FP32 steps (the FP64
+    reduction sees only FP32 storage rounding), and shifting the start by 37
+    columns shifts the result bitwise (no strip- or chunk-edge effects)."""
+    w = workloads.CONFIGS[name]()
+    p = w["params"]
+    a = Simulation(p, w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"], t_bottom=w["t_bottom"],
+                   precision="fp32")
+    m0 = a.observables()
+    a.step(1000)
+    m1 = a.observables()
+    for k in ("mass_a", "mass_b"):
+        assert abs(m1[k] - m0[k]) / m0[k] < 1e-5, (k, m0[k], m1[k])
+    sh = lambda z: np.roll(z, 37, axis=1)
+    b = Simulation(p, sh(w["rho_a"]), sh(w["rho_b"]), sh(w["temp"]),
+                   solid=None if w["solid"] is None else sh(w["solid"]),
+                   t_bottom=sh(w["t_bottom"][None, :])[0], precision="fp32")
+    b.step(1000)
+    fa, fb = a.fields(), b.fields()
+    for k in fa:
+        assert np.array_equal(sh(fa[k]), fb[k]), k
