@@ -17,22 +17,28 @@
 //            f^eq(rho_l, u_l) (Eq. (3)) and g^eq(T, u^H) (Eq. (18));
 //   store    27 aligned, coalesced stores into the other buffer.
 //
-// The strip marches upward one row per iteration. Iteration r pulls f_A, f_B
-// at row r (kept in registers for two iterations), writes that row's
-// densities and pseudopotentials to the ring, waits once at a barrier, and
-// completes row r - 2, whose 5 x 5 neighbourhood is then in the ring. Rows
-// are therefore pulled once from HBM; only the 4 halo columns per strip and
-// the 4 halo rows per chunk are pulled twice. The ring has 6 slots, so a
+// The strip marches upward one row per iteration. Iteration k pulls f_A, f_B
+// at row r = y0 - 2 + k (kept in registers for two iterations), writes that
+// row's densities and pseudopotentials to the ring, waits once at a barrier,
+// and completes row r - 2, whose 5 x 5 neighbourhood is then in the ring.
+// Rows are therefore pulled once from HBM; only the 4 halo columns per strip
+// and the 4 halo rows per chunk are pulled twice. The ring has 6 slots, so a
 // single barrier per row separates the writes of row r + 1 from the reads of
-// row r - 2.
+// row r - 2. The row loop is unrolled three times so that the three sets of
+// kept populations change roles by renaming, not by register moves.
 //
-// Memory layout: population p (0..26) of node (x, y) lives at
-// buf[p * pop_stride + y * pitch + x]; pitch is a multiple of 64 elements so
-// every wavefront row access is aligned.
+// Memory layout: population p (0..26) of node (x, y) lives at element
+// p * pop_stride + y * pitch + x of a buffer; pitch is a multiple of 64
+// elements so every wavefront row access is aligned. Addresses are formed as
+// a uniform base pointer plus a 32-bit byte offset (kWide = false, buffers
+// below 4 GiB), which maps to the scalar-base + vector-offset form of the
+// global loads and stores; kWide = true uses 64-bit offsets.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace tlbk {
 
@@ -85,7 +91,9 @@ template <typename T_> struct Store {
   using T = T_;
   using C = T_;
   __device__ static C load(const T* p) { return *p; }
-  __device__ static void store(T* p, C v) { *p = v; }
+  // The next step reads the stored populations from HBM anyway: stream them
+  // past the caches.
+  __device__ static void store(T* p, C v) { __builtin_nontemporal_store(v, p); }
 };
 
 // ---------------------------------------------------------------- arguments
@@ -111,7 +119,8 @@ enum : unsigned {
   kModeStore = 2u,    // write f*(t+1)
   kModeObserve = 4u,  // accumulate observable sums into partials
   kModeFields = 8u,   // write the fields
-  kModeSolid = 16u    // solid cells present: use the link masks
+  kModeSolid = 16u,   // solid cells present: use the link masks
+  kModeWide = 32u     // 64-bit byte offsets (population buffer >= 4 GiB)
 };
 
 template <typename C> __device__ inline C psi_exp(C rho, C rho0, C inv_rho0) {
@@ -123,367 +132,402 @@ __device__ inline float psi_exp(float rho, float rho0, float inv_rho0) {
   return -rho0 * expm1f(-rho * inv_rho0);
 }
 
+template <unsigned kMode>
+using Off = std::conditional_t<(kMode & kModeWide) != 0, uint64_t, uint32_t>;
+
+// Byte-offset addressing helpers (base pointer is uniform).
+template <class St, unsigned kMode>
+__device__ inline typename St::C ld(const void* base, Off<kMode> off) {
+  return St::load(reinterpret_cast<const typename St::T*>(static_cast<const char*>(base) + off));
+}
+template <class St, unsigned kMode>
+__device__ inline void st(void* base, Off<kMode> off, typename St::C v) {
+  St::store(reinterpret_cast<typename St::T*>(static_cast<char*>(base) + off), v);
+}
+
+// Per-node addressing: byte offset of the node in a population plane, and
+// the byte deltas to its x-1 and x+1 neighbours (periodic wrap included).
+template <unsigned kMode>
+struct NodeAddr {
+  Off<kMode> own;
+  Off<kMode> dxm, dxp;   // added modulo 2^32 / 2^64
+};
+
+template <class St, unsigned kMode>
+__device__ inline NodeAddr<kMode> node_addr(int x, int r, int lx, Off<kMode> row_b) {
+  using O = Off<kMode>;
+  constexpr int E = sizeof(typename St::T);
+  NodeAddr<kMode> n;
+  n.own = (O)r * row_b + (O)x * E;
+  n.dxm = (O)(x == 0 ? (lx - 1) * E : -E);
+  n.dxp = (O)(x == lx - 1 ? -(lx - 1) * E : E);
+  return n;
+}
+
+// Byte offset of the value pulled for direction I at a node (population
+// plane `base` + I or its opposite on bounce-back).
+template <int I, unsigned kMode>
+__device__ inline Off<kMode> pull_off(const NodeAddr<kMode>& n, uint32_t lm, Off<kMode> plane_b,
+                                      Off<kMode> row_b, Off<kMode> first_plane) {
+  using O = Off<kMode>;
+  if constexpr ((kMode & kModeInit) != 0) {
+    return first_plane + (O)I * plane_b + n.own;
+  } else {
+    constexpr int cx = Dir<I>::cx, cy = Dir<I>::cy;
+    O src = first_plane + (O)I * plane_b + n.own;
+    if constexpr (cy > 0) src -= row_b;
+    if constexpr (cy < 0) src += row_b;
+    if constexpr (cx > 0) src += n.dxm;
+    if constexpr (cx < 0) src += n.dxp;
+    if constexpr (I == 0) {
+      return src;
+    } else {
+      const O bb = first_plane + (O)Dir<I>::opp * plane_b + n.own;
+      return ((lm >> I) & 1u) ? bb : src;
+    }
+  }
+}
+
 // Link mask of node (x, r), 0 <= r < ly.
 template <unsigned kMode, typename C>
 __device__ inline uint32_t link_mask(const StepArgs<C>& a, int x, int r) {
   if constexpr ((kMode & kModeSolid) != 0) {
-    return a.link[(size_t)r * a.lx + x];
+    return a.link[(uint32_t)r * (uint32_t)a.lx + (uint32_t)x];
   } else {
     return (r == 0 ? kFromBelow : 0u) | (r == a.ly - 1 ? kFromAbove : 0u);
   }
 }
 
-// Element offset (within one population plane) and population index of the
-// value pulled for direction I at node (x, r); xm/xp are the wrapped x-1 and
-// x+1.
-template <int I, unsigned kMode>
-__device__ inline void pull_site(uint32_t lm, int x, int xm, int xp, int r, int pitch,
-                                 int& pop, int& off) {
-  if constexpr ((kMode & kModeInit) != 0) {
-    pop = I;
-    off = r * pitch + x;
-  } else {
-    constexpr int cx = Dir<I>::cx, cy = Dir<I>::cy;
-    const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
-    const bool bounce = (lm >> I) & 1u;
-    pop = bounce ? Dir<I>::opp : I;
-    off = bounce ? r * pitch + x : (r - cy) * pitch + sx;
+// Wall temperature of the solid source of direction I seen from (x, r).
+template <int I, unsigned kMode, typename C>
+__device__ inline C source_wall_temperature(const StepArgs<C>& a, int x, int r) {
+  constexpr int cx = Dir<I>::cx, cy = Dir<I>::cy;
+  const int lx = a.lx;
+  const int sx = cx > 0 ? (x == 0 ? lx - 1 : x - 1) : (cx < 0 ? (x == lx - 1 ? 0 : x + 1) : x);
+  const int sr = r - cy;
+  if (sr < 0) return a.t_bottom[sx];
+  if (sr >= a.ly) return a.t_top;
+  if constexpr ((kMode & kModeSolid) != 0) {
+    return a.solid[(uint32_t)sr * (uint32_t)lx + (uint32_t)sx] == 1 ? a.t_bottom[sx] : a.t_top;
   }
+  return a.t_top;
 }
 
-// Pull f_A and f_B at fluid node (x, r).
+// Pull f_A (f[0..8]) and f_B (f[9..17]) at fluid node n.
 template <class St, unsigned kMode, typename C>
-__device__ inline void pull_fluid(const StepArgs<C>& a, const typename St::T* __restrict__ src,
-                                  uint32_t lm, int x, int xm, int xp, int r, C (&fa)[9],
-                                  C (&fb)[9]) {
-  const long long ps = a.pop_stride;
-#define TLB_PULL_F(I)                                                  \
-  {                                                                    \
-    int pop, off;                                                      \
-    pull_site<I, kMode>(lm, x, xm, xp, r, a.pitch, pop, off);          \
-    fa[I] = St::load(src + (long long)pop * ps + off);                 \
-    fb[I] = St::load(src + (long long)(pop + 9) * ps + off);           \
+__device__ inline void pull_fluid(const void* src, const NodeAddr<kMode>& n, uint32_t lm,
+                                  Off<kMode> plane_b, Off<kMode> row_b, C (&f)[18]) {
+  const Off<kMode> plane9 = plane_b * 9;
+#define TLB_PULL_F(I)                                                            \
+  {                                                                              \
+    const Off<kMode> o = pull_off<I, kMode>(n, lm, plane_b, row_b, Off<kMode>(0)); \
+    f[I] = ld<St, kMode>(src, o);                                                \
+    f[I + 9] = ld<St, kMode>(src, o + plane9);                                   \
   }
   TLB_PULL_F(0) TLB_PULL_F(1) TLB_PULL_F(2) TLB_PULL_F(3) TLB_PULL_F(4)
   TLB_PULL_F(5) TLB_PULL_F(6) TLB_PULL_F(7) TLB_PULL_F(8)
 #undef TLB_PULL_F
 }
 
-// Wall temperature of the solid source of direction I seen from (x, r).
-template <int I, unsigned kMode, typename C>
-__device__ inline C source_wall_temperature(const StepArgs<C>& a, int x, int xm, int xp, int r) {
-  constexpr int cx = Dir<I>::cx, cy = Dir<I>::cy;
-  const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
-  const int sr = r - cy;
-  if (sr < 0) return a.t_bottom[sx];
-  if (sr >= a.ly) return a.t_top;
-  if constexpr ((kMode & kModeSolid) != 0) {
-    return a.solid[(size_t)sr * a.lx + sx] == 1 ? a.t_bottom[sx] : a.t_top;
-  }
-  return a.t_top;
-}
-
 // Pull g at fluid node (x, r) with anti-bounce-back at solid sources:
 // g_i = -g*_{opp i}(x) + 2 w_i T_w.
 template <class St, unsigned kMode, typename C>
-__device__ inline void pull_thermal(const StepArgs<C>& a, const typename St::T* __restrict__ src,
-                                    uint32_t lm, int x, int xm, int xp, int r, C (&g)[9]) {
-  const long long ps = a.pop_stride;
-#define TLB_PULL_G(I)                                                            \
-  {                                                                              \
-    int pop, off;                                                                \
-    pull_site<I, kMode>(lm, x, xm, xp, r, a.pitch, pop, off);                    \
-    C v = St::load(src + (long long)(pop + 18) * ps + off);                      \
-    if constexpr ((kMode & kModeInit) == 0 && I != 0) {                          \
-      if ((lm >> I) & 1u)                                                        \
-        v = C(2) * w_dir<C>(I) * source_wall_temperature<I, kMode>(a, x, xm, xp, r) - v; \
-    }                                                                            \
-    g[I] = v;                                                                    \
+__device__ inline void pull_thermal(const StepArgs<C>& a, const void* src, const NodeAddr<kMode>& n,
+                                    uint32_t lm, Off<kMode> plane_b, Off<kMode> row_b, int x, int r,
+                                    C (&g)[9]) {
+  const Off<kMode> plane18 = plane_b * 18;
+#define TLB_PULL_G(I)                                                                       \
+  {                                                                                         \
+    C v = ld<St, kMode>(src, pull_off<I, kMode>(n, lm, plane_b, row_b, plane18));           \
+    if constexpr ((kMode & kModeInit) == 0 && I != 0) {                                     \
+      if ((lm >> I) & 1u) v = C(2) * w_dir<C>(I) * source_wall_temperature<I, kMode>(a, x, r) - v; \
+    }                                                                                       \
+    g[I] = v;                                                                               \
   }
   TLB_PULL_G(0) TLB_PULL_G(1) TLB_PULL_G(2) TLB_PULL_G(3) TLB_PULL_G(4)
   TLB_PULL_G(5) TLB_PULL_G(6) TLB_PULL_G(7) TLB_PULL_G(8)
 #undef TLB_PULL_G
 }
 
-template <typename C> __device__ inline C sum9(const C (&f)[9]) {
+template <typename C> __device__ inline C sum9(const C* f) {
   return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
 }
 
 // Wall temperature of a solid node (x, y) inside the lattice.
 template <typename C>
 __device__ inline C solid_temperature(const StepArgs<C>& a, int x, int y) {
-  return a.solid[(size_t)y * a.lx + x] == 1 ? a.t_bottom[x] : a.t_top;
+  return a.solid[(uint32_t)y * (uint32_t)a.lx + (uint32_t)x] == 1 ? a.t_bottom[x] : a.t_top;
 }
 
 // Temperature of the neighbour (x, r) of a fluid node whose temperature is
 // t_here, for the central difference of dT/dy: T itself if fluid, else the
 // mirror value 2 T_w - t_here (wall plane half-way).
 template <class St, unsigned kMode, typename C>
-__device__ inline C neighbour_temperature(const StepArgs<C>& a, const typename St::T* __restrict__ src,
-                                          int x, int xm, int xp, int r, C t_here) {
+__device__ inline C neighbour_temperature(const StepArgs<C>& a, const void* src, int x, int r,
+                                          C t_here, Off<kMode> plane_b, Off<kMode> row_b) {
   if (r < 0) return C(2) * a.t_bottom[x] - t_here;
   if (r >= a.ly) return C(2) * a.t_top - t_here;
   const uint32_t lm = link_mask<kMode>(a, x, r);
   if (lm & kSelfSolid) return C(2) * solid_temperature(a, x, r) - t_here;
+  const NodeAddr<kMode> n = node_addr<St, kMode>(x, r, a.lx, row_b);
   C g[9];
-  pull_thermal<St, kMode>(a, src, lm, x, xm, xp, r, g);
+  pull_thermal<St, kMode>(a, src, n, lm, plane_b, row_b, x, r, g);
   return sum9(g);
 }
 
 // ---------------------------------------------------------------- kernel
 template <class St, int BX, unsigned kMode>
-__global__ __launch_bounds__(BX) void lb_step_kernel(StepArgs<typename St::C> a) {
+__global__ __launch_bounds__(BX)
+#if defined(TLB_WAVES_PER_EU)
+__attribute__((amdgpu_waves_per_eu(TLB_WAVES_PER_EU)))
+#endif
+void lb_step_kernel(StepArgs<typename St::C> a) {
   using C = typename St::C;
   using T = typename St::T;
+  using O = Off<kMode>;
   constexpr int W = BX + 4;   // ring row width: strip plus 2 halo columns each side
   constexpr int R = 6;        // ring rows
   __shared__ C s_rho[2][R][W];
   __shared__ C s_psi[2][R][W];
 
-  const T* __restrict__ src = static_cast<const T*>(a.src);
-  T* __restrict__ dst = static_cast<T*>(a.dst);
+  const void* src = a.src;
+  void* dst = a.dst;
   const int lx = a.lx, ly = a.ly;
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * BX;
   const int y0 = blockIdx.y * a.rows_per_block;
   const int y1 = min(y0 + a.rows_per_block, ly);
+  const O row_b = (O)a.pitch * sizeof(T);
+  const O plane_b = (O)a.pop_stride * sizeof(T);
 
   // own column (idle threads of a ragged strip still fill their ring slot,
   // with a wrapped column, so the halo of the last valid column is right)
   const int xo = x0 + tid;
   const bool own_valid = xo < lx;
   const int xw = xo % lx;
-  const int xwm = xw == 0 ? lx - 1 : xw - 1;
-  const int xwp = xw == lx - 1 ? 0 : xw + 1;
 
-  // halo slots 0, 1, BX+2, BX+3: one thread in each quarter of the block
-  constexpr int kQuarter = BX / 4;
-  const bool is_halo = (tid % kQuarter) == 0;
-  const int hq = tid / kQuarter;
-  const int hslot = hq < 2 ? hq : BX + hq;
+  // halo slots 0, 1, BX+2, BX+3: lanes 0..3 of one wavefront, taken in turn
+  // by the block's wavefronts from row to row (a single divergent pass per
+  // row instead of one per wavefront)
+  constexpr int kWaves = BX / 64;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int hslot = lane < 2 ? lane : BX + lane;
   const int hx = ((x0 - 2 + hslot) % lx + lx) % lx;
-  const int hxm = hx == 0 ? lx - 1 : hx - 1;
-  const int hxp = hx == lx - 1 ? 0 : hx + 1;
 
   const C psi_w0 = psi_exp(a.rho_wall0, a.rho0, a.inv_rho0);
   const C psi_w1 = psi_exp(a.rho_wall1, a.rho0, a.inv_rho0);
 
-  C fa0[9], fb0[9], fa1[9], fb1[9], fa2[9], fb2[9];
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
 
-  // Density of node (x, r) (wall values at ghost rows and solid nodes).
-  auto density = [&](int x, int xm, int xp, int r, C (&fa)[9], C (&fb)[9], C& ra, C& rb) {
-    if (r < 0 || r >= ly) {
-      ra = a.rho_wall0;
-      rb = a.rho_wall1;
-      return;
+  // Densities of node (x, r) into ring slot `slot` / column `col`; the pulled
+  // populations land in f and the node's link mask in lm.
+  auto density = [&](int x, int r, int slot, int col, C (&f)[18], uint32_t& lm) {
+    C ra = a.rho_wall0, rb = a.rho_wall1, pa = psi_w0, pb = psi_w1;
+    lm = kSelfSolid;
+    if (r >= 0 && r < ly) {
+      lm = link_mask<kMode>(a, x, r);
+      if (!((kMode & kModeSolid) != 0 && (lm & kSelfSolid))) {
+        const NodeAddr<kMode> n = node_addr<St, kMode>(x, r, lx, row_b);
+        pull_fluid<St, kMode>(src, n, lm, plane_b, row_b, f);
+        ra = sum9(f);
+        rb = sum9(f + 9);
+        pa = psi_exp(ra, a.rho0, a.inv_rho0);
+        pb = psi_exp(rb, a.rho0, a.inv_rho0);
+      }
     }
-    const uint32_t lm = link_mask<kMode>(a, x, r);
-    if ((kMode & kModeSolid) != 0 && (lm & kSelfSolid)) {
-      ra = a.rho_wall0;
-      rb = a.rho_wall1;
-      return;
-    }
-    pull_fluid<St, kMode>(a, src, lm, x, xm, xp, r, fa, fb);
-    ra = sum9(fa);
-    rb = sum9(fb);
+    s_rho[0][slot][col] = ra;
+    s_rho[1][slot][col] = rb;
+    s_psi[0][slot][col] = pa;
+    s_psi[1][slot][col] = pb;
   };
 
-  const int r_first = y0 - 2;
-  const int n_iter = (y1 - y0) + 4;
-  for (int k = 0; k < n_iter; ++k) {
-    const int r = r_first + k;
+  // One row iteration: pull row r = y0 - 2 + k into fw/lw and complete row
+  // r - 2 from fu/lu (pulled two iterations earlier).
+  auto iterate = [&](int k, C (&fw)[18], uint32_t& lw, const C (&fu)[18], uint32_t lu) {
+    const int r = y0 - 2 + k;
     const int slot = k % R;
-    {
-      C ra, rb;
-      density(xw, xwm, xwp, r, fa2, fb2, ra, rb);
-      s_rho[0][slot][tid + 2] = ra;
-      s_rho[1][slot][tid + 2] = rb;
-      s_psi[0][slot][tid + 2] = (r < 0 || r >= ly) ? psi_w0 : psi_exp(ra, a.rho0, a.inv_rho0);
-      s_psi[1][slot][tid + 2] = (r < 0 || r >= ly) ? psi_w1 : psi_exp(rb, a.rho0, a.inv_rho0);
-    }
-    if (is_halo) {
-      C ha[9], hb[9], ra, rb;
-      density(hx, hxm, hxp, r, ha, hb, ra, rb);
-      s_rho[0][slot][hslot] = ra;
-      s_rho[1][slot][hslot] = rb;
-      s_psi[0][slot][hslot] = (r < 0 || r >= ly) ? psi_w0 : psi_exp(ra, a.rho0, a.inv_rho0);
-      s_psi[1][slot][hslot] = (r < 0 || r >= ly) ? psi_w1 : psi_exp(rb, a.rho0, a.inv_rho0);
+    density(xw, r, slot, tid + 2, fw, lw);
+    if (wave == k % kWaves && lane < 4) {
+      C hf[18];
+      uint32_t hl;
+      density(hx, r, slot, hslot, hf, hl);
     }
     __syncthreads();
 
     const int y = r - 2;  // row completed in this iteration
-    if (k >= 4 && own_valid) {
-      const uint32_t lm = link_mask<kMode>(a, xw, y);
-      const long long ps = a.pop_stride;
-      const int off = y * a.pitch + xo;
-      if ((kMode & kModeSolid) != 0 && (lm & kSelfSolid)) {
-        if constexpr ((kMode & kModeStore) != 0) {
+    if (k < 4 || y >= y1 || !own_valid) return;
+    const NodeAddr<kMode> n = node_addr<St, kMode>(xw, y, lx, row_b);
+    if ((kMode & kModeSolid) != 0 && (lu & kSelfSolid)) {
+      if constexpr ((kMode & kModeStore) != 0) {
 #pragma unroll
-          for (int p = 0; p < 27; ++p) St::store(dst + p * ps + off, C(0));
-        }
-        if constexpr ((kMode & kModeFields) != 0) {
-          const size_t n = (size_t)lx * ly, q = (size_t)y * lx + xo;
-          a.fields[q] = (double)a.rho_wall0;
-          a.fields[n + q] = (double)a.rho_wall1;
-          a.fields[2 * n + q] = 0.0;
-          a.fields[3 * n + q] = 0.0;
-          a.fields[4 * n + q] = (double)solid_temperature(a, xo, y);
-        }
-      } else {
-        // ---- moments (rows kept from two iterations ago)
-        const C ra = sum9(fa0), rb = sum9(fb0);
-        const C jx = ((fa0[1] - fa0[3]) + (fa0[5] - fa0[7]) + (fa0[8] - fa0[6])) +
-                     ((fb0[1] - fb0[3]) + (fb0[5] - fb0[7]) + (fb0[8] - fb0[6]));
-        const C jy = ((fa0[2] - fa0[4]) + (fa0[5] - fa0[7]) + (fa0[6] - fa0[8])) +
-                     ((fb0[2] - fb0[4]) + (fb0[5] - fb0[7]) + (fb0[6] - fb0[8]));
-        C g[9];
-        pull_thermal<St, kMode>(a, src, lm, xw, xwm, xwp, y, g);
-        const C temp = sum9(g);
+        for (int p = 0; p < 27; ++p) st<St, kMode>(dst, (O)p * plane_b + n.own, C(0));
+      }
+      if constexpr ((kMode & kModeFields) != 0) {
+        const size_t nn = (size_t)lx * ly, q = (size_t)y * lx + xo;
+        a.fields[q] = (double)a.rho_wall0;
+        a.fields[nn + q] = (double)a.rho_wall1;
+        a.fields[2 * nn + q] = 0.0;
+        a.fields[3 * nn + q] = 0.0;
+        a.fields[4 * nn + q] = (double)solid_temperature(a, xo, y);
+      }
+      return;
+    }
+    // ---- moments
+    const C* fa = fu;
+    const C* fb = fu + 9;
+    const C ra = sum9(fa), rb = sum9(fb);
+    const C jx = ((fa[1] - fa[3]) + (fa[5] - fa[7]) + (fa[8] - fa[6])) +
+                 ((fb[1] - fb[3]) + (fb[5] - fb[7]) + (fb[8] - fb[6]));
+    const C jy = ((fa[2] - fa[4]) + (fa[5] - fa[7]) + (fa[6] - fa[8])) +
+                 ((fb[2] - fb[4]) + (fb[5] - fb[7]) + (fb[6] - fb[8]));
+    C g[9];
+    pull_thermal<St, kMode>(a, src, n, lu, plane_b, row_b, xw, y, g);
+    const C temp = sum9(g);
 
-        // ---- forces from the ring (rows y-2..y+2 are slots k-4..k)
-        const int s0 = tid + 2;
-        int rs[5];
+    // ---- forces from the ring (rows y-2..y+2 are slots k-4..k)
+    const int s0 = tid + 2;
+    int rs[5];
 #pragma unroll
-        for (int d = 0; d < 5; ++d) rs[d] = (k + 2 + d) % R;  // d = dy + 2
-        C fA[2] = {C(0), C(0)}, fB[2] = {C(0), C(0)};
-        // component self forces: attraction (NN, w) and repulsion (25, p)
+    for (int d = 0; d < 5; ++d) rs[d] = (k + 2 + d) % R;  // d = dy + 2
+    C FA[2], FB[2];
 #pragma unroll
-        for (int l = 0; l < 2; ++l) {
-          C ax = 0, ay = 0, qx = 0, qy = 0;  // NN sums (w), 25-point sums (p)
+    for (int l = 0; l < 2; ++l) {
+      C ax = 0, ay = 0, qx = 0, qy = 0;  // NN sums (w), 25-point sums (p)
 #pragma unroll
-          for (int dy = -2; dy <= 2; ++dy) {
+      for (int dy = -2; dy <= 2; ++dy) {
 #pragma unroll
-            for (int dx = 1; dx <= 2; ++dx) {
-              const int c2 = dx * dx + dy * dy;
-              const C diff = s_psi[l][rs[dy + 2]][s0 + dx] - s_psi[l][rs[dy + 2]][s0 - dx];
-              qx += (p_c2<C>(c2) * C(dx)) * diff;
-              if (c2 <= 2) ax += (w_c2<C>(c2) * C(dx)) * diff;
-            }
-          }
-#pragma unroll
-          for (int dx = -2; dx <= 2; ++dx) {
-#pragma unroll
-            for (int dy = 1; dy <= 2; ++dy) {
-              const int c2 = dx * dx + dy * dy;
-              const C diff = s_psi[l][rs[dy + 2]][s0 + dx] - s_psi[l][rs[2 - dy]][s0 + dx];
-              qy += (p_c2<C>(c2) * C(dy)) * diff;
-              if (c2 <= 2) ay += (w_c2<C>(c2) * C(dy)) * diff;
-            }
-          }
-          const C psi_here = s_psi[l][rs[2]][s0];
-          const C ga = l == 0 ? a.ga0 : a.ga1;
-          const C gr = l == 0 ? a.gr0 : a.gr1;
-          C& Fx = l == 0 ? fA[0] : fB[0];
-          C& Fy = l == 0 ? fA[1] : fB[1];
-          Fx = -psi_here * (ga * ax + gr * qx);
-          Fy = -psi_here * (ga * ay + gr * qy);
-        }
-        // cross force (NN, w, psi = rho / rho0): acts on l from the other one
-#pragma unroll
-        for (int l = 0; l < 2; ++l) {
-          const int m = 1 - l;
-          C sx = 0, sy = 0;
-#pragma unroll
-          for (int dy = -1; dy <= 1; ++dy) {
-            const int c2 = 1 + dy * dy;
-            sx += w_c2<C>(c2) * (s_rho[m][rs[dy + 2]][s0 + 1] - s_rho[m][rs[dy + 2]][s0 - 1]);
-          }
-#pragma unroll
-          for (int dx = -1; dx <= 1; ++dx) {
-            const int c2 = 1 + dx * dx;
-            sy += w_c2<C>(c2) * (s_rho[m][rs[3]][s0 + dx] - s_rho[m][rs[1]][s0 + dx]);
-          }
-          const C rl = l == 0 ? ra : rb;
-          const C pre = -a.g12 * rl * a.inv_rho0 * a.inv_rho0;
-          C& Fx = l == 0 ? fA[0] : fB[0];
-          C& Fy = l == 0 ? fA[1] : fB[1];
-          Fx += pre * sx;
-          Fy += pre * sy;
-        }
-        // buoyancy (Eq. (22))
-        fA[1] += ra * a.alpha_g * temp;
-        fB[1] += rb * a.alpha_g * temp;
-
-        // ---- velocities
-        const C rho = ra + rb;
-        const C inv_rho = C(1) / rho;
-        const C ux = jx * inv_rho, uy = jy * inv_rho;
-        const C Fx = fA[0] + fB[0], Fy = fA[1] + fB[1];
-        const C hx = ux + C(0.5) * Fx * inv_rho;
-        const C hy = uy + C(0.5) * Fy * inv_rho;
-
-        if constexpr ((kMode & kModeStore) != 0) {
-          const C tA = a.tau / ra, tB = a.tau / rb;
-          const C uax = ux + fA[0] * tA, uay = uy + fA[1] * tA;
-          const C ubx = ux + fB[0] * tB, uby = uy + fB[1] * tB;
-          const C ua2 = uax * uax + uay * uay;
-          const C ub2 = ubx * ubx + uby * uby;
-          const C uh2 = hx * hx + hy * hy;
-          // BGK relaxation written as f^eq + (1 - 1/tau)(f - f^eq): exactly
-          // f^eq at tau = 1. The rest population's equilibrium is the zeroth
-          // moment minus the other eight, so the stored populations sum to
-          // rho (and T) up to unbiased rounding: the weights rounded to the
-          // storage type do not sum to 1 and would otherwise create mass at
-          // every collision.
-          const C ka = C(1) - a.inv_tau, kg = C(1) - a.inv_tau_g;
-          C sa = 0, sb = 0, sg = 0;
-#define TLB_COLLIDE(I)                                                                     \
-  {                                                                                        \
-    constexpr int cx = Dir<I>::cx, cy = Dir<I>::cy;                                       \
-    constexpr C w = w_dir<C>(I);                                                           \
-    const C cua = C(cx) * uax + C(cy) * uay;                                               \
-    const C cub = C(cx) * ubx + C(cy) * uby;                                               \
-    const C cuh = C(cx) * hx + C(cy) * hy;                                                 \
-    const C ea = w * ra * (C(1) + C(3) * cua + C(4.5) * cua * cua - C(1.5) * ua2);         \
-    const C eb = w * rb * (C(1) + C(3) * cub + C(4.5) * cub * cub - C(1.5) * ub2);         \
-    const C eg = w * temp * (C(1) + C(3) * cuh + C(4.5) * cuh * cuh - C(1.5) * uh2);       \
-    sa += ea;                                                                              \
-    sb += eb;                                                                              \
-    sg += eg;                                                                              \
-    St::store(dst + I * ps + off, ea + ka * (fa0[I] - ea));                                \
-    St::store(dst + (I + 9) * ps + off, eb + ka * (fb0[I] - eb));                          \
-    St::store(dst + (I + 18) * ps + off, eg + kg * (g[I] - eg));                           \
-  }
-          TLB_COLLIDE(1) TLB_COLLIDE(2) TLB_COLLIDE(3) TLB_COLLIDE(4)
-          TLB_COLLIDE(5) TLB_COLLIDE(6) TLB_COLLIDE(7) TLB_COLLIDE(8)
-#undef TLB_COLLIDE
-          {
-            const C ea = ra - sa, eb = rb - sb, eg = temp - sg;
-            St::store(dst + off, ea + ka * (fa0[0] - ea));
-            St::store(dst + 9 * ps + off, eb + ka * (fb0[0] - eb));
-            St::store(dst + 18 * ps + off, eg + kg * (g[0] - eg));
-          }
-        }
-        if constexpr ((kMode & kModeFields) != 0) {
-          const size_t n = (size_t)lx * ly, q = (size_t)y * lx + xo;
-          a.fields[q] = (double)ra;
-          a.fields[n + q] = (double)rb;
-          a.fields[2 * n + q] = (double)hx;
-          a.fields[3 * n + q] = (double)hy;
-          a.fields[4 * n + q] = (double)temp;
-        }
-        if constexpr ((kMode & kModeObserve) != 0) {
-          const C tn = neighbour_temperature<St, kMode>(a, src, xw, xwm, xwp, y + 1, temp);
-          const C ts = neighbour_temperature<St, kMode>(a, src, xw, xwm, xwp, y - 1, temp);
-          acc[0] += (double)ra;
-          acc[1] += (double)rb;
-          acc[2] += (double)temp;
-          acc[3] += (double)hy * (double)temp;
-          acc[4] += 0.5 * ((double)tn - (double)ts);
-          acc[5] += (double)hx * (double)hx + (double)hy * (double)hy;
-          if (y == ly - 1) acc[6] += (double)temp - (double)a.t_top;
+        for (int dx = 1; dx <= 2; ++dx) {
+          const int c2 = dx * dx + dy * dy;
+          const C diff = s_psi[l][rs[dy + 2]][s0 + dx] - s_psi[l][rs[dy + 2]][s0 - dx];
+          qx += (p_c2<C>(c2) * C(dx)) * diff;
+          if (c2 <= 2) ax += (w_c2<C>(c2) * C(dx)) * diff;
         }
       }
-    }
-    // rotate the kept rows: row r-1 -> slot 0, row r -> slot 1
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      fa0[i] = fa1[i];
-      fb0[i] = fb1[i];
-      fa1[i] = fa2[i];
-      fb1[i] = fb2[i];
+      for (int dx = -2; dx <= 2; ++dx) {
+#pragma unroll
+        for (int dy = 1; dy <= 2; ++dy) {
+          const int c2 = dx * dx + dy * dy;
+          const C diff = s_psi[l][rs[dy + 2]][s0 + dx] - s_psi[l][rs[2 - dy]][s0 + dx];
+          qy += (p_c2<C>(c2) * C(dy)) * diff;
+          if (c2 <= 2) ay += (w_c2<C>(c2) * C(dy)) * diff;
+        }
+      }
+      const C psi_here = s_psi[l][rs[2]][s0];
+      const C ga = l == 0 ? a.ga0 : a.ga1;
+      const C gr = l == 0 ? a.gr0 : a.gr1;
+      C* F = l == 0 ? FA : FB;
+      F[0] = -psi_here * (ga * ax + gr * qx);
+      F[1] = -psi_here * (ga * ay + gr * qy);
     }
+    // cross force (NN, w, psi = rho / rho0): acts on l from the other one
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      const int m = 1 - l;
+      C sx = 0, sy = 0;
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int c2 = 1 + dy * dy;
+        sx += w_c2<C>(c2) * (s_rho[m][rs[dy + 2]][s0 + 1] - s_rho[m][rs[dy + 2]][s0 - 1]);
+      }
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int c2 = 1 + dx * dx;
+        sy += w_c2<C>(c2) * (s_rho[m][rs[3]][s0 + dx] - s_rho[m][rs[1]][s0 + dx]);
+      }
+      const C rl = l == 0 ? ra : rb;
+      const C pre = -a.g12 * rl * a.inv_rho0 * a.inv_rho0;
+      C* F = l == 0 ? FA : FB;
+      F[0] += pre * sx;
+      F[1] += pre * sy;
+    }
+    // buoyancy (Eq. (22))
+    FA[1] += ra * a.alpha_g * temp;
+    FB[1] += rb * a.alpha_g * temp;
+
+    // ---- velocities
+    const C rho = ra + rb;
+    const C inv_rho = C(1) / rho;
+    const C ux = jx * inv_rho, uy = jy * inv_rho;
+    const C Fx = FA[0] + FB[0], Fy = FA[1] + FB[1];
+    const C hx = ux + C(0.5) * Fx * inv_rho;
+    const C hy = uy + C(0.5) * Fy * inv_rho;
+
+    if constexpr ((kMode & kModeStore) != 0) {
+      const C tA = a.tau / ra, tB = a.tau / rb;
+      const C uax = ux + FA[0] * tA, uay = uy + FA[1] * tA;
+      const C ubx = ux + FB[0] * tB, uby = uy + FB[1] * tB;
+      const C ua2 = uax * uax + uay * uay;
+      const C ub2 = ubx * ubx + uby * uby;
+      const C uh2 = hx * hx + hy * hy;
+      // BGK relaxation written as f^eq + (1 - 1/tau)(f - f^eq): exactly f^eq
+      // at tau = 1. The rest population's equilibrium is the zeroth moment
+      // minus the other eight, so the stored populations sum to rho (and T)
+      // up to unbiased rounding: the weights rounded to the storage type do
+      // not sum to 1 and would otherwise create mass at every collision.
+      const C ka = C(1) - a.inv_tau, kg = C(1) - a.inv_tau_g;
+      C sa = 0, sb = 0, sg = 0;
+      const O p9 = plane_b * 9, p18 = plane_b * 18;
+#define TLB_COLLIDE(I)                                                                 \
+  {                                                                                    \
+    constexpr int cx = Dir<I>::cx, cy = Dir<I>::cy;                                   \
+    constexpr C w = w_dir<C>(I);                                                       \
+    const C cua = C(cx) * uax + C(cy) * uay;                                           \
+    const C cub = C(cx) * ubx + C(cy) * uby;                                           \
+    const C cuh = C(cx) * hx + C(cy) * hy;                                             \
+    const C ea = w * ra * (C(1) + C(3) * cua + C(4.5) * cua * cua - C(1.5) * ua2);     \
+    const C eb = w * rb * (C(1) + C(3) * cub + C(4.5) * cub * cub - C(1.5) * ub2);     \
+    const C eg = w * temp * (C(1) + C(3) * cuh + C(4.5) * cuh * cuh - C(1.5) * uh2);   \
+    sa += ea;                                                                          \
+    sb += eb;                                                                          \
+    sg += eg;                                                                          \
+    const O o = (O)I * plane_b + n.own;                                                \
+    st<St, kMode>(dst, o, ea + ka * (fa[I] - ea));                                     \
+    st<St, kMode>(dst, o + p9, eb + ka * (fb[I] - eb));                                \
+    st<St, kMode>(dst, o + p18, eg + kg * (g[I] - eg));                                \
+  }
+      TLB_COLLIDE(1) TLB_COLLIDE(2) TLB_COLLIDE(3) TLB_COLLIDE(4)
+      TLB_COLLIDE(5) TLB_COLLIDE(6) TLB_COLLIDE(7) TLB_COLLIDE(8)
+#undef TLB_COLLIDE
+      {
+        const C ea = ra - sa, eb = rb - sb, eg = temp - sg;
+        st<St, kMode>(dst, n.own, ea + ka * (fa[0] - ea));
+        st<St, kMode>(dst, n.own + p9, eb + ka * (fb[0] - eb));
+        st<St, kMode>(dst, n.own + p18, eg + kg * (g[0] - eg));
+      }
+    }
+    if constexpr ((kMode & kModeFields) != 0) {
+      const size_t nn = (size_t)lx * ly, q = (size_t)y * lx + xo;
+      a.fields[q] = (double)ra;
+      a.fields[nn + q] = (double)rb;
+      a.fields[2 * nn + q] = (double)hx;
+      a.fields[3 * nn + q] = (double)hy;
+      a.fields[4 * nn + q] = (double)temp;
+    }
+    if constexpr ((kMode & kModeObserve) != 0) {
+      const C tn = neighbour_temperature<St, kMode>(a, src, xw, y + 1, temp, plane_b, row_b);
+      const C ts = neighbour_temperature<St, kMode>(a, src, xw, y - 1, temp, plane_b, row_b);
+      acc[0] += (double)ra;
+      acc[1] += (double)rb;
+      acc[2] += (double)temp;
+      acc[3] += (double)hy * (double)temp;
+      acc[4] += 0.5 * ((double)tn - (double)ts);
+      acc[5] += (double)hx * (double)hx + (double)hy * (double)hy;
+      if (y == ly - 1) acc[6] += (double)temp - (double)a.t_top;
+    }
+  };
+
+  // Three sets of kept rows; the unrolled loop rotates their roles. The
+  // iteration count is rounded up to a multiple of 3: the extra iterations
+  // only pull in-range rows (or ghost rows) and complete nothing.
+  C f0[18], f1[18], f2[18];
+  uint32_t l0 = 0, l1 = 0, l2 = 0;
+  const int n_iter = ((y1 - y0) + 4 + 2) / 3 * 3;
+  for (int k = 0; k < n_iter; k += 3) {
+    iterate(k, f0, l0, f1, l1);
+    iterate(k + 1, f1, l1, f2, l2);
+    iterate(k + 2, f2, l2, f0, l0);
   }
 
   if constexpr ((kMode & kModeObserve) != 0) {
@@ -552,7 +596,7 @@ __global__ __launch_bounds__(256) void lb_init_equilibrium(
   const int y = blockIdx.y;
   if (x >= lx) return;
   const size_t q = (size_t)y * lx + x;
-  const int off = y * pitch + x;
+  const long long off = (long long)y * pitch + x;
   const bool is_solid = solid != nullptr && solid[q] != 0;
   const C ux = ux0 ? (C)ux0[q] : C(0), uy = uy0 ? (C)uy0[q] : C(0);
   const C u2 = ux * ux + uy * uy;
@@ -584,7 +628,8 @@ __global__ __launch_bounds__(256) void lb_export_populations(
   const int y = blockIdx.y;
   const int p = blockIdx.z;
   if (x >= lx) return;
-  out[((size_t)p * ly + y) * lx + x] = (double)St::load(buf + p * pop_stride + y * pitch + x);
+  out[((size_t)p * ly + y) * lx + x] =
+      (double)St::load(buf + p * pop_stride + (long long)y * pitch + x);
 }
 
 }  // namespace tlbk

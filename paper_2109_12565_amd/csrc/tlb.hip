@@ -20,6 +20,7 @@ thread_local char g_init_error[512];
 struct Launch {
   int bx;              // columns (threads) per block
   int rows;            // rows per block chunk
+  bool wide;           // 64-bit byte offsets (population buffer >= 4 GiB)
   dim3 grid;
 };
 
@@ -68,16 +69,56 @@ int fail(tlb_handle* h, int code, const char* fmt, ...) {
 
 bool is_fp64(const tlb_handle* h) { return h->p.precision == TLB_FP64; }
 
-Launch choose_launch(int lx, int ly) {
+// Launch geometry: 256-wide strips for wide lattices, 64-wide otherwise; the
+// rows per block are chosen so that the grid fills the GPU's resident block
+// slots about once (the occupancy of the kernel that will run), within
+// [11, 65] rows and with rows + 4 a multiple of 3 (the row loop is unrolled
+// three times). TLB_ROWS_PER_BLOCK overrides the row count.
+template <class St, int BX, unsigned kMode>
+int resident_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tlbk::lb_step_kernel<St, BX, kMode>, BX, 0) !=
+          hipSuccess ||
+      n < 1)
+    n = 1;
+  return n;
+}
+
+template <class St>
+int step_blocks_per_cu(int bx, bool wide, bool solid) {
+  using namespace tlbk;
+  constexpr unsigned S = kModeStore;
+  if (wide) return solid ? resident_blocks_per_cu<St, 256, S | kModeSolid | kModeWide>()
+                         : resident_blocks_per_cu<St, 256, S | kModeWide>();
+  if (bx == 256) return solid ? resident_blocks_per_cu<St, 256, S | kModeSolid>()
+                              : resident_blocks_per_cu<St, 256, S>();
+  return solid ? resident_blocks_per_cu<St, 64, S | kModeSolid>() : resident_blocks_per_cu<St, 64, S>();
+}
+
+Launch choose_launch(const tlb_params& p, size_t buffer_bytes, bool solid) {
   Launch l;
-  l.bx = lx >= 1024 ? 256 : 64;
-  int rows = 64;
+  const int lx = p.lx, ly = p.ly;
+  // 32-bit byte offsets address the whole population buffer below 4 GiB;
+  // TLB_FORCE_WIDE=1 selects the 64-bit variant at any size (for testing).
+  const char* force = std::getenv("TLB_FORCE_WIDE");
+  l.wide = buffer_bytes > 0xFFFFFFFFull || (force && std::atoi(force) == 1);
+  l.bx = (lx >= 2048 || l.wide) ? 256 : 64;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int per_cu = p.precision == TLB_FP64 ? step_blocks_per_cu<tlbk::Store<double>>(l.bx, l.wide, solid)
+                                             : step_blocks_per_cu<tlbk::Store<float>>(l.bx, l.wide, solid);
+  const long long slots = (long long)cus * per_cu;
+  const long long strips = (lx + l.bx - 1) / l.bx;
+  long long rows = (ly * strips + slots - 1) / slots;
+  rows = rows < 11 ? 11 : (rows > 65 ? 65 : rows);
+  while ((rows + 4) % 3) ++rows;
   if (const char* env = std::getenv("TLB_ROWS_PER_BLOCK")) {
     int v = std::atoi(env);
     if (v >= 1 && v <= 4096) rows = v;
   }
-  l.rows = rows < ly ? rows : ly;
-  l.grid = dim3((lx + l.bx - 1) / l.bx, (ly + l.rows - 1) / l.rows, 1);
+  l.rows = (int)(rows < ly ? rows : ly);
+  l.grid = dim3((unsigned)strips, (unsigned)((ly + l.rows - 1) / l.rows), 1);
   return l;
 }
 
@@ -120,17 +161,20 @@ void launch_step(const tlb_handle* h, const tlbk::StepArgs<typename St::C>& a) {
                      h->stream, a);
 }
 
-// Dispatch on block width and on the presence of solid cells.
+// Dispatch on block width, offset width and the presence of solid cells
+// (the 64-bit offset variant always runs 256-wide blocks).
+template <class St, unsigned kMode>
+void launch_solid(const tlb_handle* h, const tlbk::StepArgs<typename St::C>& a) {
+  if (h->launch.wide) launch_step<St, 256, kMode | tlbk::kModeWide>(h, a);
+  else if (h->launch.bx == 256) launch_step<St, 256, kMode>(h, a);
+  else launch_step<St, 64, kMode>(h, a);
+}
+
 template <class St, unsigned kMode>
 void launch_mode(const tlb_handle* h, const void* src, void* dst) {
   auto a = make_args<typename St::C>(h, src, dst);
-  if (h->has_solid) {
-    if (h->launch.bx == 256) launch_step<St, 256, kMode | tlbk::kModeSolid>(h, a);
-    else launch_step<St, 64, kMode | tlbk::kModeSolid>(h, a);
-  } else {
-    if (h->launch.bx == 256) launch_step<St, 256, kMode>(h, a);
-    else launch_step<St, 64, kMode>(h, a);
-  }
+  if (h->has_solid) launch_solid<St, kMode | tlbk::kModeSolid>(h, a);
+  else launch_solid<St, kMode>(h, a);
 }
 
 template <unsigned kMode>
@@ -212,7 +256,7 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
   h->pitch = (lx + 63) / 64 * 64;
   h->pop_stride = (long long)h->pitch * ly;
   h->elem = is_fp64(h) ? sizeof(double) : sizeof(float);
-  h->launch = choose_launch(lx, ly);
+  h->launch = choose_launch(*p, (size_t)27 * h->pop_stride * h->elem, h->has_solid);
 
   int rc = TLB_OK;
   auto cleanup_fail = [&](int code) {

@@ -222,3 +222,20 @@ def test_fp32_full_size_mass_and_translation_over_1000_steps(name):
     fa, fb = a.fields(), b.fields()
     for k in fa:
         assert np.array_equal(sh(fa[k]), fb[k]), k
+
+
+def test_wide_offsets_match_narrow_bitwise(monkeypatch):
+    """The 64-bit offset variant (used for buffers >= 4 GiB) gives bitwise the
+    same state as the 32-bit one; forced on a small lattice with posts."""
+    c = posts_case(lx=96, ly=48, seed=3)
+    runs = []
+    for force in ("0", "1"):
+        monkeypatch.setenv("TLB_FORCE_WIDE", force)
+        sim = Simulation(c["params"], c["rho_a"], c["rho_b"], c["temp"], solid=c["solid"],
+                         t_bottom=c["t_bottom"], precision="fp32")
+        sim.step(40)
+        runs.append((sim.populations(), sim.fields()))
+        sim.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    for k in runs[0][1]:
+        assert np.array_equal(runs[0][1][k], runs[1][1][k]), k
