@@ -351,3 +351,54 @@ def test_phase_separation_table_of_appendix_b():
         assert mn == pytest.approx(lo, rel=tol), (g_print, mn, lo)
         if g_print <= 0.10:
             assert (mx + mn) / 2 == pytest.approx(0.76015625, abs=1e-9)
+
+
+# Coexistence densities of the Appendix B two-layer run at G12 = 0.405 (the
+# A-rich and B-rich bulk values of both components after 5e4 steps; the A
+# values are the printed 0.40 row of the table).
+COEX = {"a_rich": (1.3646849643821768, 0.1595033825781161),
+        "b_rich": (0.1549724317210607, 1.370061227758187)}
+
+
+def _bulk_pressure(ra, rb, p):
+    """Bulk pressure of the implemented forces: ideal part plus the
+    non-ideal terms of the cross force (psi = rho/rho0, Eq. (8)) and of the
+    self forces (psi of Eq. (12)); both stencils have second moment c_s^2 I,
+    which gives the factors below (the cross-force form is Eq. (9))."""
+    ps = lambda r: p.rho0 * (1 - np.exp(-r / p.rho0))
+    return CS2 * (ra + rb) + CS2 * p.g12 * (ra / p.rho0) * (rb / p.rho0) + 0.5 * CS2 * (
+        (p.g_a[0] + p.g_r[0]) * ps(ra) ** 2 + (p.g_a[1] + p.g_r[1]) * ps(rb) ** 2)
+
+
+def _laplace_run(R, L=64, steps=8000):
+    p = _params(alpha_g=0.0)
+    inside = workloads.single_droplet(L, L, R)["rho_a"] > 1
+    ra = np.where(inside, *[COEX["a_rich"][0], COEX["b_rich"][0]])
+    rb = np.where(inside, *[COEX["a_rich"][1], COEX["b_rich"][1]])
+    o = Oracle(p, ra, rb, np.zeros((L, L)), periodic_y=True).step(steps)
+    f = o.fields()
+    c = L // 2
+    a_in, b_in = f["rho_a"][c - 1:c + 1, c - 1:c + 1].mean(), f["rho_b"][c - 1:c + 1, c - 1:c + 1].mean()
+    a_out, b_out = f["rho_a"][0, 0], f["rho_b"][0, 0]
+    dp = _bulk_pressure(a_in, b_in, p) - _bulk_pressure(a_out, b_out, p)
+    # equimolar radius of the (slowly dissolving) droplet
+    r_eff = np.sqrt(((f["rho_a"] - a_out) / (a_in - a_out)).sum() / np.pi)
+    return r_eff, dp
+
+
+@pytest.mark.slow
+def test_laplace_law_single_droplet():
+    """Single droplet in a periodic 64 x 64 box, no buoyancy, 8000 steps from
+    the coexistence densities: the bulk pressure jump is linear in 1/R
+    (Laplace law in 2D, Delta p = sigma / R) with R^2 >= 0.999 and an
+    intercept below 5% of the largest jump."""
+    with ThreadPoolExecutor(max_workers=min(5, os.cpu_count() or 1)) as ex:
+        res = list(ex.map(_laplace_run, [8.0, 10.0, 12.0, 14.0, 16.0]))
+    x = np.array([1 / r for r, _ in res])
+    y = np.array([dp for _, dp in res])
+    A = np.vstack([x, np.ones_like(x)]).T
+    (sigma, icpt), *_ = np.linalg.lstsq(A, y, rcond=None)
+    r2 = 1 - ((y - A @ [sigma, icpt]) ** 2).sum() / ((y - y.mean()) ** 2).sum()
+    assert sigma > 0
+    assert r2 >= 0.999, (r2, res)
+    assert abs(icpt) <= 0.05 * y.max(), (icpt, y.max())
