@@ -30,7 +30,7 @@ METRIC = "MLUPS and % HBM roofline (FP32 vs FP16-storage); adjoint/forward time 
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per node update: the 27 populations read once and
 # written once, plus one byte of solid flag when the lattice has solid cells.
-BYTES_PER_POP = {"fp64": 8, "fp32": 4}
+BYTES_PER_POP = {"fp64": 8, "fp32": 4, "fp16dev": 2, "bf16dev": 2, "fix16dev": 2}
 KERNEL_SOURCES = ("paper_2109_12565_amd/csrc/lb_kernels.hpp", "paper_2109_12565_amd/csrc/tlb.hip")
 
 
@@ -56,7 +56,7 @@ def measured_traffic(workload: str, precision: str):
 
 
 def cpu_baseline(w: dict, sample_steps: int) -> dict:
-    """FP64 oracle (single-threaded C) on the full lattice of the workload
+    """FP64 oracle (C, OpenMP over rows) on the full lattice of the workload
     for a few steps; MLUPS over the step loop only."""
     from oracle.oracle import ModelParams, Oracle
 
@@ -66,9 +66,52 @@ def cpu_baseline(w: dict, sample_steps: int) -> dict:
     ora.step(sample_steps)
     dt = time.perf_counter() - t0
     lups = w["lx"] * w["ly"] * sample_steps
-    return {"value": lups / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+    return {"value": lups / dt / 1e6, "unit": "MLUPS", "cores": ora.threads, "kind": "oracle",
             "sample": f"{sample_steps} steps of the full {w['lx']}x{w['ly']} lattice, FP64, "
                       f"{dt:.1f} s"}
+
+
+def precision_study(steps: int, every: int, storages) -> dict:
+    """Errors of each storage against the FP64 oracle on the 512x256 crop of
+    the large recipe: max relative error of rho_A, rho_B, T (over max|field|)
+    and of u^H (over the largest oracle velocity) after `steps` steps, the
+    relative error of the time-averaged Nusselt number (sampled every
+    `every` steps), and the per-component mass drift."""
+    from oracle.oracle import ModelParams, Oracle
+    from paper_2109_12565_amd import Simulation
+
+    w = workloads.crop()
+    ora = Oracle(ModelParams(**w["params"]), w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+                 t_bottom=w["t_bottom"])
+    sims = {pr: Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+                           t_bottom=w["t_bottom"], precision=pr) for pr in storages}
+    nu = {k: [] for k in ["oracle", *storages]}
+    m0 = {pr: s.observables() for pr, s in sims.items()}
+    t0 = time.perf_counter()
+    for t in range(every, steps + 1, every):
+        ora.step(every)
+        nu["oracle"].append(ora.observables()["nu"])
+        for pr, sim in sims.items():
+            sim.step(every)
+            nu[pr].append(sim.observables()["nu"])
+    ref = ora.fields()
+    umax = max(np.abs(ref["ux"]).max(), np.abs(ref["uy"]).max())
+    nu_ref = float(np.mean(nu["oracle"]))
+    out = {"study": "precision", "workload": w["name"], "steps": steps, "nu_every": every,
+           "oracle_threads": ora.threads, "nu_mean_oracle": nu_ref, "storages": {}}
+    for pr, sim in sims.items():
+        f = sim.fields()
+        obs = sim.observables()
+        e = {k: float(np.abs(f[k] - ref[k]).max() / np.abs(ref[k]).max())
+             for k in ("rho_a", "rho_b", "temp")}
+        e["u"] = float(max(np.abs(f["ux"] - ref["ux"]).max(), np.abs(f["uy"] - ref["uy"]).max()) / umax)
+        e["nu_mean"] = float(np.mean(nu[pr]))
+        e["nu_mean_rel_err"] = abs(e["nu_mean"] - nu_ref) / abs(nu_ref)
+        e["mass_a_drift"] = (obs["mass_a"] - m0[pr]["mass_a"]) / m0[pr]["mass_a"]
+        e["mass_b_drift"] = (obs["mass_b"] - m0[pr]["mass_b"]) / m0[pr]["mass_b"]
+        out["storages"][pr] = e
+    out["wall_s"] = round(time.perf_counter() - t0, 1)
+    return out
 
 
 def main() -> int:
@@ -80,6 +123,9 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=sorted(BYTES_PER_POP))
     ap.add_argument("--cpu-steps", type=int, default=2,
                     help="oracle steps for the CPU baseline (0 to skip)")
+    ap.add_argument("--study", choices=["precision"], default=None,
+                    help="instead of the benchmark, print the precision study (storages vs the "
+                         "FP64 oracle on the 512x256 crop)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before warmup, run 3 plain device copies of this many MiB (a known "
                          "traffic reference for hardware counters)")
@@ -96,6 +142,10 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.study == "precision":
+        print(json.dumps(precision_study(args.steps, 50, ["fp32", "fp16dev", "bf16dev", "fix16dev"])),
+              flush=True)
+        return 0
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib << 20
         src = torch.ones(n, dtype=torch.uint8, device="cuda")
@@ -145,7 +195,9 @@ def main() -> int:
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total_ms / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64"}[args.precision], "data": "synthetic",
+        "dtype": {"fp32": "f32", "fp64": "f64", "fp16dev": "f16-storage/f32",
+                  "bf16dev": "bf16-storage/f32", "fix16dev": "i16-storage/f32"}[args.precision],
+        "data": "synthetic",
         "config": {"workload": w["name"], "lx": w["lx"], "ly": w["ly"], "storage": args.precision,
                    "droplets": int(w["n_droplets"]), "solid_cells": 0 if w["solid"] is None
                    else int((w["solid"] != 0).sum()), "observables": "once at the end",

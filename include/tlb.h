@@ -54,10 +54,20 @@ enum tlb_status {
 };
 
 /* Storage type of the populations in device memory. Collisions are computed
- * in FP64 for TLB_FP64 and in FP32 otherwise. */
+ * in FP64 for TLB_FP64 and in FP32 otherwise. The 16-bit forms store each
+ * population as its deviation from a fixed reference: f_{l,i} - w_i
+ * rho_ref[l] for the fluid components and g_i - w_i t_ref for the
+ * temperature (halving the bytes moved per step).
+ *   TLB_FP16_DEV, TLB_BF16_DEV: floating point, round to nearest even.
+ *   TLB_FIX16_DEV: fixed point in units of 2^-15, deviations in [-1, 1)
+ *     (saturating outside); the rest population takes the exact remainder
+ *     of the stored sum, so each component's mass is conserved exactly. */
 enum tlb_precision {
   TLB_FP64 = 0,
-  TLB_FP32 = 1
+  TLB_FP32 = 1,
+  TLB_FP16_DEV = 2,   /* IEEE binary16 deviations */
+  TLB_BF16_DEV = 3,   /* bfloat16 deviations */
+  TLB_FIX16_DEV = 4   /* 16-bit fixed-point deviations */
 };
 
 /* Model constants (Sec. 2; values of Appendix A in parentheses). */
@@ -76,6 +86,8 @@ typedef struct tlb_params {
   double rho_wall[2];    /* wetting densities of both components at solid
                             nodes (Sec. 2.2.1) (0.612, 0.612) */
   double dt_nominal;     /* Delta T in the Nusselt normalisation, != 0 */
+  double rho_ref[2];     /* reference densities of the 16-bit storages */
+  double t_ref;          /* reference temperature of the 16-bit storages */
 } tlb_params;
 
 /* Observables at time `step` (Sec. 3.1, Sec. 3.3.2 Eq. (24)); sums and means

@@ -21,9 +21,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tlb_oracle.c")
 _LIB = os.path.join(_HERE, "libtlb_oracle.so")
 
-# Plain FP64: no contraction into FMA, no fast-math; OpenMP is not used so
-# the thread count can never change a result.
-CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+# Plain FP64: no contraction into FMA, no fast-math. Node loops are OpenMP
+# parallel; each node's update reads only the previous state, so results do
+# not depend on the thread count.
+CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
 
 
 def build(force: bool = False) -> str:
@@ -74,6 +75,9 @@ def _load():
         lib.ora_post_collision.argtypes = [ctypes.c_void_p, dp, dp, dp]
         lib.ora_observables.argtypes = [ctypes.c_void_p, dp]
         lib.ora_load_post_collision.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.c_int64]
+        lib.ora_threads.restype = ctypes.c_int
+        lib.ora_threads.argtypes = [ctypes.c_void_p]
+        lib.ora_set_threads.argtypes = [ctypes.c_void_p, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -101,11 +105,12 @@ class ModelParams:
 OBS_NAMES = ("mass_a", "mass_b", "sum_t", "nu", "nu_top", "ke")
 
 
+
 class Oracle:
     """One oracle run: a lattice state advanced step by step in FP64."""
 
     def __init__(self, params: ModelParams, rho_a, rho_b, temp, *, solid=None,
-                 t_bottom=None, ux0=None, uy0=None, periodic_y=False):
+                 t_bottom=None, ux0=None, uy0=None, periodic_y=False, threads=None):
         rho_a = np.ascontiguousarray(rho_a, dtype=np.float64)
         ly, lx = rho_a.shape
         self.shape = (ly, lx)
@@ -135,6 +140,8 @@ class Oracle:
                                  _dp(t_bottom))
         if not self._h:
             raise MemoryError("oracle state allocation failed")
+        if threads is not None:
+            lib.ora_set_threads(self._h, int(threads))
         self._keep = (solid, t_bottom)
 
     def __del__(self):
@@ -142,6 +149,11 @@ class Oracle:
         if h:
             _load().ora_destroy(h)
             self._h = None
+
+    @property
+    def threads(self) -> int:
+        """Threads of the parallel node loops (results do not depend on it)."""
+        return int(_load().ora_threads(self._h))
 
     @property
     def t(self) -> int:

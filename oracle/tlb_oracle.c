@@ -28,6 +28,10 @@
  *                  (Sec. 2.2) for f, and by anti-bounce-back holding the
  *                  wall temperature for g.
  *
+ * Node loops run in parallel with OpenMP: every node's update depends only
+ * on the previous state, so the thread count never changes a result; the
+ * observable sums are serial, in row-major order.
+ *
  * The state kept between steps is the pre-collision populations f(t), g(t);
  * streaming is done in push form (collide, then move), which is the same
  * arithmetic as the GPU's pull form reached by a different route.
@@ -52,6 +56,9 @@
  * paper's printed phase-separation table of Appendix B).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -109,6 +116,7 @@ typedef struct ora_params {
 typedef struct ora_state {
   ora_params p;
   int64_t t;
+  int nthreads;          /* threads of the parallel node loops */
   int n;                 /* lx * ly */
   double *f[2];          /* [9][n] pre-collision, per component */
   double *g;             /* [9][n] */
@@ -149,12 +157,21 @@ static double wall_temperature(const ora_state *s, int x, int y) {
   return fl == 1 ? s->t_bottom[wrapx(s, x)] : s->p.t_top;
 }
 
+static int ora_default_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 static double psi_exp(const ora_state *s, double rho) {
   return s->p.rho0 * (1.0 - exp(-rho / s->p.rho0));
 }
 
 /* Step 1: moments of the pre-collision populations at fluid nodes. */
 static void moments(ora_state *s) {
+#pragma omp parallel for schedule(static) num_threads(s->nthreads)
   for (int k = 0; k < s->n; ++k) {
     double ra = 0, rb = 0, jx = 0, jy = 0, tt = 0;
     for (int i = 0; i < 9; ++i) {
@@ -177,6 +194,7 @@ static void moments(ora_state *s) {
  * yy = y + 2 of the padded grid. */
 static void pseudopotentials(ora_state *s) {
   int lx = s->p.lx, ly = s->p.ly;
+#pragma omp parallel for schedule(static) num_threads(s->nthreads)
   for (int yy = 0; yy < ly + 4; ++yy) {
     int y = yy - 2;
     for (int x = 0; x < lx; ++x) {
@@ -206,6 +224,7 @@ static double padded(const ora_state *s, const double *a, int x, int y) {
 /* Step 3: forces on each component at fluid nodes. */
 static void forces(ora_state *s) {
   int lx = s->p.lx, ly = s->p.ly;
+#pragma omp parallel for schedule(static) num_threads(s->nthreads)
   for (int y = 0; y < ly; ++y) {
     for (int x = 0; x < lx; ++x) {
       int k = y * lx + x;
@@ -279,6 +298,7 @@ static void hydro_velocity(const ora_state *s, int k, double *ux, double *uy) {
  * solid nodes get zeros). */
 static void collide(ora_state *s) {
   double tau = s->p.tau, tau_g = s->p.tau_g;
+#pragma omp parallel for schedule(static) num_threads(s->nthreads)
   for (int k = 0; k < s->n; ++k) {
     if (s->solid[k]) {
       for (int i = 0; i < 9; ++i) {
@@ -315,6 +335,8 @@ static void stream(ora_state *s) {
   memset(s->fn[0], 0, sizeof(double) * 9 * n);
   memset(s->fn[1], 0, sizeof(double) * 9 * n);
   memset(s->gn, 0, sizeof(double) * 9 * n);
+  /* every (target node, direction) pair is written exactly once */
+#pragma omp parallel for schedule(static) num_threads(s->nthreads)
   for (int y = 0; y < ly; ++y) {
     for (int x = 0; x < lx; ++x) {
       int k = y * lx + x;
@@ -382,6 +404,7 @@ ora_state *ora_create(const ora_params *p, const double *rho_a,
   ora_state *s = (ora_state *)calloc(1, sizeof(ora_state));
   if (!s) return NULL;
   s->p = *p;
+  s->nthreads = ora_default_threads();
   int n = p->lx * p->ly;
   s->n = n;
   size_t pad = (size_t)(p->ly + 4) * p->lx;
@@ -540,3 +563,7 @@ void ora_load_post_collision(ora_state *s, const double *fa, const double *fb,
   stream(s);
   s->t = t;
 }
+
+/* Threads of a state's parallel node loops (n >= 1). */
+void ora_set_threads(ora_state *s, int n) { s->nthreads = n < 1 ? 1 : n; }
+int ora_threads(const ora_state *s) { return s->nthreads; }

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libtlb.so")
 
 TLB_OK, TLB_EINVAL, TLB_ENOMEM, TLB_EDEVICE, TLB_ENUMERIC, TLB_ESTATE = 0, -1, -2, -3, -4, -5
-PRECISIONS = {"fp64": 0, "fp32": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16dev": 2, "bf16dev": 3, "fix16dev": 4}
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = (
@@ -41,6 +41,7 @@ class Params(ctypes.Structure):
         ("g_a", ctypes.c_double * 2), ("g_r", ctypes.c_double * 2),
         ("alpha_g", ctypes.c_double), ("t_top", ctypes.c_double),
         ("rho_wall", ctypes.c_double * 2), ("dt_nominal", ctypes.c_double),
+        ("rho_ref", ctypes.c_double * 2), ("t_ref", ctypes.c_double),
     ]
 
 
@@ -116,7 +117,9 @@ class Simulation:
     """A lattice state on the GPU behind one ``tlb_handle``.
 
     ``params`` holds the model constants named as in ``tlb_params`` (tau,
-    tau_g, rho0, g12, g_a, g_r, alpha_g, t_top, rho_wall, dt_nominal).
+    tau_g, rho0, g12, g_a, g_r, alpha_g, t_top, rho_wall, dt_nominal, and
+    optionally rho_ref, t_ref for the 16-bit storages: by default rho0 for
+    both components and the mean of the two wall temperatures).
     Field arrays are (ly, lx) with x fastest. By default the work runs on
     torch's current stream.
     """
@@ -155,6 +158,9 @@ class Simulation:
         p.alpha_g, p.t_top = params["alpha_g"], params["t_top"]
         p.rho_wall[0], p.rho_wall[1] = params["rho_wall"]
         p.dt_nominal = params["dt_nominal"]
+        rr = params.get("rho_ref", (params["rho0"], params["rho0"]))
+        p.rho_ref[0], p.rho_ref[1] = rr
+        p.t_ref = params.get("t_ref", 0.5 * (float(np.mean(t_bottom)) + params["t_top"]))
         self.params = p
         self.precision = precision
         s = _current_stream() if stream == "torch" else stream

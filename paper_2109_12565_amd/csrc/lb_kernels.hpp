@@ -87,13 +87,68 @@ constexpr uint32_t kFromBelow = (1u << 2) | (1u << 5) | (1u << 6);
 constexpr uint32_t kFromAbove = (1u << 4) | (1u << 7) | (1u << 8);
 
 // ---------------------------------------------------------------- storage
+// Storage policies: T is the stored type, C the compute type. The kernel
+// works on values in stored form: the population itself (kDev = false) or
+// its deviation from the reference w_i * ref (kDev = true). grid() maps a
+// stored-form value onto the representable grid when the format is fixed
+// point (kFix), where sums of stored values are exact. Stores are
+// non-temporal: the next step reads the populations from HBM anyway.
 template <typename T_> struct Store {
   using T = T_;
   using C = T_;
+  static constexpr bool kDev = false;
+  static constexpr bool kFix = false;
   __device__ static C load(const T* p) { return *p; }
-  // The next step reads the stored populations from HBM anyway: stream them
-  // past the caches.
   __device__ static void store(T* p, C v) { __builtin_nontemporal_store(v, p); }
+  __device__ static C grid(C v) { return v; }
+};
+
+// 16-bit floating-point deviations, converted with round-to-nearest-even.
+struct StoreF16Dev {
+  using T = uint16_t;
+  using C = float;
+  static constexpr bool kDev = true;
+  static constexpr bool kFix = false;
+  __device__ static C grid(C v) { return v; }
+  __device__ static C load(const T* p) { return (float)__builtin_bit_cast(_Float16, *p); }
+  __device__ static void store(T* p, C v) {
+    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, (_Float16)v), p);
+  }
+};
+
+struct StoreBF16Dev {
+  using T = uint16_t;
+  using C = float;
+  static constexpr bool kDev = true;
+  static constexpr bool kFix = false;
+  __device__ static C grid(C v) { return v; }
+  __device__ static C load(const T* p) { return __uint_as_float((uint32_t)*p << 16); }
+  __device__ static void store(T* p, C v) {
+    uint32_t u = __float_as_uint(v);
+    const bool nan = (u & 0x7fffffffu) > 0x7f800000u;
+    u += 0x7fffu + ((u >> 16) & 1u);  // round half to even on the dropped 16 bits
+    __builtin_nontemporal_store((uint16_t)(nan ? (__float_as_uint(v) >> 16) | 0x40u : u >> 16), p);
+  }
+};
+
+// 16-bit fixed-point deviations in units of 2^-15 (range [-1, 1)). Every
+// stored-form value is a multiple of the unit, so sums of up to 2^8 of them
+// are exact in FP32: the collision sets the rest population to the exact
+// remainder and each component's mass is conserved exactly.
+struct StoreFix16Dev {
+  using T = int16_t;
+  using C = float;
+  static constexpr bool kDev = true;
+  static constexpr bool kFix = true;
+  static constexpr float kScale = 32768.0f;
+  __device__ static C load(const T* p) { return (float)*p * (1.0f / kScale); }
+  __device__ static C grid(C v) {
+    const float q = fminf(fmaxf(rintf(v * kScale), -32768.0f), 32767.0f);
+    return q * (1.0f / kScale);
+  }
+  __device__ static void store(T* p, C v) {
+    __builtin_nontemporal_store((int16_t)(int)(v * kScale), p);  // v is on the grid
+  }
 };
 
 // ---------------------------------------------------------------- arguments
@@ -111,6 +166,7 @@ struct StepArgs {
   C inv_tau, inv_tau_g, tau, rho0, inv_rho0, g12;
   C ga0, ga1, gr0, gr1;
   C alpha_g, t_top, rho_wall0, rho_wall1;
+  C ref_a, ref_b, ref_t;    // references of the 16-bit deviation storages
 };
 
 // Kernel variants.
@@ -213,7 +269,9 @@ __device__ inline C source_wall_temperature(const StepArgs<C>& a, int x, int r) 
   return a.t_top;
 }
 
-// Pull f_A (f[0..8]) and f_B (f[9..17]) at fluid node n.
+// Pull f_A (f[0..8]) and f_B (f[9..17]) at fluid node n, in stored form.
+// Opposite directions have equal weights, so a bounced value keeps its
+// deviation reference.
 template <class St, unsigned kMode, typename C>
 __device__ inline void pull_fluid(const void* src, const NodeAddr<kMode>& n, uint32_t lm,
                                   Off<kMode> plane_b, Off<kMode> row_b, C (&f)[18]) {
@@ -229,8 +287,9 @@ __device__ inline void pull_fluid(const void* src, const NodeAddr<kMode>& n, uin
 #undef TLB_PULL_F
 }
 
-// Pull g at fluid node (x, r) with anti-bounce-back at solid sources:
-// g_i = -g*_{opp i}(x) + 2 w_i T_w.
+// Pull g at fluid node (x, r), in stored form, with anti-bounce-back at
+// solid sources: g_i = -g*_{opp i}(x) + 2 w_i T_w, i.e. in deviations from
+// w_i T_ref: d_i = -d*_{opp i} + 2 w_i (T_w - T_ref).
 template <class St, unsigned kMode, typename C>
 __device__ inline void pull_thermal(const StepArgs<C>& a, const void* src, const NodeAddr<kMode>& n,
                                     uint32_t lm, Off<kMode> plane_b, Off<kMode> row_b, int x, int r,
@@ -240,7 +299,11 @@ __device__ inline void pull_thermal(const StepArgs<C>& a, const void* src, const
   {                                                                                         \
     C v = ld<St, kMode>(src, pull_off<I, kMode>(n, lm, plane_b, row_b, plane18));           \
     if constexpr ((kMode & kModeInit) == 0 && I != 0) {                                     \
-      if ((lm >> I) & 1u) v = C(2) * w_dir<C>(I) * source_wall_temperature<I, kMode>(a, x, r) - v; \
+      if ((lm >> I) & 1u) {                                                                 \
+        C tw = source_wall_temperature<I, kMode>(a, x, r);                                  \
+        if constexpr (St::kDev) tw -= a.ref_t;                                              \
+        v = St::grid(C(2) * w_dir<C>(I) * tw - v);                                          \
+      }                                                                                     \
     }                                                                                       \
     g[I] = v;                                                                               \
   }
@@ -272,7 +335,9 @@ __device__ inline C neighbour_temperature(const StepArgs<C>& a, const void* src,
   const NodeAddr<kMode> n = node_addr<St, kMode>(x, r, a.lx, row_b);
   C g[9];
   pull_thermal<St, kMode>(a, src, n, lm, plane_b, row_b, x, r, g);
-  return sum9(g);
+  C t = sum9(g);
+  if constexpr (St::kDev) t += a.ref_t;
+  return t;
 }
 
 // ---------------------------------------------------------------- kernel
@@ -332,6 +397,10 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
         pull_fluid<St, kMode>(src, n, lm, plane_b, row_b, f);
         ra = sum9(f);
         rb = sum9(f + 9);
+        if constexpr (St::kDev) {
+          ra += a.ref_a;
+          rb += a.ref_b;
+        }
         pa = psi_exp(ra, a.rho0, a.inv_rho0);
         pb = psi_exp(rb, a.rho0, a.inv_rho0);
       }
@@ -376,14 +445,22 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
     // ---- moments
     const C* fa = fu;
     const C* fb = fu + 9;
-    const C ra = sum9(fa), rb = sum9(fb);
+    // stored-form sums (exact for the fixed-point storage) and densities
+    const C Da = sum9(fa), Db = sum9(fb);
+    C ra = Da, rb = Db;
+    if constexpr (St::kDev) {
+      ra += a.ref_a;
+      rb += a.ref_b;
+    }
     const C jx = ((fa[1] - fa[3]) + (fa[5] - fa[7]) + (fa[8] - fa[6])) +
                  ((fb[1] - fb[3]) + (fb[5] - fb[7]) + (fb[8] - fb[6]));
     const C jy = ((fa[2] - fa[4]) + (fa[5] - fa[7]) + (fa[6] - fa[8])) +
                  ((fb[2] - fb[4]) + (fb[5] - fb[7]) + (fb[6] - fb[8]));
     C g[9];
     pull_thermal<St, kMode>(a, src, n, lu, plane_b, row_b, xw, y, g);
-    const C temp = sum9(g);
+    const C Dt = sum9(g);
+    C temp = Dt;
+    if constexpr (St::kDev) temp += a.ref_t;
 
     // ---- forces from the ring (rows y-2..y+2 are slots k-4..k)
     const int s0 = tid + 2;
@@ -461,11 +538,12 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
       const C ua2 = uax * uax + uay * uay;
       const C ub2 = ubx * ubx + uby * uby;
       const C uh2 = hx * hx + hy * hy;
-      // BGK relaxation written as f^eq + (1 - 1/tau)(f - f^eq): exactly f^eq
-      // at tau = 1. The rest population's equilibrium is the zeroth moment
-      // minus the other eight, so the stored populations sum to rho (and T)
-      // up to unbiased rounding: the weights rounded to the storage type do
-      // not sum to 1 and would otherwise create mass at every collision.
+      // BGK relaxation written as f^eq + (1 - 1/tau)(f - f^eq) in stored
+      // form (exactly f^eq at tau = 1). The rest population takes the
+      // remainder of the zeroth moment, so the stored populations sum to
+      // rho (and T) up to unbiased rounding (exactly for fixed point): the
+      // weights rounded to the storage type do not sum to 1 and would
+      // otherwise create or destroy mass at every collision.
       const C ka = C(1) - a.inv_tau, kg = C(1) - a.inv_tau_g;
       C sa = 0, sb = 0, sg = 0;
       const O p9 = plane_b * 9, p18 = plane_b * 18;
@@ -476,45 +554,68 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
     const C cua = C(cx) * uax + C(cy) * uay;                                           \
     const C cub = C(cx) * ubx + C(cy) * uby;                                           \
     const C cuh = C(cx) * hx + C(cy) * hy;                                             \
-    const C ea = w * ra * (C(1) + C(3) * cua + C(4.5) * cua * cua - C(1.5) * ua2);     \
-    const C eb = w * rb * (C(1) + C(3) * cub + C(4.5) * cub * cub - C(1.5) * ub2);     \
-    const C eg = w * temp * (C(1) + C(3) * cuh + C(4.5) * cuh * cuh - C(1.5) * uh2);   \
-    sa += ea;                                                                          \
-    sb += eb;                                                                          \
-    sg += eg;                                                                          \
+    C ea = w * ra * (C(1) + C(3) * cua + C(4.5) * cua * cua - C(1.5) * ua2);           \
+    C eb = w * rb * (C(1) + C(3) * cub + C(4.5) * cub * cub - C(1.5) * ub2);           \
+    C eg = w * temp * (C(1) + C(3) * cuh + C(4.5) * cuh * cuh - C(1.5) * uh2);         \
+    if constexpr (St::kDev) {                                                          \
+      ea -= w * a.ref_a;                                                               \
+      eb -= w * a.ref_b;                                                               \
+      eg -= w * a.ref_t;                                                               \
+    }                                                                                  \
+    const C qa = St::grid(ea + ka * (fa[I] - ea));                                     \
+    const C qb = St::grid(eb + ka * (fb[I] - eb));                                     \
+    const C qg = St::grid(eg + kg * (g[I] - eg));                                      \
+    if constexpr (St::kFix) {                                                          \
+      sa += qa;                                                                        \
+      sb += qb;                                                                        \
+      sg += qg;                                                                        \
+    } else {                                                                           \
+      sa += ea;                                                                        \
+      sb += eb;                                                                        \
+      sg += eg;                                                                        \
+    }                                                                                  \
     const O o = (O)I * plane_b + n.own;                                                \
-    st<St, kMode>(dst, o, ea + ka * (fa[I] - ea));                                     \
-    st<St, kMode>(dst, o + p9, eb + ka * (fb[I] - eb));                                \
-    st<St, kMode>(dst, o + p18, eg + kg * (g[I] - eg));                                \
+    st<St, kMode>(dst, o, qa);                                                         \
+    st<St, kMode>(dst, o + p9, qb);                                                    \
+    st<St, kMode>(dst, o + p18, qg);                                                   \
   }
       TLB_COLLIDE(1) TLB_COLLIDE(2) TLB_COLLIDE(3) TLB_COLLIDE(4)
       TLB_COLLIDE(5) TLB_COLLIDE(6) TLB_COLLIDE(7) TLB_COLLIDE(8)
 #undef TLB_COLLIDE
-      {
-        const C ea = ra - sa, eb = rb - sb, eg = temp - sg;
+      if constexpr (St::kFix) {
+        // exact remainders: the stored populations sum to the pulled ones
+        st<St, kMode>(dst, n.own, St::grid(Da - sa));
+        st<St, kMode>(dst, n.own + p9, St::grid(Db - sb));
+        st<St, kMode>(dst, n.own + p18, St::grid(Dt - sg));
+      } else {
+        const C ea = Da - sa, eb = Db - sb, eg = Dt - sg;
         st<St, kMode>(dst, n.own, ea + ka * (fa[0] - ea));
         st<St, kMode>(dst, n.own + p9, eb + ka * (fb[0] - eb));
         st<St, kMode>(dst, n.own + p18, eg + kg * (g[0] - eg));
       }
     }
+    // FP64 densities for output: reference plus the stored-form sum
+    const double dra = St::kDev ? (double)a.ref_a + (double)Da : (double)ra;
+    const double drb = St::kDev ? (double)a.ref_b + (double)Db : (double)rb;
+    const double dtt = St::kDev ? (double)a.ref_t + (double)Dt : (double)temp;
     if constexpr ((kMode & kModeFields) != 0) {
       const size_t nn = (size_t)lx * ly, q = (size_t)y * lx + xo;
-      a.fields[q] = (double)ra;
-      a.fields[nn + q] = (double)rb;
+      a.fields[q] = dra;
+      a.fields[nn + q] = drb;
       a.fields[2 * nn + q] = (double)hx;
       a.fields[3 * nn + q] = (double)hy;
-      a.fields[4 * nn + q] = (double)temp;
+      a.fields[4 * nn + q] = dtt;
     }
     if constexpr ((kMode & kModeObserve) != 0) {
       const C tn = neighbour_temperature<St, kMode>(a, src, xw, y + 1, temp, plane_b, row_b);
       const C ts = neighbour_temperature<St, kMode>(a, src, xw, y - 1, temp, plane_b, row_b);
-      acc[0] += (double)ra;
-      acc[1] += (double)rb;
-      acc[2] += (double)temp;
-      acc[3] += (double)hy * (double)temp;
+      acc[0] += dra;
+      acc[1] += drb;
+      acc[2] += dtt;
+      acc[3] += (double)hy * dtt;
       acc[4] += 0.5 * ((double)tn - (double)ts);
       acc[5] += (double)hx * (double)hx + (double)hy * (double)hy;
-      if (y == ly - 1) acc[6] += (double)temp - (double)a.t_top;
+      if (y == ly - 1) acc[6] += dtt - (double)a.t_top;
     }
   };
 
@@ -590,8 +691,10 @@ __global__ __launch_bounds__(256) void lb_init_equilibrium(
     typename St::T* __restrict__ buf, const double* __restrict__ rho_a,
     const double* __restrict__ rho_b, const double* __restrict__ temp,
     const double* __restrict__ ux0, const double* __restrict__ uy0,
-    const uint8_t* __restrict__ solid, int lx, int ly, int pitch, long long pop_stride) {
+    const uint8_t* __restrict__ solid, int lx, int ly, int pitch, long long pop_stride,
+    typename St::C ref_a, typename St::C ref_b, typename St::C ref_t) {
   using C = typename St::C;
+  const C ref[3] = {St::kDev ? ref_a : C(0), St::kDev ? ref_b : C(0), St::kDev ? ref_t : C(0)};
   const int x = blockIdx.x * 256 + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= lx) return;
@@ -609,27 +712,36 @@ __global__ __launch_bounds__(256) void lb_init_equilibrium(
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
       const C v = dens[s] * shape;
-      sum[s] += v;
-      St::store(buf + (long long)(i + 9 * s) * pop_stride + off, is_solid ? C(0) : v);
+      const C d = St::grid(v - w_dir<C>(i) * ref[s]);   // stored form
+      sum[s] += St::kFix ? d : v;
+      St::store(buf + (long long)(i + 9 * s) * pop_stride + off, is_solid ? C(0) : d);
     }
   }
   // rest population: zeroth moment minus the other eight (exact mass)
 #pragma unroll
-  for (int s = 0; s < 3; ++s)
-    St::store(buf + (long long)(9 * s) * pop_stride + off, is_solid ? C(0) : dens[s] - sum[s]);
+  for (int s = 0; s < 3; ++s) {
+    const C d = St::kFix ? St::grid(St::grid(dens[s] - ref[s]) - sum[s])
+                         : (dens[s] - sum[s]) - w_dir<C>(0) * ref[s];
+    St::store(buf + (long long)(9 * s) * pop_stride + off, is_solid ? C(0) : d);
+  }
 }
 
-// Copy populations out as doubles [27][ly][lx] (drops the row padding).
+// Copy populations out as doubles [27][ly][lx] (drops the row padding, adds
+// the deviation references back, zero at solid nodes).
 template <class St>
 __global__ __launch_bounds__(256) void lb_export_populations(
-    const typename St::T* __restrict__ buf, double* __restrict__ out, int lx, int ly, int pitch,
-    long long pop_stride) {
+    const typename St::T* __restrict__ buf, double* __restrict__ out,
+    const uint8_t* __restrict__ solid, int lx, int ly, int pitch, long long pop_stride,
+    typename St::C ref_a, typename St::C ref_b, typename St::C ref_t) {
   const int x = blockIdx.x * 256 + threadIdx.x;
   const int y = blockIdx.y;
   const int p = blockIdx.z;
   if (x >= lx) return;
-  out[((size_t)p * ly + y) * lx + x] =
-      (double)St::load(buf + p * pop_stride + (long long)y * pitch + x);
+  double v = (double)St::load(buf + p * pop_stride + (long long)y * pitch + x);
+  if constexpr (St::kDev)
+    v += w_dir<double>(p % 9) * (double)(p < 9 ? ref_a : (p < 18 ? ref_b : ref_t));
+  if (solid[(size_t)y * lx + x] != 0) v = 0.0;
+  out[((size_t)p * ly + y) * lx + x] = v;
 }
 
 }  // namespace tlbk

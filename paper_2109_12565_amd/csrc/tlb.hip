@@ -69,6 +69,22 @@ int fail(tlb_handle* h, int code, const char* fmt, ...) {
 
 bool is_fp64(const tlb_handle* h) { return h->p.precision == TLB_FP64; }
 
+size_t storage_bytes(int precision) {
+  return precision == TLB_FP64 ? sizeof(double) : (precision == TLB_FP32 ? sizeof(float) : 2);
+}
+
+// Call f with a value of the storage policy type of the handle's precision.
+template <class F>
+void with_storage(int precision, F&& f) {
+  switch (precision) {
+    case TLB_FP64: f(tlbk::Store<double>{}); break;
+    case TLB_FP32: f(tlbk::Store<float>{}); break;
+    case TLB_FP16_DEV: f(tlbk::StoreF16Dev{}); break;
+    case TLB_BF16_DEV: f(tlbk::StoreBF16Dev{}); break;
+    default: f(tlbk::StoreFix16Dev{}); break;
+  }
+}
+
 // Launch geometry: 256-wide strips for wide lattices, 64-wide otherwise; the
 // rows per block are chosen so that the grid fills the GPU's resident block
 // slots about once (the occupancy of the kernel that will run), within
@@ -106,8 +122,10 @@ Launch choose_launch(const tlb_params& p, size_t buffer_bytes, bool solid) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int per_cu = p.precision == TLB_FP64 ? step_blocks_per_cu<tlbk::Store<double>>(l.bx, l.wide, solid)
-                                             : step_blocks_per_cu<tlbk::Store<float>>(l.bx, l.wide, solid);
+  int per_cu = 1;
+  with_storage(p.precision, [&](auto st) {
+    per_cu = step_blocks_per_cu<decltype(st)>(l.bx, l.wide, solid);
+  });
   const long long slots = (long long)cus * per_cu;
   const long long strips = (lx + l.bx - 1) / l.bx;
   long long rows = (ly * strips + slots - 1) / slots;
@@ -152,6 +170,9 @@ tlbk::StepArgs<C> make_args(const tlb_handle* h, const void* src, void* dst) {
   a.t_top = C(p.t_top);
   a.rho_wall0 = C(p.rho_wall[0]);
   a.rho_wall1 = C(p.rho_wall[1]);
+  a.ref_a = C(p.rho_ref[0]);
+  a.ref_b = C(p.rho_ref[1]);
+  a.ref_t = C(p.t_ref);
   return a;
 }
 
@@ -179,8 +200,7 @@ void launch_mode(const tlb_handle* h, const void* src, void* dst) {
 
 template <unsigned kMode>
 void launch_any(const tlb_handle* h, const void* src, void* dst) {
-  if (is_fp64(h)) launch_mode<tlbk::Store<double>, kMode>(h, src, dst);
-  else launch_mode<tlbk::Store<float>, kMode>(h, src, dst);
+  with_storage(h->p.precision, [&](auto st) { launch_mode<decltype(st), kMode>(h, src, dst); });
 }
 
 // Re-run the step that produced f*(t) without storing, to evaluate the
@@ -210,8 +230,10 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
     return fail(nullptr, TLB_EINVAL, "tlb_init: NULL params or field array");
   if (p->lx < 1 || p->ly < 1 || (long long)p->lx * p->ly > (1LL << 30))
     return fail(nullptr, TLB_EINVAL, "tlb_init: bad lattice size %d x %d", p->lx, p->ly);
-  if (p->precision != TLB_FP64 && p->precision != TLB_FP32)
+  if (p->precision < TLB_FP64 || p->precision > TLB_FIX16_DEV)
     return fail(nullptr, TLB_EINVAL, "tlb_init: unknown precision %d", p->precision);
+  if (!std::isfinite(p->rho_ref[0]) || !std::isfinite(p->rho_ref[1]) || !std::isfinite(p->t_ref))
+    return fail(nullptr, TLB_EINVAL, "tlb_init: rho_ref and t_ref must be finite");
   if (!(p->tau > 0.5) || !(p->tau_g > 0.5) || !finite_positive(p->rho0) || !(p->dt_nominal != 0) ||
       !std::isfinite(p->dt_nominal))
     return fail(nullptr, TLB_EINVAL, "tlb_init: need tau > 1/2, tau_g > 1/2, rho0 > 0, dt_nominal != 0");
@@ -255,7 +277,7 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
 
   h->pitch = (lx + 63) / 64 * 64;
   h->pop_stride = (long long)h->pitch * ly;
-  h->elem = is_fp64(h) ? sizeof(double) : sizeof(float);
+  h->elem = storage_bytes(p->precision);
   h->launch = choose_launch(*p, (size_t)27 * h->pop_stride * h->elem, h->has_solid);
 
   int rc = TLB_OK;
@@ -293,7 +315,7 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
   const size_t nblocks = (size_t)h->launch.grid.x * h->launch.grid.y;
   INIT_HIP(hipMalloc(&h->partials, nblocks * 8 * sizeof(double)));
   INIT_HIP(hipMalloc(&h->obs, 8 * sizeof(double)));
-  INIT_HIP(hipMalloc(&h->t_bottom, lx * h->elem));
+  INIT_HIP(hipMalloc(&h->t_bottom, lx * (is_fp64(h) ? sizeof(double) : sizeof(float))));
   INIT_HIP(hipMalloc(&h->solid, n));
   INIT_HIP(hipMemcpyAsync(h->solid, sol.data(), n, hipMemcpyHostToDevice, h->stream));
   if (h->has_solid) {
@@ -318,14 +340,14 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
   dim3 g2((lx + 255) / 256, ly, 1);
   const double* dux = nf == 5 ? d_fields + 3 * n : nullptr;
   const double* duy = nf == 5 ? d_fields + 4 * n : nullptr;
-  if (is_fp64(h))
-    hipLaunchKernelGGL(tlbk::lb_init_equilibrium<tlbk::Store<double>>, g2, dim3(256), 0, h->stream,
-                       static_cast<double*>(h->buf[1]), d_fields, d_fields + n, d_fields + 2 * n,
-                       dux, duy, h->solid, lx, ly, h->pitch, h->pop_stride);
-  else
-    hipLaunchKernelGGL(tlbk::lb_init_equilibrium<tlbk::Store<float>>, g2, dim3(256), 0, h->stream,
-                       static_cast<float*>(h->buf[1]), d_fields, d_fields + n, d_fields + 2 * n,
-                       dux, duy, h->solid, lx, ly, h->pitch, h->pop_stride);
+  with_storage(p->precision, [&](auto st) {
+    using St = decltype(st);
+    using C = typename St::C;
+    hipLaunchKernelGGL(tlbk::lb_init_equilibrium<St>, g2, dim3(256), 0, h->stream,
+                       static_cast<typename St::T*>(h->buf[1]), d_fields, d_fields + n,
+                       d_fields + 2 * n, dux, duy, h->solid, lx, ly, h->pitch, h->pop_stride,
+                       C(p->rho_ref[0]), C(p->rho_ref[1]), C(p->t_ref));
+  });
   INIT_HIP(hipGetLastError());
   launch_any<tlbk::kModeInit | tlbk::kModeStore>(h, h->buf[1], h->buf[0]);
   INIT_HIP(hipGetLastError());
@@ -402,14 +424,14 @@ int tlb_get_populations(tlb_handle* h, double* out) {
   const size_t total = (size_t)27 * lx * ly;
   if (!h->export_buf) TLB_HIP(h, hipMalloc(&h->export_buf, total * sizeof(double)));
   dim3 g((lx + 255) / 256, ly, 27);
-  if (is_fp64(h))
-    hipLaunchKernelGGL(tlbk::lb_export_populations<tlbk::Store<double>>, g, dim3(256), 0, h->stream,
-                       static_cast<const double*>(h->buf[h->cur]), h->export_buf, lx, ly, h->pitch,
-                       h->pop_stride);
-  else
-    hipLaunchKernelGGL(tlbk::lb_export_populations<tlbk::Store<float>>, g, dim3(256), 0, h->stream,
-                       static_cast<const float*>(h->buf[h->cur]), h->export_buf, lx, ly, h->pitch,
-                       h->pop_stride);
+  with_storage(h->p.precision, [&](auto st) {
+    using St = decltype(st);
+    using C = typename St::C;
+    hipLaunchKernelGGL(tlbk::lb_export_populations<St>, g, dim3(256), 0, h->stream,
+                       static_cast<const typename St::T*>(h->buf[h->cur]), h->export_buf,
+                       h->solid, lx, ly, h->pitch, h->pop_stride, C(h->p.rho_ref[0]),
+                       C(h->p.rho_ref[1]), C(h->p.t_ref));
+  });
   TLB_HIP(h, hipGetLastError());
   TLB_HIP(h, hipMemcpyAsync(out, h->export_buf, total * sizeof(double), hipMemcpyDeviceToHost,
                             h->stream));

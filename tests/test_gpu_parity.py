@@ -239,3 +239,90 @@ def test_wide_offsets_match_narrow_bitwise(monkeypatch):
     assert np.array_equal(runs[0][0], runs[1][0])
     for k in runs[0][1]:
         assert np.array_equal(runs[0][1][k], runs[1][1][k]), k
+
+
+# ------------------------------------------------- 16-bit deviation storage
+
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def half_ulp(dev, mant_bits, min_exp):
+    """Half a unit in the last place of |dev| in a binary format with
+    `mant_bits` explicit mantissa bits and smallest normal exponent
+    `min_exp` (subnormals below it)."""
+    e = np.floor(np.log2(np.maximum(np.abs(dev), 2.0 ** min_exp)))
+    return 0.5 * 2.0 ** (e - mant_bits)
+
+
+FORMATS = {"fp16dev": (10, -14), "bf16dev": (7, -126), "fix16dev": None}
+FIX_UNIT = 2.0 ** -15
+
+
+@pytest.mark.parametrize("precision", sorted(FORMATS))
+def test_dev16_one_step_is_the_oracle_step_rounded_once(precision):
+    """From the GPU's own 16-bit state (decoded exactly), one GPU step equals
+    the oracle's FP64 step up to one round-to-nearest of each stored
+    deviation (half an ulp of the floating formats; half a unit of the
+    fixed-point one, whose rest population absorbs the other eight roundings:
+    4 units) plus FP32 arithmetic; the fields of the streamed state agree to
+    FP32 arithmetic."""
+    w = workloads.crop(steps=0)
+    p = w["params"]
+    sim = Simulation(p, w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+                     t_bottom=w["t_bottom"], precision=precision)
+    sim.step(20)
+    state = sim.populations()
+    sim.step(1)
+    got_pop, got_fields = sim.populations(), sim.fields()
+    ora = Oracle(ModelParams(**p), w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+                 t_bottom=w["t_bottom"]).load_post_collision(state, 21)
+    errs = field_errors(got_fields, ora.fields())
+    print(precision, "fields after load", errs)
+    if FORMATS[precision] is None:
+        # fixed point rounds the anti-bounce-back wall source onto its grid:
+        # half a unit on each of the (at most 3) bounced links of a wall node
+        assert errs["temp"] <= 3 * 0.5 * FIX_UNIT + 2e-6, errs
+        errs.pop("temp")
+    assert max(errs.values()) <= 2e-6, errs
+    ref = ora.post_collision()
+    pr = sim.params
+    refs = np.concatenate([W9 * pr.rho_ref[0], W9 * pr.rho_ref[1], W9 * pr.t_ref])[:, None, None]
+    fluid = (w["solid"] == 0)[None]
+    dev = ref - refs
+    if FORMATS[precision] is None:
+        rounding = np.full_like(dev, 0.5 * FIX_UNIT)
+        rounding[[0, 9, 18]] = 4.0 * FIX_UNIT
+        # g also carries the wall-source rounding of T at wall nodes (above)
+        rounding[18:27] += 3 * 0.5 * FIX_UNIT
+    else:
+        rounding = half_ulp(dev, *FORMATS[precision])
+    bound = rounding + 4e-6 * np.maximum(np.abs(ref), 1e-3)
+    excess = np.where(fluid, np.abs(got_pop - ref) - bound, 0.0)
+    print(precision, "max |gpu-ora|/bound", float(np.where(fluid, np.abs(got_pop - ref) / bound, 0).max()))
+    assert excess.max() <= 0.0
+
+
+def test_fix16_conserves_each_component_mass_exactly():
+    """Fixed-point storage: the integer sum of every component's stored
+    deviations over the fluid nodes is the same after 1000 steps (streaming
+    and bounce-back move integers, the collision's rest population takes the
+    exact remainder)."""
+    w = workloads.crop(steps=0)
+    sim = Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+                     t_bottom=w["t_bottom"], precision="fix16dev")
+    pr = sim.params
+    fluid = w["solid"] == 0
+
+    def integer_masses():
+        pop = sim.populations()
+        out = []
+        for k, ref in ((0, pr.rho_ref[0]), (9, pr.rho_ref[1])):
+            refs = (W9 * np.float64(np.float32(ref)))[:, None, None]
+            q = np.rint((pop[k:k + 9] - refs) / FIX_UNIT)
+            assert np.abs((pop[k:k + 9] - refs) / FIX_UNIT - q)[:, fluid].max() < 1e-6
+            out.append(int(q[:, fluid].astype(np.int64).sum()))
+        return out
+
+    m0 = integer_masses()
+    sim.step(1000)
+    assert integer_masses() == m0

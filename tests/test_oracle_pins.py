@@ -328,7 +328,7 @@ def _golden_rows():
 def _phase_run(g12):
     s = workloads.two_layer()
     p = _params(g12=g12, alpha_g=0.0)
-    o = Oracle(p, s["rho_a"], s["rho_b"], s["temp"], periodic_y=True)
+    o = Oracle(p, s["rho_a"], s["rho_b"], s["temp"], periodic_y=True, threads=1)
     o.step(50000)
     r = o.fields()["rho_a"]
     return r.max(), r.min()
@@ -375,7 +375,7 @@ def _laplace_run(R, L=64, steps=8000):
     inside = workloads.single_droplet(L, L, R)["rho_a"] > 1
     ra = np.where(inside, *[COEX["a_rich"][0], COEX["b_rich"][0]])
     rb = np.where(inside, *[COEX["a_rich"][1], COEX["b_rich"][1]])
-    o = Oracle(p, ra, rb, np.zeros((L, L)), periodic_y=True).step(steps)
+    o = Oracle(p, ra, rb, np.zeros((L, L)), periodic_y=True, threads=1).step(steps)
     f = o.fields()
     c = L // 2
     a_in, b_in = f["rho_a"][c - 1:c + 1, c - 1:c + 1].mean(), f["rho_b"][c - 1:c + 1, c - 1:c + 1].mean()
