@@ -1,0 +1,58 @@
+// Host-side launch interface between the C ABI (tlb.hip) and the kernels.
+// Each storage type's kernels are instantiated in a translation unit of their
+// own (launch_<storage>.hip), compiled in parallel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tlb.h"
+
+namespace tlbh {
+
+struct Geometry {
+  int bx = 64;       // columns (threads) per block
+  int rows = 1;      // rows per block chunk
+  bool wide = false; // 64-bit byte offsets (population buffer >= 4 GiB)
+  dim3 grid;
+};
+
+// Everything a launch needs from a handle.
+struct Device {
+  const tlb_params* p = nullptr;
+  hipStream_t stream = nullptr;
+  Geometry geo;
+  int pitch = 0;
+  long long pop_stride = 0;
+  bool has_solid = false;
+  bool tau_one = false;            // tau = tau_g = 1 path
+  const uint16_t* link = nullptr;
+  const uint8_t* solid = nullptr;
+  const void* t_bottom = nullptr;  // compute-type copy of the bottom temperature
+  double* partials = nullptr;
+  double* fields = nullptr;
+};
+
+// Kernel passes of the step kernel.
+enum class Pass {
+  kStep,         // f*(t) -> f*(t+1)
+  kInitStep,     // f(0) in place -> f*(0)
+  kObserve,      // observable sums of time t from f*(t-1), no store
+  kObserveInit,  // same at t = 0 from f(0)
+  kFields,       // fields of time t from f*(t-1), no store
+  kFieldsInit    // same at t = 0 from f(0)
+};
+
+template <class St>
+struct Launcher {
+  // Resident blocks per CU of the step kernel for this geometry.
+  static int blocks_per_cu(int bx, bool wide, bool solid, bool tau_one);
+  static void step(const Device& d, Pass pass, const void* src, void* dst);
+  // f(0) = equilibria of the initial fields (rho_a, rho_b, temp, ux0, uy0;
+  // the velocities may be null).
+  static void init_equilibrium(const Device& d, void* buf, const double* rho_a, const double* rho_b,
+                               const double* temp, const double* ux0, const double* uy0);
+  static void export_populations(const Device& d, const void* buf, double* out);
+};
+
+}  // namespace tlbh

@@ -176,7 +176,8 @@ enum : unsigned {
   kModeObserve = 4u,  // accumulate observable sums into partials
   kModeFields = 8u,   // write the fields
   kModeSolid = 16u,   // solid cells present: use the link masks
-  kModeWide = 32u     // 64-bit byte offsets (population buffer >= 4 GiB)
+  kModeWide = 32u,    // 64-bit byte offsets (population buffer >= 4 GiB)
+  kModeTauOne = 64u   // tau = tau_g = 1: the collision returns the equilibria
 };
 
 template <typename C> __device__ inline C psi_exp(C rho, C rho0, C inv_rho0) {
@@ -316,6 +317,16 @@ template <typename C> __device__ inline C sum9(const C* f) {
   return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
 }
 
+// Momentum sum_i c_i (f_A,i + f_B,i), x and y components.
+template <typename C> __device__ inline C momentum_x(const C* fa, const C* fb) {
+  return ((fa[1] - fa[3]) + (fa[5] - fa[7]) + (fa[8] - fa[6])) +
+         ((fb[1] - fb[3]) + (fb[5] - fb[7]) + (fb[8] - fb[6]));
+}
+template <typename C> __device__ inline C momentum_y(const C* fa, const C* fb) {
+  return ((fa[2] - fa[4]) + (fa[5] - fa[7]) + (fa[6] - fa[8])) +
+         ((fb[2] - fb[4]) + (fb[5] - fb[7]) + (fb[6] - fb[8]));
+}
+
 // Wall temperature of a solid node (x, y) inside the lattice.
 template <typename C>
 __device__ inline C solid_temperature(const StepArgs<C>& a, int x, int y) {
@@ -350,6 +361,8 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
   using C = typename St::C;
   using T = typename St::T;
   using O = Off<kMode>;
+  constexpr bool kTauOne = (kMode & kModeTauOne) != 0;
+  constexpr int kKept = kTauOne ? 4 : 18;  // values kept per pulled row
   constexpr int W = BX + 4;   // ring row width: strip plus 2 halo columns each side
   constexpr int R = 6;        // ring rows
   __shared__ C s_rho[2][R][W];
@@ -386,9 +399,11 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
 
   // Densities of node (x, r) into ring slot `slot` / column `col`; the pulled
-  // populations land in f and the node's link mask in lm.
+  // populations land in f and the node's link mask in lm. Returns whether
+  // the node was pulled (fluid, inside the lattice).
   auto density = [&](int x, int r, int slot, int col, C (&f)[18], uint32_t& lm) {
     C ra = a.rho_wall0, rb = a.rho_wall1, pa = psi_w0, pb = psi_w1;
+    bool pulled = false;
     lm = kSelfSolid;
     if (r >= 0 && r < ly) {
       lm = link_mask<kMode>(a, x, r);
@@ -403,20 +418,45 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
         }
         pa = psi_exp(ra, a.rho0, a.inv_rho0);
         pb = psi_exp(rb, a.rho0, a.inv_rho0);
+        pulled = true;
       }
     }
     s_rho[0][slot][col] = ra;
     s_rho[1][slot][col] = rb;
     s_psi[0][slot][col] = pa;
     s_psi[1][slot][col] = pb;
+    return pulled;
   };
 
-  // One row iteration: pull row r = y0 - 2 + k into fw/lw and complete row
-  // r - 2 from fu/lu (pulled two iterations earlier).
-  auto iterate = [&](int k, C (&fw)[18], uint32_t& lw, const C (&fu)[18], uint32_t lu) {
+  // One row iteration: pull row r = y0 - 2 + k (kept in kw/lw) and complete
+  // row y = r - 2 from ku/lu (kept two iterations earlier). The g values of
+  // row y are pulled together with the f values of row r, so each
+  // iteration waits on memory once. With tau = tau_g = 1 the collision
+  // returns the equilibria, so a kept row is only its moments.
+  auto iterate = [&](int k, C (&kw)[kKept], uint32_t& lw, const C (&ku)[kKept], uint32_t lu) {
     const int r = y0 - 2 + k;
+    const int y = r - 2;
     const int slot = k % R;
-    density(xw, r, slot, tid + 2, fw, lw);
+    const bool out = k >= 4 && y < y1 && own_valid;
+    const bool out_fluid = out && !((kMode & kModeSolid) != 0 && (lu & kSelfSolid));
+    const NodeAddr<kMode> n = node_addr<St, kMode>(xw, y < 0 ? 0 : y, lx, row_b);
+    C g[9];
+    if (out_fluid) pull_thermal<St, kMode>(a, src, n, lu, plane_b, row_b, xw, y, g);
+    {
+      C f[18];
+      const bool pulled = density(xw, r, slot, tid + 2, f, lw);
+      if constexpr (kTauOne) {
+        if (pulled) {
+          kw[0] = sum9(f);
+          kw[1] = sum9(f + 9);
+          kw[2] = momentum_x(f, f + 9);
+          kw[3] = momentum_y(f, f + 9);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 18; ++i) kw[i] = f[i];
+      }
+    }
     if (wave == k % kWaves && lane < 4) {
       C hf[18];
       uint32_t hl;
@@ -424,10 +464,8 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
     }
     __syncthreads();
 
-    const int y = r - 2;  // row completed in this iteration
-    if (k < 4 || y >= y1 || !own_valid) return;
-    const NodeAddr<kMode> n = node_addr<St, kMode>(xw, y, lx, row_b);
-    if ((kMode & kModeSolid) != 0 && (lu & kSelfSolid)) {
+    if (!out) return;
+    if (!out_fluid) {
       if constexpr ((kMode & kModeStore) != 0) {
 #pragma unroll
         for (int p = 0; p < 27; ++p) st<St, kMode>(dst, (O)p * plane_b + n.own, C(0));
@@ -442,22 +480,26 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
       }
       return;
     }
-    // ---- moments
-    const C* fa = fu;
-    const C* fb = fu + 9;
-    // stored-form sums (exact for the fixed-point storage) and densities
-    const C Da = sum9(fa), Db = sum9(fb);
+    [[maybe_unused]] const C* fa = ku;
+    [[maybe_unused]] const C* fb = ku + 9 * (kTauOne ? 0 : 1);
+    // ---- moments: stored-form sums (exact for the fixed-point storage)
+    C Da, Db, jx, jy;
+    if constexpr (kTauOne) {
+      Da = ku[0];
+      Db = ku[1];
+      jx = ku[2];
+      jy = ku[3];
+    } else {
+      Da = sum9(fa);
+      Db = sum9(fb);
+      jx = momentum_x(fa, fb);
+      jy = momentum_y(fa, fb);
+    }
     C ra = Da, rb = Db;
     if constexpr (St::kDev) {
       ra += a.ref_a;
       rb += a.ref_b;
     }
-    const C jx = ((fa[1] - fa[3]) + (fa[5] - fa[7]) + (fa[8] - fa[6])) +
-                 ((fb[1] - fb[3]) + (fb[5] - fb[7]) + (fb[8] - fb[6]));
-    const C jy = ((fa[2] - fa[4]) + (fa[5] - fa[7]) + (fa[6] - fa[8])) +
-                 ((fb[2] - fb[4]) + (fb[5] - fb[7]) + (fb[6] - fb[8]));
-    C g[9];
-    pull_thermal<St, kMode>(a, src, n, lu, plane_b, row_b, xw, y, g);
     const C Dt = sum9(g);
     C temp = Dt;
     if constexpr (St::kDev) temp += a.ref_t;
@@ -562,9 +604,15 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
       eb -= w * a.ref_b;                                                               \
       eg -= w * a.ref_t;                                                               \
     }                                                                                  \
-    const C qa = St::grid(ea + ka * (fa[I] - ea));                                     \
-    const C qb = St::grid(eb + ka * (fb[I] - eb));                                     \
-    const C qg = St::grid(eg + kg * (g[I] - eg));                                      \
+    C qa = ea, qb = eb, qg = eg;                                                       \
+    if constexpr (!kTauOne) {                                                          \
+      qa += ka * (fa[I] - ea);                                                         \
+      qb += ka * (fb[I] - eb);                                                         \
+      qg += kg * (g[I] - eg);                                                          \
+    }                                                                                  \
+    qa = St::grid(qa);                                                                 \
+    qb = St::grid(qb);                                                                 \
+    qg = St::grid(qg);                                                                 \
     if constexpr (St::kFix) {                                                          \
       sa += qa;                                                                        \
       sb += qb;                                                                        \
@@ -587,6 +635,10 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
         st<St, kMode>(dst, n.own, St::grid(Da - sa));
         st<St, kMode>(dst, n.own + p9, St::grid(Db - sb));
         st<St, kMode>(dst, n.own + p18, St::grid(Dt - sg));
+      } else if constexpr (kTauOne) {
+        st<St, kMode>(dst, n.own, Da - sa);
+        st<St, kMode>(dst, n.own + p9, Db - sb);
+        st<St, kMode>(dst, n.own + p18, Dt - sg);
       } else {
         const C ea = Da - sa, eb = Db - sb, eg = Dt - sg;
         st<St, kMode>(dst, n.own, ea + ka * (fa[0] - ea));
@@ -622,7 +674,7 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
   // Three sets of kept rows; the unrolled loop rotates their roles. The
   // iteration count is rounded up to a multiple of 3: the extra iterations
   // only pull in-range rows (or ghost rows) and complete nothing.
-  C f0[18], f1[18], f2[18];
+  C f0[kKept], f1[kKept], f2[kKept];
   uint32_t l0 = 0, l1 = 0, l2 = 0;
   const int n_iter = ((y1 - y0) + 4 + 2) / 3 * 3;
   for (int k = 0; k < n_iter; k += 3) {
@@ -647,40 +699,6 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
       for (int w = 0; w < BX / 64; ++w) v += s_acc[w][tid];
       a.partials[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 8 + tid] = v;
     }
-  }
-}
-
-// Final observable reduction: one block sums the per-block partials in a
-// fixed order and forms the observables of the header's definitions.
-struct ObsArgs {
-  const double* partials;
-  int nblocks;
-  double n_fluid, n_top;
-  double kappa, dt_nominal, ly;
-  double* out;   // [6] mass_a, mass_b, sum_t, nu, nu_top, ke
-};
-
-__global__ __launch_bounds__(256) void lb_reduce_observables(ObsArgs a) {
-  __shared__ double s[7][256];
-  const int tid = threadIdx.x;
-  double v[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int b = tid; b < a.nblocks; b += 256)
-    for (int j = 0; j < 7; ++j) v[j] += a.partials[(size_t)b * 8 + j];
-  for (int j = 0; j < 7; ++j) s[j][tid] = v[j];
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (tid < h)
-      for (int j = 0; j < 7; ++j) s[j][tid] += s[j][tid + h];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const double inv = a.n_fluid > 0 ? 1.0 / a.n_fluid : 0.0;
-    a.out[0] = s[0][0];
-    a.out[1] = s[1][0];
-    a.out[2] = s[2][0];
-    a.out[3] = (s[3][0] * inv - a.kappa * s[4][0] * inv) / (a.kappa * a.dt_nominal / a.ly);
-    a.out[4] = a.n_top > 0 ? 2.0 * a.ly / a.dt_nominal * (s[6][0] / a.n_top) : 0.0;
-    a.out[5] = s[5][0] * inv;
   }
 }
 

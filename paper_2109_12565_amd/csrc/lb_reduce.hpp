@@ -1,0 +1,42 @@
+// Final reduction of the observable sums (one block, fixed order).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tlbk {
+
+// Final observable reduction: one block sums the per-block partials in a
+// fixed order and forms the observables of the header's definitions.
+struct ObsArgs {
+  const double* partials;
+  int nblocks;
+  double n_fluid, n_top;
+  double kappa, dt_nominal, ly;
+  double* out;   // [6] mass_a, mass_b, sum_t, nu, nu_top, ke
+};
+
+__global__ __launch_bounds__(256) void lb_reduce_observables(ObsArgs a) {
+  __shared__ double s[7][256];
+  const int tid = threadIdx.x;
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = tid; b < a.nblocks; b += 256)
+    for (int j = 0; j < 7; ++j) v[j] += a.partials[(size_t)b * 8 + j];
+  for (int j = 0; j < 7; ++j) s[j][tid] = v[j];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h)
+      for (int j = 0; j < 7; ++j) s[j][tid] += s[j][tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double inv = a.n_fluid > 0 ? 1.0 / a.n_fluid : 0.0;
+    a.out[0] = s[0][0];
+    a.out[1] = s[1][0];
+    a.out[2] = s[2][0];
+    a.out[3] = (s[3][0] * inv - a.kappa * s[4][0] * inv) / (a.kappa * a.dt_nominal / a.ly);
+    a.out[4] = a.n_top > 0 ? 2.0 * a.ly / a.dt_nominal * (s[6][0] / a.n_top) : 0.0;
+    a.out[5] = s[5][0] * inv;
+  }
+}
+
+}  // namespace tlbk

@@ -11,18 +11,13 @@
 #include <vector>
 
 #include "../../include/tlb.h"
+#include "launch.hpp"
 #include "lb_kernels.hpp"
+#include "lb_reduce.hpp"
 
 namespace {
 
 thread_local char g_init_error[512];
-
-struct Launch {
-  int bx;              // columns (threads) per block
-  int rows;            // rows per block chunk
-  bool wide;           // 64-bit byte offsets (population buffer >= 4 GiB)
-  dim3 grid;
-};
 
 }  // namespace
 
@@ -45,7 +40,8 @@ struct tlb_handle {
   double* fields = nullptr;        // [5][ly][lx], allocated on first use
   double* export_buf = nullptr;    // [27][ly][lx], allocated on first use
   double n_fluid = 0, n_top = 0;
-  Launch launch{};
+  tlbh::Geometry launch{};
+  bool tau_one = false;            // tau = tau_g = 1: equilibria path
   char err[512] = {0};
 };
 
@@ -90,29 +86,8 @@ void with_storage(int precision, F&& f) {
 // slots about once (the occupancy of the kernel that will run), within
 // [11, 65] rows and with rows + 4 a multiple of 3 (the row loop is unrolled
 // three times). TLB_ROWS_PER_BLOCK overrides the row count.
-template <class St, int BX, unsigned kMode>
-int resident_blocks_per_cu() {
-  int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tlbk::lb_step_kernel<St, BX, kMode>, BX, 0) !=
-          hipSuccess ||
-      n < 1)
-    n = 1;
-  return n;
-}
-
-template <class St>
-int step_blocks_per_cu(int bx, bool wide, bool solid) {
-  using namespace tlbk;
-  constexpr unsigned S = kModeStore;
-  if (wide) return solid ? resident_blocks_per_cu<St, 256, S | kModeSolid | kModeWide>()
-                         : resident_blocks_per_cu<St, 256, S | kModeWide>();
-  if (bx == 256) return solid ? resident_blocks_per_cu<St, 256, S | kModeSolid>()
-                              : resident_blocks_per_cu<St, 256, S>();
-  return solid ? resident_blocks_per_cu<St, 64, S | kModeSolid>() : resident_blocks_per_cu<St, 64, S>();
-}
-
-Launch choose_launch(const tlb_params& p, size_t buffer_bytes, bool solid) {
-  Launch l;
+tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool solid, bool tau_one) {
+  tlbh::Geometry l;
   const int lx = p.lx, ly = p.ly;
   // 32-bit byte offsets address the whole population buffer below 4 GiB;
   // TLB_FORCE_WIDE=1 selects the 64-bit variant at any size (for testing).
@@ -124,7 +99,7 @@ Launch choose_launch(const tlb_params& p, size_t buffer_bytes, bool solid) {
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   int per_cu = 1;
   with_storage(p.precision, [&](auto st) {
-    per_cu = step_blocks_per_cu<decltype(st)>(l.bx, l.wide, solid);
+    per_cu = tlbh::Launcher<decltype(st)>::blocks_per_cu(l.bx, l.wide, solid, tau_one);
   });
   const long long slots = (long long)cus * per_cu;
   const long long strips = (lx + l.bx - 1) / l.bx;
@@ -140,76 +115,37 @@ Launch choose_launch(const tlb_params& p, size_t buffer_bytes, bool solid) {
   return l;
 }
 
-template <typename C>
-tlbk::StepArgs<C> make_args(const tlb_handle* h, const void* src, void* dst) {
-  tlbk::StepArgs<C> a{};
-  const tlb_params& p = h->p;
-  a.src = src;
-  a.dst = dst;
-  a.link = h->link;
-  a.solid = h->solid;
-  a.t_bottom = static_cast<const C*>(h->t_bottom);
-  a.partials = h->partials;
-  a.fields = h->fields;
-  a.lx = p.lx;
-  a.ly = p.ly;
-  a.pitch = h->pitch;
-  a.rows_per_block = h->launch.rows;
-  a.pop_stride = h->pop_stride;
-  a.inv_tau = C(1.0 / p.tau);
-  a.inv_tau_g = C(1.0 / p.tau_g);
-  a.tau = C(p.tau);
-  a.rho0 = C(p.rho0);
-  a.inv_rho0 = C(1.0 / p.rho0);
-  a.g12 = C(p.g12);
-  a.ga0 = C(p.g_a[0]);
-  a.ga1 = C(p.g_a[1]);
-  a.gr0 = C(p.g_r[0]);
-  a.gr1 = C(p.g_r[1]);
-  a.alpha_g = C(p.alpha_g);
-  a.t_top = C(p.t_top);
-  a.rho_wall0 = C(p.rho_wall[0]);
-  a.rho_wall1 = C(p.rho_wall[1]);
-  a.ref_a = C(p.rho_ref[0]);
-  a.ref_b = C(p.rho_ref[1]);
-  a.ref_t = C(p.t_ref);
-  return a;
+tlbh::Device device_view(const tlb_handle* h) {
+  tlbh::Device d;
+  d.p = &h->p;
+  d.stream = h->stream;
+  d.geo = h->launch;
+  d.pitch = h->pitch;
+  d.pop_stride = h->pop_stride;
+  d.has_solid = h->has_solid;
+  d.tau_one = h->tau_one;
+  d.link = h->link;
+  d.solid = h->solid;
+  d.t_bottom = h->t_bottom;
+  d.partials = h->partials;
+  d.fields = h->fields;
+  return d;
 }
 
-template <class St, int BX, unsigned kMode>
-void launch_step(const tlb_handle* h, const tlbk::StepArgs<typename St::C>& a) {
-  hipLaunchKernelGGL((tlbk::lb_step_kernel<St, BX, kMode>), h->launch.grid, dim3(BX), 0,
-                     h->stream, a);
-}
-
-// Dispatch on block width, offset width and the presence of solid cells
-// (the 64-bit offset variant always runs 256-wide blocks).
-template <class St, unsigned kMode>
-void launch_solid(const tlb_handle* h, const tlbk::StepArgs<typename St::C>& a) {
-  if (h->launch.wide) launch_step<St, 256, kMode | tlbk::kModeWide>(h, a);
-  else if (h->launch.bx == 256) launch_step<St, 256, kMode>(h, a);
-  else launch_step<St, 64, kMode>(h, a);
-}
-
-template <class St, unsigned kMode>
-void launch_mode(const tlb_handle* h, const void* src, void* dst) {
-  auto a = make_args<typename St::C>(h, src, dst);
-  if (h->has_solid) launch_solid<St, kMode | tlbk::kModeSolid>(h, a);
-  else launch_solid<St, kMode>(h, a);
-}
-
-template <unsigned kMode>
-void launch_any(const tlb_handle* h, const void* src, void* dst) {
-  with_storage(h->p.precision, [&](auto st) { launch_mode<decltype(st), kMode>(h, src, dst); });
+void launch_pass(const tlb_handle* h, tlbh::Pass pass, const void* src, void* dst) {
+  const tlbh::Device d = device_view(h);
+  with_storage(h->p.precision,
+               [&](auto st) { tlbh::Launcher<decltype(st)>::step(d, pass, src, dst); });
 }
 
 // Re-run the step that produced f*(t) without storing, to evaluate the
-// moments, forces and u^H of time t (observables and/or fields).
-template <unsigned kMode>
-int evaluate_time_level(tlb_handle* h) {
+// moments, forces and u^H of time t (observables or fields).
+int evaluate_time_level(tlb_handle* h, bool fields) {
   const void* src = h->buf[1 - h->cur];
-  if (h->t == 0) launch_any<kMode | tlbk::kModeInit>(h, src, nullptr);
-  else launch_any<kMode>(h, src, nullptr);
+  using tlbh::Pass;
+  const Pass pass = h->t == 0 ? (fields ? Pass::kFieldsInit : Pass::kObserveInit)
+                              : (fields ? Pass::kFields : Pass::kObserve);
+  launch_pass(h, pass, src, nullptr);
   TLB_HIP(h, hipGetLastError());
   return TLB_OK;
 }
@@ -278,7 +214,11 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
   h->pitch = (lx + 63) / 64 * 64;
   h->pop_stride = (long long)h->pitch * ly;
   h->elem = storage_bytes(p->precision);
-  h->launch = choose_launch(*p, (size_t)27 * h->pop_stride * h->elem, h->has_solid);
+  // tau = tau_g = 1 gives f* = f^eq exactly: the kernels keep only moments of
+  // the pulled rows (TLB_GENERAL_PATH=1 forces the general path, for tests)
+  const char* general = std::getenv("TLB_GENERAL_PATH");
+  h->tau_one = p->tau == 1.0 && p->tau_g == 1.0 && !(general && std::atoi(general) == 1);
+  h->launch = choose_launch(*p, (size_t)27 * h->pop_stride * h->elem, h->has_solid, h->tau_one);
 
   int rc = TLB_OK;
   auto cleanup_fail = [&](int code) {
@@ -337,19 +277,17 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
   for (int k = 0; k < nf; ++k)
     INIT_HIP(hipMemcpyAsync(d_fields + k * n, srcs[k], n * sizeof(double), hipMemcpyHostToDevice,
                             h->stream));
-  dim3 g2((lx + 255) / 256, ly, 1);
   const double* dux = nf == 5 ? d_fields + 3 * n : nullptr;
   const double* duy = nf == 5 ? d_fields + 4 * n : nullptr;
-  with_storage(p->precision, [&](auto st) {
-    using St = decltype(st);
-    using C = typename St::C;
-    hipLaunchKernelGGL(tlbk::lb_init_equilibrium<St>, g2, dim3(256), 0, h->stream,
-                       static_cast<typename St::T*>(h->buf[1]), d_fields, d_fields + n,
-                       d_fields + 2 * n, dux, duy, h->solid, lx, ly, h->pitch, h->pop_stride,
-                       C(p->rho_ref[0]), C(p->rho_ref[1]), C(p->t_ref));
-  });
+  {
+    const tlbh::Device d = device_view(h);
+    with_storage(p->precision, [&](auto st) {
+      tlbh::Launcher<decltype(st)>::init_equilibrium(d, h->buf[1], d_fields, d_fields + n,
+                                                     d_fields + 2 * n, dux, duy);
+    });
+  }
   INIT_HIP(hipGetLastError());
-  launch_any<tlbk::kModeInit | tlbk::kModeStore>(h, h->buf[1], h->buf[0]);
+  launch_pass(h, tlbh::Pass::kInitStep, h->buf[1], h->buf[0]);
   INIT_HIP(hipGetLastError());
   INIT_HIP(hipStreamSynchronize(h->stream));
   INIT_HIP(hipFree(d_fields));
@@ -364,7 +302,7 @@ int tlb_step(tlb_handle* h, int64_t nsteps) {
   if (!h) return fail(nullptr, TLB_EINVAL, "tlb_step: NULL handle");
   if (nsteps < 0) return fail(h, TLB_EINVAL, "tlb_step: nsteps < 0");
   for (int64_t s = 0; s < nsteps; ++s) {
-    launch_any<tlbk::kModeStore>(h, h->buf[h->cur], h->buf[1 - h->cur]);
+    launch_pass(h, tlbh::Pass::kStep, h->buf[h->cur], h->buf[1 - h->cur]);
     h->cur = 1 - h->cur;
     h->t += 1;
   }
@@ -374,7 +312,7 @@ int tlb_step(tlb_handle* h, int64_t nsteps) {
 
 int tlb_observables(tlb_handle* h, tlb_obs* out) {
   if (!h || !out) return fail(h, TLB_EINVAL, "tlb_observables: NULL argument");
-  int rc = evaluate_time_level<tlbk::kModeObserve>(h);
+  int rc = evaluate_time_level(h, false);
   if (rc != TLB_OK) return rc;
   tlbk::ObsArgs oa{};
   oa.partials = h->partials;
@@ -407,7 +345,7 @@ int tlb_get_fields(tlb_handle* h, double* rho_a, double* rho_b, double* ux, doub
   if (!h) return fail(nullptr, TLB_EINVAL, "tlb_get_fields: NULL handle");
   const size_t n = (size_t)h->p.lx * h->p.ly;
   if (!h->fields) TLB_HIP(h, hipMalloc(&h->fields, 5 * n * sizeof(double)));
-  int rc = evaluate_time_level<tlbk::kModeFields>(h);
+  int rc = evaluate_time_level(h, true);
   if (rc != TLB_OK) return rc;
   double* outs[5] = {rho_a, rho_b, ux, uy, temp};
   for (int k = 0; k < 5; ++k)
@@ -423,15 +361,12 @@ int tlb_get_populations(tlb_handle* h, double* out) {
   const int lx = h->p.lx, ly = h->p.ly;
   const size_t total = (size_t)27 * lx * ly;
   if (!h->export_buf) TLB_HIP(h, hipMalloc(&h->export_buf, total * sizeof(double)));
-  dim3 g((lx + 255) / 256, ly, 27);
-  with_storage(h->p.precision, [&](auto st) {
-    using St = decltype(st);
-    using C = typename St::C;
-    hipLaunchKernelGGL(tlbk::lb_export_populations<St>, g, dim3(256), 0, h->stream,
-                       static_cast<const typename St::T*>(h->buf[h->cur]), h->export_buf,
-                       h->solid, lx, ly, h->pitch, h->pop_stride, C(h->p.rho_ref[0]),
-                       C(h->p.rho_ref[1]), C(h->p.t_ref));
-  });
+  {
+    const tlbh::Device d = device_view(h);
+    with_storage(h->p.precision, [&](auto st) {
+      tlbh::Launcher<decltype(st)>::export_populations(d, h->buf[h->cur], h->export_buf);
+    });
+  }
   TLB_HIP(h, hipGetLastError());
   TLB_HIP(h, hipMemcpyAsync(out, h->export_buf, total * sizeof(double), hipMemcpyDeviceToHost,
                             h->stream));

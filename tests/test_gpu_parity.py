@@ -326,3 +326,35 @@ def test_fix16_conserves_each_component_mass_exactly():
     m0 = integer_masses()
     sim.step(1000)
     assert integer_masses() == m0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fix16dev"])
+def test_tau_one_path_matches_general_path_bitwise(monkeypatch, precision):
+    """At tau = tau_g = 1 the collision returns the equilibria; the kernels
+    then keep only the moments of the pulled rows. That path must give
+    bitwise the state of the general path (forced by TLB_GENERAL_PATH=1)."""
+    c = posts_case(lx=96, ly=48, seed=4)
+    runs = []
+    for general in ("1", "0"):
+        monkeypatch.setenv("TLB_GENERAL_PATH", general)
+        sim = Simulation(c["params"], c["rho_a"], c["rho_b"], c["temp"], solid=c["solid"],
+                         t_bottom=c["t_bottom"], precision=precision)
+        sim.step(30)
+        runs.append((sim.populations(), sim.fields(), sim.observables()))
+        sim.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    for k in runs[0][1]:
+        assert np.array_equal(runs[0][1][k], runs[1][1][k]), k
+    assert runs[0][2] == runs[1][2]
+
+
+def test_general_path_fp32_tau_not_one():
+    """tau = 0.8, tau_g = 1.3 (general path) against the oracle, FP32, 300
+    steps."""
+    c = posts_case(lx=128, ly=64, seed=12)
+    c["params"] = dict(c["params"], tau=0.8, tau_g=1.3)
+    sim, ora = run_pair(c, 300, "fp32")
+    errs = field_errors(sim.fields(), ora.fields())
+    print("fp32 tau 0.8/1.3 fields", errs)
+    assert max(errs[k] for k in FIELDS) <= 1e-5, errs
+    assert max(errs["ux"], errs["uy"]) <= 3e-5, errs
