@@ -31,7 +31,9 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per node update: the 27 populations read once and
 # written once, plus one byte of solid flag when the lattice has solid cells.
 BYTES_PER_POP = {"fp64": 8, "fp32": 4, "fp16dev": 2, "bf16dev": 2, "fix16dev": 2}
-KERNEL_SOURCES = ("paper_2109_12565_amd/csrc/lb_kernels.hpp", "paper_2109_12565_amd/csrc/tlb.hip")
+KERNEL_SOURCES = ("paper_2109_12565_amd/csrc/lb_kernels.hpp",
+                  "paper_2109_12565_amd/csrc/launch_impl.hpp",
+                  "paper_2109_12565_amd/csrc/tlb.hip")
 
 
 def kernel_hash() -> str:
@@ -69,6 +71,44 @@ def cpu_baseline(w: dict, sample_steps: int) -> dict:
     return {"value": lups / dt / 1e6, "unit": "MLUPS", "cores": ora.threads, "kind": "oracle",
             "sample": f"{sample_steps} steps of the full {w['lx']}x{w['ly']} lattice, FP64, "
                       f"{dt:.1f} s"}
+
+
+def adjoint_ratio(steps: int, ckpt: int, precision: str) -> dict:
+    """Time of the taped forward plus the reverse sweep (checkpoint segment
+    recompute included) over the time of the plain forward, for the same
+    `steps` steps of the 1024x512 emulsion with a noisy bottom temperature."""
+    import torch
+
+    from paper_2109_12565_amd import Simulation
+
+    w = workloads.mid()
+    tb = workloads.bottom_temperature_noise(w["lx"], 5)
+
+    def make():
+        return Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], t_bottom=tb,
+                          precision=precision)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    with make() as sim:  # warm both paths once (allocations, code loading)
+        sim.step(10)
+        sim.forward_taped(ckpt, ckpt)
+        sim.adjoint(ckpt)
+    with make() as sim:
+        t_fwd, _ = timed(lambda: sim.step(steps))
+    with make() as sim:
+        t_tape, loss = timed(lambda: sim.forward_taped(steps, ckpt))
+        t_adj, g = timed(lambda: sim.adjoint(steps))
+    return {"workload": w["name"], "storage": precision, "steps": steps, "ckpt_every": ckpt,
+            "forward_ms": round(t_fwd * 1e3, 2), "taped_forward_ms": round(t_tape * 1e3, 2),
+            "reverse_ms": round(t_adj * 1e3, 2),
+            "ratio": round((t_tape + t_adj) / t_fwd, 2), "loss": loss,
+            "grad_max_abs": float(np.abs(g).max())}
 
 
 def precision_study(steps: int, every: int, storages) -> dict:
@@ -126,6 +166,9 @@ def main() -> int:
     ap.add_argument("--study", choices=["precision"], default=None,
                     help="instead of the benchmark, print the precision study (storages vs the "
                          "FP64 oracle on the 512x256 crop)")
+    ap.add_argument("--adjoint-steps", type=int, default=500,
+                    help="steps of the adjoint/forward time ratio on the 1024x512 emulsion "
+                         "(FP32, checkpoints every 25; 0 to skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before warmup, run 3 plain device copies of this many MiB (a known "
                          "traffic reference for hardware counters)")
@@ -206,10 +249,12 @@ def main() -> int:
         "check": {"mass_a": obs["mass_a"], "mass_b": obs["mass_b"], "nu": obs["nu"],
                   "wall_s": round(wall, 3)},
     }
+    sim.close()
+    if args.adjoint_steps > 0:
+        out["adjoint"] = adjoint_ratio(args.adjoint_steps, 25, "fp32")
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)
-    sim.close()
     return 0
 
 

@@ -150,6 +150,34 @@ int tlb_get_populations(tlb_handle *h, double *out);
  * the following steps and observable evaluations. */
 int tlb_set_bottom_temperature(tlb_handle *h, const double *t_bottom);
 
+/* Taped forward run for the discrete adjoint (flat walls only, FP64 or FP32
+ * storage). Advances nsteps >= 1 steps exactly as tlb_step does, keeping a
+ * device copy of the state f* every ckpt_every >= 1 steps (the first at the
+ * current time t0), and evaluates the loss
+ *   L = (1/nsteps) sum_{t = t0+1}^{t0+nsteps} Nu_top(t),
+ * Nu_top(t) = 2 ly / dt_nominal * mean over row ly-1 of (T(t) - t_top), the
+ * time-averaged top-wall Nusselt number (Sec. 3.3.2, Eq. (24) in top-wall
+ * flux form), as a function of the bottom wall temperature T_b.
+ *   loss  host, receives L (may be NULL)
+ * The tape (checkpoints) replaces any previous one and stays valid until the
+ * next tlb_forward_taped, tlb_set_bottom_temperature or tlb_destroy; later
+ * tlb_step calls do not touch it. Checkpoint memory is
+ * ceil(nsteps / ckpt_every) copies of the state. Synchronises the stream.
+ * Errors: TLB_EINVAL (solid cells, 16-bit storage, bad counts, state buffer
+ * of 4 GiB or more, ly > 65535), TLB_ENOMEM, TLB_EDEVICE. */
+int tlb_forward_taped(tlb_handle *h, int64_t nsteps, int32_t ckpt_every, double *loss);
+
+/* Reverse sweep of the taped run: grad_t_bottom (host, lx doubles) receives
+ * seed * dL/dT_b(x), the exact derivative of the discrete forward map (the
+ * adjoint of Eqs. (1)-(3), (6)-(12), (16)-(18), (22) and of the
+ * anti-bounce-back wall source 2 w_i T_b). Each checkpoint segment is
+ * recomputed into a device tape of ckpt_every - 1 states, then swept
+ * backwards one step at a time. nsteps must equal the taped count. The
+ * handle's current state is not changed. Synchronises the stream.
+ * Errors: TLB_ESTATE (no valid tape, or nsteps differs from it),
+ * TLB_EINVAL (NULL grad_t_bottom), TLB_ENOMEM, TLB_EDEVICE. */
+int tlb_adjoint_step(tlb_handle *h, int64_t nsteps, double seed, double *grad_t_bottom);
+
 /* Current time step. Returns -1 for a NULL handle. */
 int64_t tlb_time(const tlb_handle *h);
 

@@ -3,6 +3,6 @@
 
 ``Simulation`` wraps one handle of the HIP library ``lib/libtlb.so``.
 """
-from ._lib import EXPORTS, PRECISIONS, Simulation, TlbError, load_library
+from ._lib import EXPORTS, PRECISIONS, Simulation, TlbError, load_library, top_nusselt_loss
 
-__all__ = ["EXPORTS", "PRECISIONS", "Simulation", "TlbError", "load_library"]
+__all__ = ["EXPORTS", "PRECISIONS", "Simulation", "TlbError", "load_library", "top_nusselt_loss"]

@@ -22,7 +22,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "fp16dev": 2, "bf16dev": 3, "fix16dev": 4}
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = (
     "tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_populations",
-    "tlb_set_bottom_temperature", "tlb_time", "tlb_destroy", "tlb_last_error",
+    "tlb_set_bottom_temperature", "tlb_forward_taped", "tlb_adjoint_step", "tlb_time",
+    "tlb_destroy", "tlb_last_error",
 )
 
 
@@ -77,13 +78,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tlb_get_fields.argtypes = [vp, dp, dp, dp, dp, dp]
     lib.tlb_get_populations.argtypes = [vp, dp]
     lib.tlb_set_bottom_temperature.argtypes = [vp, dp]
+    lib.tlb_forward_taped.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, dp]
+    lib.tlb_adjoint_step.argtypes = [vp, ctypes.c_int64, ctypes.c_double, dp]
     lib.tlb_time.argtypes = [vp]
     lib.tlb_time.restype = ctypes.c_int64
     lib.tlb_destroy.argtypes = [vp]
     lib.tlb_last_error.argtypes = [vp]
     lib.tlb_last_error.restype = ctypes.c_char_p
     for name in ("tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_populations",
-                 "tlb_set_bottom_temperature", "tlb_destroy"):
+                 "tlb_set_bottom_temperature", "tlb_forward_taped", "tlb_adjoint_step",
+                 "tlb_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -206,6 +210,21 @@ class Simulation:
         tb = np.ascontiguousarray(np.broadcast_to(np.asarray(t_bottom, np.float64), (self.shape[1],)))
         self._check(self._lib.tlb_set_bottom_temperature(self._h, _dp(tb)))
 
+    def forward_taped(self, nsteps: int, ckpt_every: int = 25) -> float:
+        """Advance ``nsteps`` steps keeping checkpoints every ``ckpt_every``;
+        returns the time-averaged top-wall Nusselt number over them."""
+        loss = ctypes.c_double()
+        self._check(self._lib.tlb_forward_taped(self._h, int(nsteps), int(ckpt_every),
+                                                ctypes.byref(loss)))
+        return loss.value
+
+    def adjoint(self, nsteps: int, seed: float = 1.0) -> np.ndarray:
+        """``seed`` times the gradient of the taped loss with respect to the
+        bottom wall temperature, shape (lx,)."""
+        out = np.empty(self.shape[1])
+        self._check(self._lib.tlb_adjoint_step(self._h, int(nsteps), float(seed), _dp(out)))
+        return out
+
     def close(self) -> None:
         h = getattr(self, "_h", None)
         if h is not None and h.value:
@@ -223,3 +242,34 @@ class Simulation:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def _autograd_function():
+    import torch
+
+    class TopNusseltLoss(torch.autograd.Function):
+        """L(T_b) = time-averaged top-wall Nusselt number of ``nsteps`` steps of
+        ``sim`` from its current state, differentiable in the bottom wall
+        temperature ``t_bottom`` (an (lx,) tensor) through the library's
+        discrete adjoint. The forward call advances ``sim``."""
+
+        @staticmethod
+        def forward(ctx, t_bottom, sim, nsteps, ckpt_every):
+            sim.set_bottom_temperature(t_bottom.detach().to("cpu", torch.float64).numpy())
+            loss = sim.forward_taped(nsteps, ckpt_every)
+            ctx.sim, ctx.nsteps = sim, nsteps
+            ctx.dtype, ctx.device = t_bottom.dtype, t_bottom.device
+            return torch.tensor(loss, dtype=t_bottom.dtype, device=t_bottom.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g = ctx.sim.adjoint(ctx.nsteps, float(grad_out))
+            return torch.as_tensor(g, dtype=ctx.dtype).to(ctx.device), None, None, None
+
+    return TopNusseltLoss
+
+
+def top_nusselt_loss(sim: Simulation, t_bottom, nsteps: int, ckpt_every: int = 25):
+    """Differentiable time-averaged top-wall Nusselt number (see
+    ``TopNusseltLoss``)."""
+    return _autograd_function().apply(t_bottom, sim, nsteps, ckpt_every)

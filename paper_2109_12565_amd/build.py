@@ -1,8 +1,9 @@
 """Build the HIP library ``libtlb.so`` (and the HBM probe) for gfx950 in-tree.
 
 ``python -m paper_2109_12565_amd.build`` (or ``__graft_entry__.build()``)
-compiles the C ABI (``csrc/tlb.hip``) and one translation unit per storage
-type (``csrc/launch_*.hip``) in parallel with hipcc, links them into
+compiles the C ABI (``csrc/tlb.hip``), the adjoint launches
+(``csrc/adjoint.hip``) and one translation unit per storage type
+(``csrc/launch_*.hip``) in parallel with hipcc, links them into
 ``paper_2109_12565_amd/lib/libtlb.so``, and builds ``lib/hbm_probe``.
 """
 from __future__ import annotations
@@ -43,7 +44,8 @@ def _run(cmd, verbose):
 
 def build(verbose: bool = False, jobs: int = 0) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    sources = [os.path.join(CSRC, "tlb.hip")] + sorted(glob.glob(os.path.join(CSRC, "launch_*.hip")))
+    sources = ([os.path.join(CSRC, "tlb.hip"), os.path.join(CSRC, "adjoint.hip")] +
+               sorted(glob.glob(os.path.join(CSRC, "launch_*.hip"))))
     objects = [os.path.join(OBJDIR, os.path.basename(s)[:-4] + ".o") for s in sources]
     jobs = jobs or min(len(sources), os.cpu_count() or 1, 16)
     with ThreadPoolExecutor(max_workers=jobs) as ex:

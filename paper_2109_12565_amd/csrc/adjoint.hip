@@ -1,0 +1,54 @@
+// Launches of the discrete adjoint kernels (FP64 and FP32 storages).
+#include "adjoint_kernels.hpp"
+#include "launch.hpp"
+#include "launch_impl.hpp"
+
+namespace tlbh {
+
+namespace {
+
+template <class St>
+tlbk::AdjArgs<typename St::C> adjoint_args(const Device& d, const AdjointWork& w,
+                                           const void* state, int in) {
+  using C = typename St::C;
+  tlbk::AdjArgs<C> a{};
+  a.s = detail::make_args<C>(d, state, nullptr);
+  a.state = state;
+  a.lam_next = static_cast<const C*>(w.lam[in]);
+  a.lam = static_cast<C*>(w.lam[1 - in]);
+  a.fbar = static_cast<C*>(w.fbar);
+  a.Fbar = static_cast<C*>(w.Fbar);
+  a.aux = static_cast<C*>(w.aux);
+  a.rbar = static_cast<C*>(w.rbar);
+  a.grad = w.grad;
+  a.loss_terms = w.loss_terms;
+  return a;
+}
+
+}  // namespace
+
+template <class St>
+void Adjoint<St>::top_row_term(const Device& d, const AdjointWork& w, const void* state, int k) {
+  auto a = adjoint_args<St>(d, w, state, 0);
+  a.step_index = k;
+  hipLaunchKernelGGL((tlbk::adj_top_row_sum<St>), dim3(1), dim3(256), 0, d.stream, a);
+}
+
+template <class St>
+void Adjoint<St>::reverse_step(const Device& d, const AdjointWork& w, const void* state, int in,
+                               double kappa_top) {
+  auto a = adjoint_args<St>(d, w, state, in);
+  a.kappa_top = static_cast<typename St::C>(kappa_top);
+  const int lx = d.p->lx, ly = d.p->ly;
+  const dim3 grid((lx + 255) / 256, ly), block(256);
+  hipLaunchKernelGGL((tlbk::adj_density<St>), grid, block, 0, d.stream, a);
+  hipLaunchKernelGGL((tlbk::adj_local<St>), grid, block, 0, d.stream, a);
+  hipLaunchKernelGGL((tlbk::adj_scatter<St>), grid, block, 0, d.stream, a);
+  hipLaunchKernelGGL((tlbk::adj_pull<St>), grid, block, 0, d.stream, a);
+  hipLaunchKernelGGL((tlbk::adj_grad_tb<St>), dim3((lx + 255) / 256), block, 0, d.stream, a);
+}
+
+template struct Adjoint<tlbk::Store<double>>;
+template struct Adjoint<tlbk::Store<float>>;
+
+}  // namespace tlbh

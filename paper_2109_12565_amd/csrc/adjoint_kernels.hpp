@@ -1,0 +1,329 @@
+// Discrete adjoint of the lattice Boltzmann step (flat walls, FP64/FP32
+// storage), for the gradient of the time-averaged top-wall Nusselt number
+// with respect to the bottom-wall temperature profile T_b(x).
+//
+// Forward map of one step at a fluid node x (Sec. 2): pull the populations
+// (bounce-back / anti-bounce-back at the walls, the bottom one at T_b),
+// moments rho_l, j, T; forces F_l from the pseudopotentials of the 5 x 5
+// neighbourhood (Eqs. (7), (10)-(12)) plus buoyancy (Eq. (22)); u = j/rho,
+// u_l = u + tau F_l / rho_l (Eq. (6)), u^H = u + F / (2 rho); BGK towards
+// f^eq(rho_l, u_l), g^eq(T, u^H) (Eqs. (2), (3), (16), (18)).
+//
+// Reverse sweep for one step, given lambda(t+1) = dL/d f*(t+1):
+//   adj_local    per node: adjoint of the BGK relaxation, the equilibria, the
+//                velocity shift, u^H, u = j/rho, the node's own terms of the
+//                forces and the moments -> dL/d f(t) pulled values (local
+//                part) and dL/dF_l;
+//   adj_scatter  per node: the transpose of the force stencils (the node's
+//                density enters its neighbours' forces) -> dL/drho_l;
+//   adj_pull     per node: the transpose of the pull (each post-collision
+//                value is pulled exactly once) -> lambda(t);
+//   adj_grad_tb  per column: the anti-bounce-back source 2 w_i T_b of the
+//                bottom links -> dL/dT_b.
+// Densities and pseudopotentials of the step's pulled state are precomputed
+// by adj_density; the forward quantities of a node are recomputed from them
+// and from the node's pulled populations.
+#pragma once
+
+#include "lb_kernels.hpp"
+
+namespace tlbk {
+
+template <typename C>
+struct AdjArgs {
+  StepArgs<C> s;         // forward arguments (walls, constants, layout)
+  const void* state;     // f*(t) (stored type)
+  const C* lam_next;     // lambda(t+1), population layout
+  C* lam;                // lambda(t), population layout
+  C* fbar;               // dL/d f(t) pulled values (27 planes)
+  C* Fbar;               // dL/dF: 4 planes (F_A,x F_A,y F_B,x F_B,y)
+  C* aux;                // rho_A, rho_B, psi_A, psi_B of the pulled state
+  C* rbar;               // dL/drho from the stencil transpose (2 planes)
+  double* grad;          // [lx] accumulated dL/dT_b
+  double* loss_terms;    // per-step loss terms (forward)
+  C kappa_top;           // dL/dT of each top-row node for this step
+  int step_index;
+};
+
+template <typename C>
+__device__ inline long long plane_index(const StepArgs<C>& a, int p, int x, int y) {
+  return (long long)p * a.pop_stride + (long long)y * a.pitch + x;
+}
+
+template <typename C>
+__device__ inline int wrapx(const StepArgs<C>& a, int x) {
+  return x < 0 ? x + a.lx : (x >= a.lx ? x - a.lx : x);
+}
+
+// Density of component l at lattice node (x, y) (wall value outside).
+template <typename C>
+__device__ inline C rho_node(const AdjArgs<C>& a, int l, int x, int y) {
+  if (y < 0 || y >= a.s.ly) return l == 0 ? a.s.rho_wall0 : a.s.rho_wall1;
+  return a.aux[plane_index(a.s, l, wrapx(a.s, x), y)];
+}
+
+// psi_l = rho0 (1 - exp(-rho_l / rho0)) (Eq. (12)) at (x, y).
+template <typename C>
+__device__ inline C psi_node(const AdjArgs<C>& a, int l, int x, int y) {
+  if (y < 0 || y >= a.s.ly)
+    return psi_exp(l == 0 ? a.s.rho_wall0 : a.s.rho_wall1, a.s.rho0, a.s.inv_rho0);
+  return a.aux[plane_index(a.s, 2 + l, wrapx(a.s, x), y)];
+}
+
+// F-bar of component l at (x, y); zero outside the lattice.
+template <typename C>
+__device__ inline void fbar_node(const AdjArgs<C>& a, int l, int x, int y, C& fx, C& fy) {
+  if (y < 0 || y >= a.s.ly) {
+    fx = fy = C(0);
+    return;
+  }
+  const long long q = plane_index(a.s, 0, wrapx(a.s, x), y);
+  fx = a.Fbar[q + (long long)(2 * l) * a.s.pop_stride];
+  fy = a.Fbar[q + (long long)(2 * l + 1) * a.s.pop_stride];
+}
+
+// Pulled populations of node (x, y) from the state (flat walls).
+template <class St>
+__device__ inline void adj_pull_node(const AdjArgs<typename St::C>& a, int x, int y,
+                                     typename St::C (&f)[18], typename St::C (&g)[9]) {
+  using O = Off<0>;
+  const O row_b = (O)a.s.pitch * sizeof(typename St::T);
+  const O plane_b = (O)a.s.pop_stride * sizeof(typename St::T);
+  const uint32_t lm = link_mask<0u>(a.s, x, y);
+  const NodeAddr<0u> n = node_addr<St, 0u>(x, y, a.s.lx, row_b);
+  pull_fluid<St, 0u>(a.state, n, lm, plane_b, row_b, f);
+  pull_thermal<St, 0u>(a.s, a.state, n, lm, plane_b, row_b, x, y, g);
+}
+
+template <class St>
+__global__ __launch_bounds__(256) void adj_density(AdjArgs<typename St::C> a) {
+  using C = typename St::C;
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= a.s.lx) return;
+  C f[18], g[9];
+  adj_pull_node<St>(a, x, y, f, g);
+  const C ra = sum9(f), rb = sum9(f + 9);
+  a.aux[plane_index(a.s, 0, x, y)] = ra;
+  a.aux[plane_index(a.s, 1, x, y)] = rb;
+  a.aux[plane_index(a.s, 2, x, y)] = psi_exp(ra, a.s.rho0, a.s.inv_rho0);
+  a.aux[plane_index(a.s, 3, x, y)] = psi_exp(rb, a.s.rho0, a.s.inv_rho0);
+}
+
+// Forward loss term of one step: sum over the top row of T - T_top from the
+// pulled state, in a fixed order (one block).
+template <class St>
+__global__ __launch_bounds__(256) void adj_top_row_sum(AdjArgs<typename St::C> a) {
+  using C = typename St::C;
+  __shared__ double part[256];
+  double acc = 0;
+  const int y = a.s.ly - 1;
+  for (int x = threadIdx.x; x < a.s.lx; x += 256) {
+    C f[18], g[9];
+    adj_pull_node<St>(a, x, y, f, g);
+    acc += (double)sum9(g) - (double)a.s.t_top;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.loss_terms[a.step_index] = part[0];
+}
+
+template <class St>
+__global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
+  using C = typename St::C;
+  const StepArgs<C>& s = a.s;
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= s.lx) return;
+  C f[18], g[9];
+  adj_pull_node<St>(a, x, y, f, g);
+
+  // ---- forward recompute
+  const C ra = sum9(f), rb = sum9(f + 9), temp = sum9(g);
+  const C jx = momentum_x(f, f + 9), jy = momentum_y(f, f + 9);
+  const C rho = ra + rb, inv_rho = C(1) / rho;
+  const C ux = jx * inv_rho, uy = jy * inv_rho;
+  C Sa[2][2], Sr[2][2], X[2][2], ps[2], dps[2], rl[2] = {ra, rb};
+  for (int l = 0; l < 2; ++l) {
+    ps[l] = psi_node(a, l, x, y);
+    dps[l] = C(1) - ps[l] * s.inv_rho0;  // d psi / d rho = exp(-rho / rho0)
+    Sa[l][0] = Sa[l][1] = Sr[l][0] = Sr[l][1] = X[l][0] = X[l][1] = C(0);
+  }
+  for (int dy = -2; dy <= 2; ++dy)
+    for (int dx = -2; dx <= 2; ++dx) {
+      if (dx == 0 && dy == 0) continue;
+      const int c2 = dx * dx + dy * dy;
+      const C pw = p_c2<C>(c2), ww = w_c2<C>(c2);
+      for (int l = 0; l < 2; ++l) {
+        const C v = psi_node(a, l, x + dx, y + dy);
+        Sr[l][0] += pw * v * C(dx);
+        Sr[l][1] += pw * v * C(dy);
+        if (c2 <= 2) {
+          Sa[l][0] += ww * v * C(dx);
+          Sa[l][1] += ww * v * C(dy);
+          const C r = rho_node(a, 1 - l, x + dx, y + dy);  // other component
+          X[l][0] += ww * r * C(dx);
+          X[l][1] += ww * r * C(dy);
+        }
+      }
+    }
+  const C gcross = s.g12 * s.inv_rho0 * s.inv_rho0;
+  const C ga[2] = {s.ga0, s.ga1}, gr[2] = {s.gr0, s.gr1};
+  C F[2][2];
+  for (int l = 0; l < 2; ++l)
+    for (int d = 0; d < 2; ++d)
+      F[l][d] = -ps[l] * (ga[l] * Sa[l][d] + gr[l] * Sr[l][d]) - gcross * rl[l] * X[l][d];
+  F[0][1] += ra * s.alpha_g * temp;
+  F[1][1] += rb * s.alpha_g * temp;
+  const C Fx = F[0][0] + F[1][0], Fy = F[0][1] + F[1][1];
+  C ul[2][2];
+  for (int l = 0; l < 2; ++l) {
+    ul[l][0] = ux + s.tau * F[l][0] / rl[l];
+    ul[l][1] = uy + s.tau * F[l][1] / rl[l];
+  }
+  const C hx = ux + Fx * C(0.5) * inv_rho, hy = uy + Fy * C(0.5) * inv_rho;
+
+  // ---- adjoint of the BGK relaxation and of the equilibria
+  const C ka = C(1) - s.inv_tau, kg = C(1) - s.inv_tau_g;
+  C fb[18], gb[9];
+  C rbar[2] = {0, 0}, ubar[2][2] = {{0, 0}, {0, 0}}, tbar = 0, hbar[2] = {0, 0};
+  for (int l = 0; l < 2; ++l) {
+    const C u2 = ul[l][0] * ul[l][0] + ul[l][1] * ul[l][1];
+    for (int i = 0; i < 9; ++i) {
+      const C cx = C(dir_cx(i)), cy = C(dir_cy(i)), w = w_dir<C>(i);
+      const C lam = a.lam_next[plane_index(s, 9 * l + i, x, y)];
+      fb[9 * l + i] = ka * lam;
+      const C e = (C(1) - ka) * lam;  // adjoint of f^eq_i
+      const C cu = cx * ul[l][0] + cy * ul[l][1];
+      rbar[l] += e * w * (C(1) + C(3) * cu + C(4.5) * cu * cu - C(1.5) * u2);
+      const C k = e * w * rl[l];
+      ubar[l][0] += k * (C(3) * cx + C(9) * cu * cx - C(3) * ul[l][0]);
+      ubar[l][1] += k * (C(3) * cy + C(9) * cu * cy - C(3) * ul[l][1]);
+    }
+  }
+  {
+    const C u2 = hx * hx + hy * hy;
+    for (int i = 0; i < 9; ++i) {
+      const C cx = C(dir_cx(i)), cy = C(dir_cy(i)), w = w_dir<C>(i);
+      const C lam = a.lam_next[plane_index(s, 18 + i, x, y)];
+      gb[i] = kg * lam;
+      const C e = (C(1) - kg) * lam;
+      const C cu = cx * hx + cy * hy;
+      tbar += e * w * (C(1) + C(3) * cu + C(4.5) * cu * cu - C(1.5) * u2);
+      const C k = e * w * temp;
+      hbar[0] += k * (C(3) * cx + C(9) * cu * cx - C(3) * hx);
+      hbar[1] += k * (C(3) * cy + C(9) * cu * cy - C(3) * hy);
+    }
+  }
+  // ---- velocities: u_l = u + tau F_l / rho_l, u^H = u + F / (2 rho), u = j / rho
+  C Fbar[2][2], uc[2] = {ubar[0][0] + ubar[1][0] + hbar[0], ubar[0][1] + ubar[1][1] + hbar[1]};
+  C rtot = C(0);
+  for (int l = 0; l < 2; ++l) {
+    for (int d = 0; d < 2; ++d) Fbar[l][d] = s.tau * ubar[l][d] / rl[l] + hbar[d] * C(0.5) * inv_rho;
+    rbar[l] -= s.tau * (ubar[l][0] * F[l][0] + ubar[l][1] * F[l][1]) / (rl[l] * rl[l]);
+  }
+  rtot -= (hbar[0] * Fx + hbar[1] * Fy) * C(0.5) * inv_rho * inv_rho;
+  const C jbx = uc[0] * inv_rho, jby = uc[1] * inv_rho;
+  rtot -= (uc[0] * jx + uc[1] * jy) * inv_rho * inv_rho;
+  rbar[0] += rtot;
+  rbar[1] += rtot;
+  // ---- the node's own terms of the forces
+  for (int l = 0; l < 2; ++l) {
+    // buoyancy rho_l alpha_g T e_y
+    rbar[l] += Fbar[l][1] * s.alpha_g * temp;
+    tbar += Fbar[l][1] * s.alpha_g * rl[l];
+    // cross-force prefactor rho_l / rho0
+    rbar[l] -= gcross * (Fbar[l][0] * X[l][0] + Fbar[l][1] * X[l][1]);
+    // self-force prefactor psi_l(x)
+    const C psibar = -(Fbar[l][0] * (ga[l] * Sa[l][0] + gr[l] * Sr[l][0]) +
+                       Fbar[l][1] * (ga[l] * Sa[l][1] + gr[l] * Sr[l][1]));
+    rbar[l] += psibar * dps[l];
+  }
+  // ---- moments (and the loss term of the top row: dL/dT = kappa_top)
+  if (y == s.ly - 1) tbar += a.kappa_top;
+  for (int i = 0; i < 9; ++i) {
+    const C cx = C(dir_cx(i)), cy = C(dir_cy(i));
+    fb[i] += rbar[0] + cx * jbx + cy * jby;
+    fb[9 + i] += rbar[1] + cx * jbx + cy * jby;
+    gb[i] += tbar;
+  }
+  for (int p = 0; p < 18; ++p) a.fbar[plane_index(s, p, x, y)] = fb[p];
+  for (int i = 0; i < 9; ++i) a.fbar[plane_index(s, 18 + i, x, y)] = gb[i];
+  for (int l = 0; l < 2; ++l)
+    for (int d = 0; d < 2; ++d) a.Fbar[plane_index(s, 2 * l + d, x, y)] = Fbar[l][d];
+}
+
+// Transpose of the force stencils: rho_l(x') enters the self forces of its
+// 24 neighbours through psi_l and the cross forces of the other component's
+// 8 neighbours through rho_l / rho0.
+template <class St>
+__global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
+  using C = typename St::C;
+  const StepArgs<C>& s = a.s;
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= s.lx) return;
+  const C gcross = s.g12 * s.inv_rho0 * s.inv_rho0;
+  const C ga[2] = {s.ga0, s.ga1}, gr[2] = {s.gr0, s.gr1};
+  C psibar[2] = {0, 0}, rb[2] = {0, 0};
+  for (int dy = -2; dy <= 2; ++dy)
+    for (int dx = -2; dx <= 2; ++dx) {
+      if (dx == 0 && dy == 0) continue;
+      // neighbour x - c whose stencil reaches this node with offset c
+      const int nx = x - dx, ny = y - dy;
+      const int c2 = dx * dx + dy * dy;
+      const C pw = p_c2<C>(c2), ww = w_c2<C>(c2);
+      for (int l = 0; l < 2; ++l) {
+        C fx, fy;
+        fbar_node(a, l, nx, ny, fx, fy);
+        const C dot = fx * C(dx) + fy * C(dy);
+        psibar[l] -= psi_node(a, l, nx, ny) * (ga[l] * ww + gr[l] * pw) * dot;
+        if (c2 <= 2) rb[1 - l] -= gcross * rho_node(a, l, nx, ny) * ww * dot;
+      }
+    }
+  for (int l = 0; l < 2; ++l) {
+    const C dps = C(1) - psi_node(a, l, x, y) * s.inv_rho0;
+    a.rbar[plane_index(s, l, x, y)] = rb[l] + psibar[l] * dps;
+  }
+}
+
+// Transpose of the pull: f*_i(y) was pulled by the node y + c_i, or, when
+// that node is a wall, by y itself as direction opp(i) (bounce-back; with a
+// minus sign for g, anti-bounce-back).
+template <class St>
+__global__ __launch_bounds__(256) void adj_pull(AdjArgs<typename St::C> a) {
+  using C = typename St::C;
+  const StepArgs<C>& s = a.s;
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= s.lx) return;
+  const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+  for (int i = 0; i < 9; ++i) {
+    const int tx = wrapx(s, x + dir_cx(i)), ty = y + dir_cy(i);
+    const bool wall = ty < 0 || ty >= s.ly;
+    const int sx = wall ? x : tx, sy = wall ? y : ty, si = wall ? opp[i] : i;
+    for (int l = 0; l < 2; ++l) {
+      const C v = a.fbar[plane_index(s, 9 * l + si, sx, sy)] + a.rbar[plane_index(s, l, sx, sy)];
+      a.lam[plane_index(s, 9 * l + i, x, y)] = v;
+    }
+    const C gv = a.fbar[plane_index(s, 18 + si, sx, sy)];
+    a.lam[plane_index(s, 18 + i, x, y)] = wall ? -gv : gv;
+  }
+}
+
+// dL/dT_b(c) += sum of 2 w_i gbar_i(x, 0) over the bottom links whose solid
+// source lies in column c: i = 2 at x = c, i = 5 at x = c + 1, i = 6 at
+// x = c - 1.
+template <class St>
+__global__ __launch_bounds__(256) void adj_grad_tb(AdjArgs<typename St::C> a) {
+  using C = typename St::C;
+  const StepArgs<C>& s = a.s;
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= s.lx) return;
+  const double v = 2.0 * ((double)w_dir<C>(2) * (double)a.fbar[plane_index(s, 18 + 2, c, 0)] +
+                          (double)w_dir<C>(5) * (double)a.fbar[plane_index(s, 18 + 5, wrapx(s, c + 1), 0)] +
+                          (double)w_dir<C>(6) * (double)a.fbar[plane_index(s, 18 + 6, wrapx(s, c - 1), 0)]);
+  a.grad[c] += v;
+}
+
+}  // namespace tlbk

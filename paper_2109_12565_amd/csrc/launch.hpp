@@ -6,7 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/tlb.h"
+#include "tlb.h"
 
 namespace tlbh {
 
@@ -53,6 +53,34 @@ struct Launcher {
   static void init_equilibrium(const Device& d, void* buf, const double* rho_a, const double* rho_b,
                                const double* temp, const double* ux0, const double* uy0);
   static void export_populations(const Device& d, const void* buf, double* out);
+};
+
+// Work buffers of the reverse sweep, in the compute type of the storage and
+// the population layout (pitch, pop_stride).
+struct AdjointWork {
+  void* lam[2] = {nullptr, nullptr};  // adjoint populations, 27 planes each
+  void* fbar = nullptr;               // dL/d(pulled populations), 27 planes
+  void* Fbar = nullptr;               // dL/dF, 4 planes
+  void* aux = nullptr;                // rho_A, rho_B, psi_A, psi_B, 4 planes
+  void* rbar = nullptr;               // dL/drho from the force stencils, 2 planes
+  double* grad = nullptr;             // [lx] dL/dT_b
+  double* loss_terms = nullptr;       // [steps] top-row sums of T - t_top
+};
+
+// Number of compute-type planes of an AdjointWork.
+constexpr int kAdjointPlanes = 27 * 2 + 27 + 4 + 4 + 2;
+
+// Discrete adjoint of the flat-wall step, for the FP64 and FP32 storages.
+template <class St>
+struct Adjoint {
+  // w.loss_terms[k] = sum over the top row of T - t_top, T the temperature
+  // pulled from `state` (the step's pre-collision temperature).
+  static void top_row_term(const Device& d, const AdjointWork& w, const void* state, int k);
+  // Reverse step of state -> next state: lambda[1 - in] from lambda[in]
+  // (dL/d of the next state), adding the top-row loss term with weight
+  // kappa_top and accumulating dL/dT_b into w.grad.
+  static void reverse_step(const Device& d, const AdjointWork& w, const void* state, int in,
+                           double kappa_top);
 };
 
 }  // namespace tlbh

@@ -6,11 +6,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
 
-#include "../../include/tlb.h"
+#include "tlb.h"
 #include "launch.hpp"
 #include "lb_kernels.hpp"
 #include "lb_reduce.hpp"
@@ -42,6 +43,17 @@ struct tlb_handle {
   double n_fluid = 0, n_top = 0;
   tlbh::Geometry launch{};
   bool tau_one = false;            // tau = tau_g = 1: equilibria path
+  // adjoint tape (flat walls, FP64 / FP32 storage)
+  void* ckpt = nullptr;            // checkpoints of f*, ckpt_cap states
+  size_t ckpt_cap = 0;
+  void* tape = nullptr;            // recomputed states of one segment
+  size_t tape_cap = 0;
+  void* adj = nullptr;             // AdjointWork planes
+  double* adj_scalars = nullptr;   // grad [lx] + loss terms [loss_cap]
+  size_t loss_cap = 0;
+  int64_t taped_steps = 0;
+  int ckpt_every = 0;
+  bool tape_valid = false;
   char err[512] = {0};
 };
 
@@ -151,6 +163,59 @@ int evaluate_time_level(tlb_handle* h, bool fields) {
 }
 
 bool finite_positive(double v) { return std::isfinite(v) && v > 0; }
+
+size_t state_bytes(const tlb_handle* h) { return (size_t)27 * h->pop_stride * h->elem; }
+
+// Device buffer of at least `bytes`, reallocated when too small.
+int ensure_buffer(tlb_handle* h, void** ptr, size_t* cap, size_t bytes, const char* what) {
+  if (*cap >= bytes && *ptr) return TLB_OK;
+  if (*ptr) {
+    TLB_HIP(h, hipStreamSynchronize(h->stream));
+    TLB_HIP(h, hipFree(*ptr));
+    *ptr = nullptr;
+    *cap = 0;
+  }
+  const hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return fail(h, e == hipErrorOutOfMemory ? TLB_ENOMEM : TLB_EDEVICE,
+                "%s: hipMalloc of %zu bytes failed: %s", what, bytes, hipGetErrorString(e));
+  }
+  *cap = bytes;
+  return TLB_OK;
+}
+
+// Adjoint work buffers (planes and FP64 scalars) for a run of `nsteps`.
+int ensure_adjoint_work(tlb_handle* h, int64_t nsteps, tlbh::AdjointWork* w) {
+  const size_t csize = is_fp64(h) ? sizeof(double) : sizeof(float);
+  const size_t plane = (size_t)h->pop_stride * csize;
+  size_t cap = h->adj ? (size_t)tlbh::kAdjointPlanes * plane : 0;
+  int rc = ensure_buffer(h, &h->adj, &cap, (size_t)tlbh::kAdjointPlanes * plane, "adjoint work");
+  if (rc != TLB_OK) return rc;
+  const size_t scalars = (size_t)h->p.lx + (size_t)nsteps;
+  size_t scap = h->adj_scalars ? ((size_t)h->p.lx + h->loss_cap) * sizeof(double) : 0;
+  rc = ensure_buffer(h, reinterpret_cast<void**>(&h->adj_scalars), &scap, scalars * sizeof(double),
+                     "adjoint scalars");
+  if (rc != TLB_OK) return rc;
+  h->loss_cap = scap / sizeof(double) - (size_t)h->p.lx;
+  char* base = static_cast<char*>(h->adj);
+  w->lam[0] = base;
+  w->lam[1] = base + 27 * plane;
+  w->fbar = base + 54 * plane;
+  w->Fbar = base + 81 * plane;
+  w->aux = base + 85 * plane;
+  w->rbar = base + 89 * plane;
+  w->grad = h->adj_scalars;
+  w->loss_terms = h->adj_scalars + h->p.lx;
+  return TLB_OK;
+}
+
+// Call f with the storage policy of an FP64 / FP32 handle.
+template <class F>
+void with_adjoint_storage(const tlb_handle* h, F&& f) {
+  if (is_fp64(h)) f(tlbk::Store<double>{});
+  else f(tlbk::Store<float>{});
+}
 
 }  // namespace
 
@@ -377,6 +442,7 @@ int tlb_get_populations(tlb_handle* h, double* out) {
 int tlb_set_bottom_temperature(tlb_handle* h, const double* t_bottom) {
   if (!h || !t_bottom) return fail(h, TLB_EINVAL, "tlb_set_bottom_temperature: NULL argument");
   const int lx = h->p.lx;
+  h->tape_valid = false;
   if (is_fp64(h)) {
     TLB_HIP(h, hipMemcpyAsync(h->t_bottom, t_bottom, lx * sizeof(double), hipMemcpyHostToDevice,
                               h->stream));
@@ -390,13 +456,105 @@ int tlb_set_bottom_temperature(tlb_handle* h, const double* t_bottom) {
   return TLB_OK;
 }
 
+int tlb_forward_taped(tlb_handle* h, int64_t nsteps, int32_t ckpt_every, double* loss) {
+  if (!h) return fail(nullptr, TLB_EINVAL, "tlb_forward_taped: NULL handle");
+  if (nsteps < 1 || ckpt_every < 1)
+    return fail(h, TLB_EINVAL, "tlb_forward_taped: need nsteps >= 1 and ckpt_every >= 1");
+  if (h->has_solid)
+    return fail(h, TLB_EINVAL, "tlb_forward_taped: the adjoint supports flat walls only");
+  if (h->p.precision != TLB_FP64 && h->p.precision != TLB_FP32)
+    return fail(h, TLB_EINVAL, "tlb_forward_taped: the adjoint needs FP64 or FP32 storage");
+  if (h->launch.wide)
+    return fail(h, TLB_EINVAL, "tlb_forward_taped: state buffer of 4 GiB or more");
+  if (h->p.ly > 65535)
+    return fail(h, TLB_EINVAL, "tlb_forward_taped: ly > 65535 rows");
+  h->tape_valid = false;
+  const size_t sb = state_bytes(h);
+  const int64_t nck = (nsteps + ckpt_every - 1) / ckpt_every;
+  int rc = ensure_buffer(h, &h->ckpt, &h->ckpt_cap, (size_t)nck * sb, "checkpoints");
+  if (rc != TLB_OK) return rc;
+  tlbh::AdjointWork w;
+  rc = ensure_adjoint_work(h, nsteps, &w);
+  if (rc != TLB_OK) return rc;
+  const tlbh::Device d = device_view(h);
+  for (int64_t k = 0; k < nsteps; ++k) {
+    if (k % ckpt_every == 0)
+      TLB_HIP(h, hipMemcpyAsync(static_cast<char*>(h->ckpt) + (size_t)(k / ckpt_every) * sb,
+                                h->buf[h->cur], sb, hipMemcpyDeviceToDevice, h->stream));
+    with_adjoint_storage(h, [&](auto st) {
+      tlbh::Adjoint<decltype(st)>::top_row_term(d, w, h->buf[h->cur], (int)k);
+    });
+    launch_pass(h, tlbh::Pass::kStep, h->buf[h->cur], h->buf[1 - h->cur]);
+    h->cur = 1 - h->cur;
+    h->t += 1;
+  }
+  TLB_HIP(h, hipGetLastError());
+  std::vector<double> terms((size_t)nsteps);
+  TLB_HIP(h, hipMemcpyAsync(terms.data(), w.loss_terms, terms.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, h->stream));
+  TLB_HIP(h, hipStreamSynchronize(h->stream));
+  double acc = 0;
+  for (double v : terms) acc += v;
+  if (loss)
+    *loss = acc * 2.0 * h->p.ly / (h->p.dt_nominal * h->p.lx) / (double)nsteps;
+  h->taped_steps = nsteps;
+  h->ckpt_every = ckpt_every;
+  h->tape_valid = true;
+  return TLB_OK;
+}
+
+int tlb_adjoint_step(tlb_handle* h, int64_t nsteps, double seed, double* grad_t_bottom) {
+  if (!h) return fail(nullptr, TLB_EINVAL, "tlb_adjoint_step: NULL handle");
+  if (!grad_t_bottom) return fail(h, TLB_EINVAL, "tlb_adjoint_step: NULL grad_t_bottom");
+  if (!h->tape_valid) return fail(h, TLB_ESTATE, "tlb_adjoint_step: no valid tape");
+  if (nsteps != h->taped_steps)
+    return fail(h, TLB_ESTATE, "tlb_adjoint_step: %lld steps requested, the tape holds %lld",
+                (long long)nsteps, (long long)h->taped_steps);
+  const int K = h->ckpt_every;
+  const size_t sb = state_bytes(h);
+  int rc = K > 1 ? ensure_buffer(h, &h->tape, &h->tape_cap, (size_t)(K - 1) * sb, "tape") : TLB_OK;
+  if (rc != TLB_OK) return rc;
+  tlbh::AdjointWork w;
+  rc = ensure_adjoint_work(h, nsteps, &w);
+  if (rc != TLB_OK) return rc;
+  const size_t csize = is_fp64(h) ? sizeof(double) : sizeof(float);
+  TLB_HIP(h, hipMemsetAsync(w.lam[0], 0, (size_t)27 * h->pop_stride * csize, h->stream));
+  TLB_HIP(h, hipMemsetAsync(w.grad, 0, (size_t)h->p.lx * sizeof(double), h->stream));
+  // dL/dT(x) of each top-row node at each step
+  const double kappa_top = seed * 2.0 * h->p.ly / (h->p.dt_nominal * h->p.lx * (double)nsteps);
+  const tlbh::Device d = device_view(h);
+  const int64_t nck = (nsteps + K - 1) / K;
+  int in = 0;
+  for (int64_t seg = nck - 1; seg >= 0; --seg) {
+    const int64_t s0 = seg * K;
+    const int len = (int)std::min<int64_t>(K, nsteps - s0);
+    auto slot = [&](int j) -> void* {
+      return j == 0 ? static_cast<char*>(h->ckpt) + (size_t)seg * sb
+                    : static_cast<char*>(h->tape) + (size_t)(j - 1) * sb;
+    };
+    for (int j = 1; j < len; ++j) launch_pass(h, tlbh::Pass::kStep, slot(j - 1), slot(j));
+    for (int j = len - 1; j >= 0; --j) {
+      with_adjoint_storage(h, [&](auto st) {
+        tlbh::Adjoint<decltype(st)>::reverse_step(d, w, slot(j), in, kappa_top);
+      });
+      in = 1 - in;
+    }
+  }
+  TLB_HIP(h, hipGetLastError());
+  TLB_HIP(h, hipMemcpyAsync(grad_t_bottom, w.grad, (size_t)h->p.lx * sizeof(double),
+                            hipMemcpyDeviceToHost, h->stream));
+  TLB_HIP(h, hipStreamSynchronize(h->stream));
+  return TLB_OK;
+}
+
 int64_t tlb_time(const tlb_handle* h) { return h ? h->t : -1; }
 
 int tlb_destroy(tlb_handle* h) {
   if (!h) return TLB_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   void* ptrs[] = {h->buf[0], h->buf[1], h->link,   h->solid,      h->t_bottom,
-                  h->partials, h->obs,  h->fields, h->export_buf};
+                  h->partials, h->obs,  h->fields, h->export_buf, h->ckpt,
+                  h->tape,     h->adj,  h->adj_scalars};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);

@@ -168,6 +168,15 @@ def crop(seed: int = 4, steps: int = 5000) -> dict:
                 params=dict(BASE_PARAMS))
 
 
+def adjoint_strip(seed: int = 2, steps: int = 500) -> dict:
+    """1024 x 64 strip with the ``mid`` recipe (42 x 2 discs R=10, same
+    noise): the width of ``mid`` with the top wall inside the bottom wall's
+    domain of dependence over a few hundred steps."""
+    d = _emulsion(1024, 64, seed, 42, 2, 10.0, 0.01, 1e-3, posts=False)
+    return dict(d, name="strip-1024x64", lx=1024, ly=64, seed=seed, steps=steps,
+                params=dict(BASE_PARAMS))
+
+
 def bottom_temperature_noise(lx: int, seed: int = 5, amplitude: float = 1e-2) -> np.ndarray:
     """Bottom-wall temperature 1 + U(-amplitude, amplitude) per column."""
     return 1.0 + _rng(seed).uniform(-amplitude, amplitude, lx)
@@ -189,4 +198,4 @@ def single_droplet(lx: int, ly: int, radius: float) -> dict:
                 temp=np.zeros((ly, lx)))
 
 
-CONFIGS = {"small": small, "mid": mid, "large": large, "crop": crop}
+CONFIGS = {"small": small, "mid": mid, "large": large, "crop": crop, "strip": adjoint_strip}
