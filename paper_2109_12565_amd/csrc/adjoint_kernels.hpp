@@ -90,9 +90,10 @@ __device__ inline void adj_pull_node(const AdjArgs<typename St::C>& a, int x, in
   const O row_b = (O)a.s.pitch * sizeof(typename St::T);
   const O plane_b = (O)a.s.pop_stride * sizeof(typename St::T);
   const uint32_t lm = link_mask<0u>(a.s, x, y);
-  const NodeAddr<0u> n = node_addr<St, 0u>(x, y, a.s.lx, row_b);
-  pull_fluid<St, 0u>(a.state, n, lm, plane_b, row_b, f);
-  pull_thermal<St, 0u>(a.s, a.state, n, lm, plane_b, row_b, x, y, g);
+  const PopMem<St, 0u> m(a.state, (uint64_t)plane_b * 27);
+  const LaneOff<0u> L = lane_off<St, 0u>(x, a.s.lx, plane_b, row_b);
+  pull_fluid<St, 0u>(m, L, y, lm, f);
+  pull_thermal<St, 0u>(a.s, m, L, x, y, lm, g);
 }
 
 template <class St>

@@ -29,10 +29,12 @@
 //
 // Memory layout: population p (0..26) of node (x, y) lives at element
 // p * pop_stride + y * pitch + x of a buffer; pitch is a multiple of 64
-// elements so every wavefront row access is aligned. Addresses are formed as
-// a uniform base pointer plus a 32-bit byte offset (kWide = false, buffers
-// below 4 GiB), which maps to the scalar-base + vector-offset form of the
-// global loads and stores; kWide = true uses 64-bit offsets.
+// elements so every wavefront row access is aligned. Buffers below 4 GiB are
+// accessed through a buffer resource: the plane and row part of an offset is
+// uniform (a scalar register), the column part is per lane and fixed for
+// the whole kernel, so the 27 loads and 27 stores of a node need no vector
+// address arithmetic; kWide = true (4 GiB and above) adds 64-bit offsets to
+// a flat pointer.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -98,8 +100,10 @@ template <typename T_> struct Store {
   using C = T_;
   static constexpr bool kDev = false;
   static constexpr bool kFix = false;
-  __device__ static C load(const T* p) { return *p; }
-  __device__ static void store(T* p, C v) { __builtin_nontemporal_store(v, p); }
+  __device__ static C decode(T v) { return v; }
+  __device__ static T encode(C v) { return v; }
+  __device__ static C load(const T* p) { return decode(*p); }
+  __device__ static void store(T* p, C v) { __builtin_nontemporal_store(encode(v), p); }
   __device__ static C grid(C v) { return v; }
 };
 
@@ -110,10 +114,10 @@ struct StoreF16Dev {
   static constexpr bool kDev = true;
   static constexpr bool kFix = false;
   __device__ static C grid(C v) { return v; }
-  __device__ static C load(const T* p) { return (float)__builtin_bit_cast(_Float16, *p); }
-  __device__ static void store(T* p, C v) {
-    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, (_Float16)v), p);
-  }
+  __device__ static C decode(T v) { return (float)__builtin_bit_cast(_Float16, v); }
+  __device__ static T encode(C v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+  __device__ static C load(const T* p) { return decode(*p); }
+  __device__ static void store(T* p, C v) { __builtin_nontemporal_store(encode(v), p); }
 };
 
 struct StoreBF16Dev {
@@ -122,13 +126,15 @@ struct StoreBF16Dev {
   static constexpr bool kDev = true;
   static constexpr bool kFix = false;
   __device__ static C grid(C v) { return v; }
-  __device__ static C load(const T* p) { return __uint_as_float((uint32_t)*p << 16); }
-  __device__ static void store(T* p, C v) {
+  __device__ static C decode(T v) { return __uint_as_float((uint32_t)v << 16); }
+  __device__ static T encode(C v) {
     uint32_t u = __float_as_uint(v);
     const bool nan = (u & 0x7fffffffu) > 0x7f800000u;
     u += 0x7fffu + ((u >> 16) & 1u);  // round half to even on the dropped 16 bits
-    __builtin_nontemporal_store((uint16_t)(nan ? (__float_as_uint(v) >> 16) | 0x40u : u >> 16), p);
+    return (uint16_t)(nan ? (__float_as_uint(v) >> 16) | 0x40u : u >> 16);
   }
+  __device__ static C load(const T* p) { return decode(*p); }
+  __device__ static void store(T* p, C v) { __builtin_nontemporal_store(encode(v), p); }
 };
 
 // 16-bit fixed-point deviations in units of 2^-15 (range [-1, 1)). Every
@@ -141,14 +147,14 @@ struct StoreFix16Dev {
   static constexpr bool kDev = true;
   static constexpr bool kFix = true;
   static constexpr float kScale = 32768.0f;
-  __device__ static C load(const T* p) { return (float)*p * (1.0f / kScale); }
+  __device__ static C decode(T v) { return (float)v * (1.0f / kScale); }
+  __device__ static T encode(C v) { return (int16_t)(int)(v * kScale); }  // v is on the grid
+  __device__ static C load(const T* p) { return decode(*p); }
   __device__ static C grid(C v) {
     const float q = fminf(fmaxf(rintf(v * kScale), -32768.0f), 32767.0f);
     return q * (1.0f / kScale);
   }
-  __device__ static void store(T* p, C v) {
-    __builtin_nontemporal_store((int16_t)(int)(v * kScale), p);  // v is on the grid
-  }
+  __device__ static void store(T* p, C v) { __builtin_nontemporal_store(encode(v), p); }
 };
 
 // ---------------------------------------------------------------- arguments
@@ -185,64 +191,167 @@ template <typename C> __device__ inline C psi_exp(C rho, C rho0, C inv_rho0) {
   // to keep full relative precision at small rho.
   return -rho0 * expm1(-rho * inv_rho0);
 }
-__device__ inline float psi_exp(float rho, float rho0, float inv_rho0) {
-  return -rho0 * expm1f(-rho * inv_rho0);
+// FP32: e^x - 1 by its Taylor polynomial of degree 8 for |x| <= 1/2
+// (truncation below 1e-8 relative) and from the hardware exp2 elsewhere,
+// where 1 - e^x >= 0.39 leaves no cancellation.
+__device__ inline float expm1_fast(float x) {
+  float p = fmaf(x, 1.0f / 40320.0f, 1.0f / 5040.0f);
+  p = fmaf(x, p, 1.0f / 720.0f);
+  p = fmaf(x, p, 1.0f / 120.0f);
+  p = fmaf(x, p, 1.0f / 24.0f);
+  p = fmaf(x, p, 1.0f / 6.0f);
+  p = fmaf(x, p, 0.5f);
+  p = fmaf(x, p, 1.0f);
+  const float small = x * p;
+  const float large = __builtin_amdgcn_exp2f(x * 1.44269504088896341f) - 1.0f;
+  return fabsf(x) <= 0.5f ? small : large;
 }
+__device__ inline float psi_exp(float rho, float rho0, float inv_rho0) {
+  return -rho0 * expm1_fast(-rho * inv_rho0);
+}
+
+// Reciprocal: the hardware approximation (1 ulp) in FP32, IEEE division in
+// FP64.
+template <typename C> __device__ inline C recip(C v) { return C(1) / v; }
+template <> __device__ inline float recip<float>(float v) { return __builtin_amdgcn_rcpf(v); }
 
 template <unsigned kMode>
 using Off = std::conditional_t<(kMode & kModeWide) != 0, uint64_t, uint32_t>;
 
-// Byte-offset addressing helpers (base pointer is uniform).
-template <class St, unsigned kMode>
-__device__ inline typename St::C ld(const void* base, Off<kMode> off) {
-  return St::load(reinterpret_cast<const typename St::T*>(static_cast<const char*>(base) + off));
-}
-template <class St, unsigned kMode>
-__device__ inline void st(void* base, Off<kMode> off, typename St::C v) {
-  St::store(reinterpret_cast<typename St::T*>(static_cast<char*>(base) + off), v);
-}
+// ---------------------------------------------------------------- memory
+// Buffer resource word 3 for gfx9-family raw (untyped, unswizzled) access,
+// and the cache-policy bit of a non-temporal store.
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kNonTemporal = 2;
 
-// Per-node addressing: byte offset of the node in a population plane, and
-// the byte deltas to its x-1 and x+1 neighbours (periodic wrap included).
+// Population buffer access. Every byte offset is split into a uniform part
+// `soff` (plane and row, held in a scalar register) and a per-lane part
+// `voff` (column, plus a bounce-back displacement where a lane needs one).
+// Below 4 GiB the buffer is accessed through a buffer resource, where the
+// uniform part costs no vector instruction; the 64-bit variant adds both
+// parts to a flat pointer.
+template <class St, unsigned kMode>
+struct PopMem {
+  using T = typename St::T;
+  using C = typename St::C;
+  using O = Off<kMode>;
+  using U2 = unsigned int __attribute__((ext_vector_type(2)));
+  static constexpr bool kBuf = (kMode & kModeWide) == 0;
+  __amdgpu_buffer_rsrc_t rsrc;
+  char* base;
+  __device__ PopMem(const void* p, uint64_t bytes) : base(static_cast<char*>(const_cast<void*>(p))) {
+    if constexpr (kBuf)
+      rsrc = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)(uint32_t)bytes, kBufferWord3);
+  }
+  __device__ C ld(O soff, O voff) const {
+    if constexpr (kBuf) {
+      if constexpr (sizeof(T) == 8)
+        return St::decode(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, soff, 0)));
+      else if constexpr (sizeof(T) == 4)
+        return St::decode(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, soff, 0)));
+      else
+        return St::decode(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rsrc, voff, soff, 0)));
+    } else {
+      return St::decode(*reinterpret_cast<const T*>(base + soff + voff));
+    }
+  }
+  __device__ void st(O soff, O voff, C v) const {
+    const T raw = St::encode(v);
+    if constexpr (kBuf) {
+      if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, raw), rsrc, voff, soff, kNonTemporal);
+      else if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, raw), rsrc, voff, soff,
+                                              kNonTemporal);
+      else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, raw), rsrc, voff, soff,
+                                              kNonTemporal);
+    } else {
+      __builtin_nontemporal_store(raw, reinterpret_cast<T*>(base + soff + voff));
+    }
+  }
+};
+
+// Per-lane byte offsets of one column x within a row (x itself and its
+// periodic neighbours x - 1 and x + 1) and the uniform plane and row sizes.
 template <unsigned kMode>
-struct NodeAddr {
-  Off<kMode> own;
-  Off<kMode> dxm, dxp;   // added modulo 2^32 / 2^64
+struct LaneOff {
+  Off<kMode> v0, vm, vp;
+  Off<kMode> plane_b, row_b;
 };
 
 template <class St, unsigned kMode>
-__device__ inline NodeAddr<kMode> node_addr(int x, int r, int lx, Off<kMode> row_b) {
+__device__ inline LaneOff<kMode> lane_off(int x, int lx, Off<kMode> plane_b, Off<kMode> row_b) {
   using O = Off<kMode>;
   constexpr int E = sizeof(typename St::T);
-  NodeAddr<kMode> n;
-  n.own = (O)r * row_b + (O)x * E;
-  n.dxm = (O)(x == 0 ? (lx - 1) * E : -E);
-  n.dxp = (O)(x == lx - 1 ? -(lx - 1) * E : E);
-  return n;
+  LaneOff<kMode> L;
+  L.v0 = (O)x * E;
+  L.vm = (O)(x == 0 ? lx - 1 : x - 1) * E;
+  L.vp = (O)(x == lx - 1 ? 0 : x + 1) * E;
+  L.plane_b = plane_b;
+  L.row_b = row_b;
+  return L;
 }
 
-// Byte offset of the value pulled for direction I at a node (population
-// plane `base` + I or its opposite on bounce-back).
-template <int I, unsigned kMode>
-__device__ inline Off<kMode> pull_off(const NodeAddr<kMode>& n, uint32_t lm, Off<kMode> plane_b,
-                                      Off<kMode> row_b, Off<kMode> first_plane) {
-  using O = Off<kMode>;
-  if constexpr ((kMode & kModeInit) != 0) {
-    return first_plane + (O)I * plane_b + n.own;
+// Offsets of the value pulled for direction I into row r, in the block of
+// nine planes that starts at byte `first`: plane I at row r - c_y, column
+// x - c_x; or, where the link is solid (bounce-back), plane opp(I) at the
+// node itself. The two alternatives differ by two planes and |c_y| rows;
+// the uniform part is the lower of the two, so every lane offset is
+// non-negative and a lane picks its alternative with its own offset alone.
+template <unsigned kMode>
+struct PullOff {
+  Off<kMode> s, v;
+};
+
+// v + s evaluated where it is used: the displaced offsets of the rare
+// bounce-back path are not hoisted out of the row loop, so they occupy no
+// registers across it.
+template <typename O>
+__device__ inline O add_in_place(O v, O s) {
+  if constexpr (sizeof(O) == 4) {
+    O out;
+    asm volatile("v_add_u32 %0, %1, %2" : "=v"(out) : "s"(s), "v"(v));
+    return out;
   } else {
-    constexpr int cx = Dir<I>::cx, cy = Dir<I>::cy;
-    O src = first_plane + (O)I * plane_b + n.own;
-    if constexpr (cy > 0) src -= row_b;
-    if constexpr (cy < 0) src += row_b;
-    if constexpr (cx > 0) src += n.dxm;
-    if constexpr (cx < 0) src += n.dxp;
-    if constexpr (I == 0) {
-      return src;
+    return v + s;
+  }
+}
+
+template <int I, unsigned kMode, bool kBounce>
+__device__ inline PullOff<kMode> pull_off(const LaneOff<kMode>& L, Off<kMode> first, int r,
+                                          bool bounce) {
+  using O = Off<kMode>;
+  constexpr int cx = Dir<I>::cx, cy = Dir<I>::cy, opp = Dir<I>::opp;
+  const O shifted = cx > 0 ? L.vm : (cx < 0 ? L.vp : L.v0);
+  PullOff<kMode> o;
+  if constexpr (I == 0) {
+    o.s = first + (O)r * L.row_b;
+    o.v = L.v0;
+  } else if constexpr (!kBounce) {
+    o.s = first + (O)I * L.plane_b + (O)(r - cy) * L.row_b;
+    o.v = shifted;
+  } else {
+    const O d = (O)2 * L.plane_b + (cy != 0 ? L.row_b : (O)0);
+    if constexpr (opp > I) {
+      o.s = first + (O)I * L.plane_b + (O)(r - cy) * L.row_b;
+      o.v = bounce ? add_in_place(L.v0, d) : shifted;
     } else {
-      const O bb = first_plane + (O)Dir<I>::opp * plane_b + n.own;
-      return ((lm >> I) & 1u) ? bb : src;
+      o.s = first + (O)opp * L.plane_b + (O)r * L.row_b;
+      o.v = bounce ? L.v0 : add_in_place(shifted, d);
     }
   }
+  return o;
+}
+
+// Link-mask bits of the eight moving directions.
+constexpr uint32_t kLinkBits = 0x1FEu;
+
+// Whether any lane of the wavefront has a bounce-back link (uniform).
+template <unsigned kMode>
+__device__ inline bool any_link(uint32_t lm) {
+  if constexpr ((kMode & kModeSolid) != 0) return __any((lm & kLinkBits) != 0u);
+  else return (lm & kLinkBits) != 0u;  // flat walls: the mask depends on the row only
 }
 
 // Link mask of node (x, r), 0 <= r < ly.
@@ -262,54 +371,88 @@ __device__ inline C source_wall_temperature(const StepArgs<C>& a, int x, int r) 
   const int lx = a.lx;
   const int sx = cx > 0 ? (x == 0 ? lx - 1 : x - 1) : (cx < 0 ? (x == lx - 1 ? 0 : x + 1) : x);
   const int sr = r - cy;
-  if (sr < 0) return a.t_bottom[sx];
+  const C tb = a.t_bottom[sx];  // loaded first: a select of values, not of addresses
+  if (sr < 0) return tb;
   if (sr >= a.ly) return a.t_top;
   if constexpr ((kMode & kModeSolid) != 0) {
-    return a.solid[(uint32_t)sr * (uint32_t)lx + (uint32_t)sx] == 1 ? a.t_bottom[sx] : a.t_top;
+    const bool held_bottom = a.solid[(uint32_t)sr * (uint32_t)lx + (uint32_t)sx] == 1;
+    return held_bottom ? tb : a.t_top;
   }
   return a.t_top;
 }
 
-// Pull f_A (f[0..8]) and f_B (f[9..17]) at fluid node n, in stored form.
-// Opposite directions have equal weights, so a bounced value keeps its
-// deviation reference.
+// Pull f_A (f[0..8]) and f_B (f[9..17]) of row r at lane column L, in
+// stored form. Opposite directions have equal weights, so a bounced value
+// keeps its deviation reference.
 template <class St, unsigned kMode, typename C>
-__device__ inline void pull_fluid(const void* src, const NodeAddr<kMode>& n, uint32_t lm,
-                                  Off<kMode> plane_b, Off<kMode> row_b, C (&f)[18]) {
-  const Off<kMode> plane9 = plane_b * 9;
-#define TLB_PULL_F(I)                                                            \
-  {                                                                              \
-    const Off<kMode> o = pull_off<I, kMode>(n, lm, plane_b, row_b, Off<kMode>(0)); \
-    f[I] = ld<St, kMode>(src, o);                                                \
-    f[I + 9] = ld<St, kMode>(src, o + plane9);                                   \
+__device__ inline void pull_fluid(const PopMem<St, kMode>& m, const LaneOff<kMode>& L, int r,
+                                  uint32_t lm, C (&f)[18]) {
+  using O = Off<kMode>;
+  const O p9 = L.plane_b * 9;
+  if constexpr ((kMode & kModeInit) != 0) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const O s = (O)i * L.plane_b + (O)r * L.row_b;
+      f[i] = m.ld(s, L.v0);
+      f[i + 9] = m.ld(s + p9, L.v0);
+    }
+    return;
   }
-  TLB_PULL_F(0) TLB_PULL_F(1) TLB_PULL_F(2) TLB_PULL_F(3) TLB_PULL_F(4)
-  TLB_PULL_F(5) TLB_PULL_F(6) TLB_PULL_F(7) TLB_PULL_F(8)
+#define TLB_PULL_F(I, B)                                                       \
+  {                                                                            \
+    const auto o = pull_off<I, kMode, B>(L, O(0), r, ((lm >> I) & 1u) != 0u);  \
+    f[I] = m.ld(o.s, o.v);                                                     \
+    f[I + 9] = m.ld(o.s + p9, o.v);                                            \
+  }
+  if (any_link<kMode>(lm)) {
+    TLB_PULL_F(0, true) TLB_PULL_F(1, true) TLB_PULL_F(2, true) TLB_PULL_F(3, true)
+    TLB_PULL_F(4, true) TLB_PULL_F(5, true) TLB_PULL_F(6, true) TLB_PULL_F(7, true)
+    TLB_PULL_F(8, true)
+  } else {
+    TLB_PULL_F(0, false) TLB_PULL_F(1, false) TLB_PULL_F(2, false) TLB_PULL_F(3, false)
+    TLB_PULL_F(4, false) TLB_PULL_F(5, false) TLB_PULL_F(6, false) TLB_PULL_F(7, false)
+    TLB_PULL_F(8, false)
+  }
 #undef TLB_PULL_F
 }
 
-// Pull g at fluid node (x, r), in stored form, with anti-bounce-back at
-// solid sources: g_i = -g*_{opp i}(x) + 2 w_i T_w, i.e. in deviations from
-// w_i T_ref: d_i = -d*_{opp i} + 2 w_i (T_w - T_ref).
+// Pull g of row r at lane column L (column index x), in stored form, with
+// anti-bounce-back at solid sources: g_i = -g*_{opp i}(x) + 2 w_i T_w, i.e.
+// in deviations from w_i T_ref: d_i = -d*_{opp i} + 2 w_i (T_w - T_ref).
 template <class St, unsigned kMode, typename C>
-__device__ inline void pull_thermal(const StepArgs<C>& a, const void* src, const NodeAddr<kMode>& n,
-                                    uint32_t lm, Off<kMode> plane_b, Off<kMode> row_b, int x, int r,
+__device__ inline void pull_thermal(const StepArgs<C>& a, const PopMem<St, kMode>& m,
+                                    const LaneOff<kMode>& L, int x, int r, uint32_t lm,
                                     C (&g)[9]) {
-  const Off<kMode> plane18 = plane_b * 18;
-#define TLB_PULL_G(I)                                                                       \
-  {                                                                                         \
-    C v = ld<St, kMode>(src, pull_off<I, kMode>(n, lm, plane_b, row_b, plane18));           \
-    if constexpr ((kMode & kModeInit) == 0 && I != 0) {                                     \
-      if ((lm >> I) & 1u) {                                                                 \
-        C tw = source_wall_temperature<I, kMode>(a, x, r);                                  \
-        if constexpr (St::kDev) tw -= a.ref_t;                                              \
-        v = St::grid(C(2) * w_dir<C>(I) * tw - v);                                          \
-      }                                                                                     \
-    }                                                                                       \
-    g[I] = v;                                                                               \
+  using O = Off<kMode>;
+  const O p18 = L.plane_b * 18;
+  if constexpr ((kMode & kModeInit) != 0) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = m.ld(p18 + (O)i * L.plane_b + (O)r * L.row_b, L.v0);
+    return;
   }
-  TLB_PULL_G(0) TLB_PULL_G(1) TLB_PULL_G(2) TLB_PULL_G(3) TLB_PULL_G(4)
-  TLB_PULL_G(5) TLB_PULL_G(6) TLB_PULL_G(7) TLB_PULL_G(8)
+#define TLB_PULL_G(I, B)                                                          \
+  {                                                                               \
+    const bool bb = ((lm >> I) & 1u) != 0u;                                       \
+    const auto o = pull_off<I, kMode, B>(L, p18, r, bb);                          \
+    C v = m.ld(o.s, o.v);                                                         \
+    if constexpr (B && I != 0) {                                                  \
+      if (bb) {                                                                   \
+        C tw = source_wall_temperature<I, kMode>(a, x, r);                        \
+        if constexpr (St::kDev) tw -= a.ref_t;                                    \
+        v = St::grid(C(2) * w_dir<C>(I) * tw - v);                                \
+      }                                                                           \
+    }                                                                             \
+    g[I] = v;                                                                     \
+  }
+  if (any_link<kMode>(lm)) {
+    TLB_PULL_G(0, true) TLB_PULL_G(1, true) TLB_PULL_G(2, true) TLB_PULL_G(3, true)
+    TLB_PULL_G(4, true) TLB_PULL_G(5, true) TLB_PULL_G(6, true) TLB_PULL_G(7, true)
+    TLB_PULL_G(8, true)
+  } else {
+    TLB_PULL_G(0, false) TLB_PULL_G(1, false) TLB_PULL_G(2, false) TLB_PULL_G(3, false)
+    TLB_PULL_G(4, false) TLB_PULL_G(5, false) TLB_PULL_G(6, false) TLB_PULL_G(7, false)
+    TLB_PULL_G(8, false)
+  }
 #undef TLB_PULL_G
 }
 
@@ -330,22 +473,22 @@ template <typename C> __device__ inline C momentum_y(const C* fa, const C* fb) {
 // Wall temperature of a solid node (x, y) inside the lattice.
 template <typename C>
 __device__ inline C solid_temperature(const StepArgs<C>& a, int x, int y) {
-  return a.solid[(uint32_t)y * (uint32_t)a.lx + (uint32_t)x] == 1 ? a.t_bottom[x] : a.t_top;
+  const C tb = a.t_bottom[x];
+  return a.solid[(uint32_t)y * (uint32_t)a.lx + (uint32_t)x] == 1 ? tb : a.t_top;
 }
 
 // Temperature of the neighbour (x, r) of a fluid node whose temperature is
 // t_here, for the central difference of dT/dy: T itself if fluid, else the
 // mirror value 2 T_w - t_here (wall plane half-way).
 template <class St, unsigned kMode, typename C>
-__device__ inline C neighbour_temperature(const StepArgs<C>& a, const void* src, int x, int r,
-                                          C t_here, Off<kMode> plane_b, Off<kMode> row_b) {
+__device__ inline C neighbour_temperature(const StepArgs<C>& a, const PopMem<St, kMode>& m,
+                                          const LaneOff<kMode>& L, int x, int r, C t_here) {
   if (r < 0) return C(2) * a.t_bottom[x] - t_here;
   if (r >= a.ly) return C(2) * a.t_top - t_here;
   const uint32_t lm = link_mask<kMode>(a, x, r);
   if (lm & kSelfSolid) return C(2) * solid_temperature(a, x, r) - t_here;
-  const NodeAddr<kMode> n = node_addr<St, kMode>(x, r, a.lx, row_b);
   C g[9];
-  pull_thermal<St, kMode>(a, src, n, lm, plane_b, row_b, x, r, g);
+  pull_thermal<St, kMode>(a, m, L, x, r, lm, g);
   C t = sum9(g);
   if constexpr (St::kDev) t += a.ref_t;
   return t;
@@ -368,8 +511,6 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
   __shared__ C s_rho[2][R][W];
   __shared__ C s_psi[2][R][W];
 
-  const void* src = a.src;
-  void* dst = a.dst;
   const int lx = a.lx, ly = a.ly;
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * BX;
@@ -377,6 +518,8 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
   const int y1 = min(y0 + a.rows_per_block, ly);
   const O row_b = (O)a.pitch * sizeof(T);
   const O plane_b = (O)a.pop_stride * sizeof(T);
+  const PopMem<St, kMode> msrc(a.src, (uint64_t)plane_b * 27);
+  const PopMem<St, kMode> mdst(a.dst, (uint64_t)plane_b * 27);
 
   // own column (idle threads of a ragged strip still fill their ring slot,
   // with a wrapped column, so the halo of the last valid column is right)
@@ -392,6 +535,8 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
   const int wave = tid >> 6;
   const int hslot = lane < 2 ? lane : BX + lane;
   const int hx = ((x0 - 2 + hslot) % lx + lx) % lx;
+  const LaneOff<kMode> Lo = lane_off<St, kMode>(xw, lx, plane_b, row_b);
+  const LaneOff<kMode> Lh = lane_off<St, kMode>(hx, lx, plane_b, row_b);
 
   const C psi_w0 = psi_exp(a.rho_wall0, a.rho0, a.inv_rho0);
   const C psi_w1 = psi_exp(a.rho_wall1, a.rho0, a.inv_rho0);
@@ -401,15 +546,15 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
   // Densities of node (x, r) into ring slot `slot` / column `col`; the pulled
   // populations land in f and the node's link mask in lm. Returns whether
   // the node was pulled (fluid, inside the lattice).
-  auto density = [&](int x, int r, int slot, int col, C (&f)[18], uint32_t& lm) {
+  auto density = [&](int x, const LaneOff<kMode>& L, int r, int slot, int col, C (&f)[18],
+                     uint32_t& lm) {
     C ra = a.rho_wall0, rb = a.rho_wall1, pa = psi_w0, pb = psi_w1;
     bool pulled = false;
     lm = kSelfSolid;
     if (r >= 0 && r < ly) {
       lm = link_mask<kMode>(a, x, r);
       if (!((kMode & kModeSolid) != 0 && (lm & kSelfSolid))) {
-        const NodeAddr<kMode> n = node_addr<St, kMode>(x, r, lx, row_b);
-        pull_fluid<St, kMode>(src, n, lm, plane_b, row_b, f);
+        pull_fluid<St, kMode>(msrc, L, r, lm, f);
         ra = sum9(f);
         rb = sum9(f + 9);
         if constexpr (St::kDev) {
@@ -439,12 +584,12 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
     const int slot = k % R;
     const bool out = k >= 4 && y < y1 && own_valid;
     const bool out_fluid = out && !((kMode & kModeSolid) != 0 && (lu & kSelfSolid));
-    const NodeAddr<kMode> n = node_addr<St, kMode>(xw, y < 0 ? 0 : y, lx, row_b);
+    const O yrow = (O)(y < 0 ? 0 : y) * row_b;
     C g[9];
-    if (out_fluid) pull_thermal<St, kMode>(a, src, n, lu, plane_b, row_b, xw, y, g);
+    if (out_fluid) pull_thermal<St, kMode>(a, msrc, Lo, xw, y, lu, g);
     {
       C f[18];
-      const bool pulled = density(xw, r, slot, tid + 2, f, lw);
+      const bool pulled = density(xw, Lo, r, slot, tid + 2, f, lw);
       if constexpr (kTauOne) {
         if (pulled) {
           kw[0] = sum9(f);
@@ -460,7 +605,7 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
     if (wave == k % kWaves && lane < 4) {
       C hf[18];
       uint32_t hl;
-      density(hx, r, slot, hslot, hf, hl);
+      density(hx, Lh, r, slot, hslot, hf, hl);
     }
     __syncthreads();
 
@@ -468,7 +613,7 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
     if (!out_fluid) {
       if constexpr ((kMode & kModeStore) != 0) {
 #pragma unroll
-        for (int p = 0; p < 27; ++p) st<St, kMode>(dst, (O)p * plane_b + n.own, C(0));
+        for (int p = 0; p < 27; ++p) mdst.st((O)p * plane_b + yrow, Lo.v0, C(0));
       }
       if constexpr ((kMode & kModeFields) != 0) {
         const size_t nn = (size_t)lx * ly, q = (size_t)y * lx + xo;
@@ -567,14 +712,14 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
 
     // ---- velocities
     const C rho = ra + rb;
-    const C inv_rho = C(1) / rho;
+    const C inv_rho = recip(rho);
     const C ux = jx * inv_rho, uy = jy * inv_rho;
     const C Fx = FA[0] + FB[0], Fy = FA[1] + FB[1];
     const C hx = ux + C(0.5) * Fx * inv_rho;
     const C hy = uy + C(0.5) * Fy * inv_rho;
 
     if constexpr ((kMode & kModeStore) != 0) {
-      const C tA = a.tau / ra, tB = a.tau / rb;
+      const C tA = a.tau * recip(ra), tB = a.tau * recip(rb);
       const C uax = ux + FA[0] * tA, uay = uy + FA[1] * tA;
       const C ubx = ux + FB[0] * tB, uby = uy + FB[1] * tB;
       const C ua2 = uax * uax + uay * uay;
@@ -589,61 +734,80 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
       const C ka = C(1) - a.inv_tau, kg = C(1) - a.inv_tau_g;
       C sa = 0, sb = 0, sg = 0;
       const O p9 = plane_b * 9, p18 = plane_b * 18;
-#define TLB_COLLIDE(I)                                                                 \
+    // Opposite directions share the even part of the equilibrium:
+    // f^eq_{i, opp i} = S_i +- D_i with S_i = w_i rho (1 + 4.5 (c_i.u)^2
+    // - 1.5 u^2) and D_i = 3 w_i rho (c_i.u), so each pair costs one S and
+    // one D per field.
+#define TLB_PAIR(I)                                                                    \
   {                                                                                    \
+    constexpr int J = Dir<I>::opp;                                                     \
     constexpr int cx = Dir<I>::cx, cy = Dir<I>::cy;                                   \
     constexpr C w = w_dir<C>(I);                                                       \
     const C cua = C(cx) * uax + C(cy) * uay;                                           \
     const C cub = C(cx) * ubx + C(cy) * uby;                                           \
     const C cuh = C(cx) * hx + C(cy) * hy;                                             \
-    C ea = w * ra * (C(1) + C(3) * cua + C(4.5) * cua * cua - C(1.5) * ua2);           \
-    C eb = w * rb * (C(1) + C(3) * cub + C(4.5) * cub * cub - C(1.5) * ub2);           \
-    C eg = w * temp * (C(1) + C(3) * cuh + C(4.5) * cuh * cuh - C(1.5) * uh2);         \
+    C Sa = w * ra * (C(1) + C(4.5) * cua * cua - C(1.5) * ua2);                        \
+    C Sb = w * rb * (C(1) + C(4.5) * cub * cub - C(1.5) * ub2);                        \
+    C Sg = w * temp * (C(1) + C(4.5) * cuh * cuh - C(1.5) * uh2);                      \
+    const C Dla = C(3) * w * ra * cua;                                                 \
+    const C Dlb = C(3) * w * rb * cub;                                                 \
+    const C Dlg = C(3) * w * temp * cuh;                                               \
     if constexpr (St::kDev) {                                                          \
-      ea -= w * a.ref_a;                                                               \
-      eb -= w * a.ref_b;                                                               \
-      eg -= w * a.ref_t;                                                               \
+      Sa -= w * a.ref_a;                                                               \
+      Sb -= w * a.ref_b;                                                               \
+      Sg -= w * a.ref_t;                                                               \
     }                                                                                  \
-    C qa = ea, qb = eb, qg = eg;                                                       \
+    const C eaI = Sa + Dla, eaJ = Sa - Dla;                                            \
+    const C ebI = Sb + Dlb, ebJ = Sb - Dlb;                                            \
+    const C egI = Sg + Dlg, egJ = Sg - Dlg;                                            \
+    C qaI = eaI, qaJ = eaJ, qbI = ebI, qbJ = ebJ, qgI = egI, qgJ = egJ;               \
     if constexpr (!kTauOne) {                                                          \
-      qa += ka * (fa[I] - ea);                                                         \
-      qb += ka * (fb[I] - eb);                                                         \
-      qg += kg * (g[I] - eg);                                                          \
+      qaI += ka * (fa[I] - eaI);                                                       \
+      qaJ += ka * (fa[J] - eaJ);                                                       \
+      qbI += ka * (fb[I] - ebI);                                                       \
+      qbJ += ka * (fb[J] - ebJ);                                                       \
+      qgI += kg * (g[I] - egI);                                                        \
+      qgJ += kg * (g[J] - egJ);                                                        \
     }                                                                                  \
-    qa = St::grid(qa);                                                                 \
-    qb = St::grid(qb);                                                                 \
-    qg = St::grid(qg);                                                                 \
+    qaI = St::grid(qaI);                                                               \
+    qaJ = St::grid(qaJ);                                                               \
+    qbI = St::grid(qbI);                                                               \
+    qbJ = St::grid(qbJ);                                                               \
+    qgI = St::grid(qgI);                                                               \
+    qgJ = St::grid(qgJ);                                                               \
     if constexpr (St::kFix) {                                                          \
-      sa += qa;                                                                        \
-      sb += qb;                                                                        \
-      sg += qg;                                                                        \
+      sa += qaI + qaJ;                                                                 \
+      sb += qbI + qbJ;                                                                 \
+      sg += qgI + qgJ;                                                                 \
     } else {                                                                           \
-      sa += ea;                                                                        \
-      sb += eb;                                                                        \
-      sg += eg;                                                                        \
+      sa += eaI + eaJ;                                                                 \
+      sb += ebI + ebJ;                                                                 \
+      sg += egI + egJ;                                                                 \
     }                                                                                  \
-    const O o = (O)I * plane_b + n.own;                                                \
-    st<St, kMode>(dst, o, qa);                                                         \
-    st<St, kMode>(dst, o + p9, qb);                                                    \
-    st<St, kMode>(dst, o + p18, qg);                                                   \
+    const O oI = (O)I * plane_b + yrow, oJ = (O)J * plane_b + yrow;                    \
+    mdst.st(oI, Lo.v0, qaI);                                                           \
+    mdst.st(oJ, Lo.v0, qaJ);                                                           \
+    mdst.st(oI + p9, Lo.v0, qbI);                                                      \
+    mdst.st(oJ + p9, Lo.v0, qbJ);                                                      \
+    mdst.st(oI + p18, Lo.v0, qgI);                                                     \
+    mdst.st(oJ + p18, Lo.v0, qgJ);                                                     \
   }
-      TLB_COLLIDE(1) TLB_COLLIDE(2) TLB_COLLIDE(3) TLB_COLLIDE(4)
-      TLB_COLLIDE(5) TLB_COLLIDE(6) TLB_COLLIDE(7) TLB_COLLIDE(8)
-#undef TLB_COLLIDE
+      TLB_PAIR(1) TLB_PAIR(2) TLB_PAIR(5) TLB_PAIR(6)
+#undef TLB_PAIR
       if constexpr (St::kFix) {
         // exact remainders: the stored populations sum to the pulled ones
-        st<St, kMode>(dst, n.own, St::grid(Da - sa));
-        st<St, kMode>(dst, n.own + p9, St::grid(Db - sb));
-        st<St, kMode>(dst, n.own + p18, St::grid(Dt - sg));
+        mdst.st(yrow, Lo.v0, St::grid(Da - sa));
+        mdst.st(yrow + p9, Lo.v0, St::grid(Db - sb));
+        mdst.st(yrow + p18, Lo.v0, St::grid(Dt - sg));
       } else if constexpr (kTauOne) {
-        st<St, kMode>(dst, n.own, Da - sa);
-        st<St, kMode>(dst, n.own + p9, Db - sb);
-        st<St, kMode>(dst, n.own + p18, Dt - sg);
+        mdst.st(yrow, Lo.v0, Da - sa);
+        mdst.st(yrow + p9, Lo.v0, Db - sb);
+        mdst.st(yrow + p18, Lo.v0, Dt - sg);
       } else {
         const C ea = Da - sa, eb = Db - sb, eg = Dt - sg;
-        st<St, kMode>(dst, n.own, ea + ka * (fa[0] - ea));
-        st<St, kMode>(dst, n.own + p9, eb + ka * (fb[0] - eb));
-        st<St, kMode>(dst, n.own + p18, eg + kg * (g[0] - eg));
+        mdst.st(yrow, Lo.v0, ea + ka * (fa[0] - ea));
+        mdst.st(yrow + p9, Lo.v0, eb + ka * (fb[0] - eb));
+        mdst.st(yrow + p18, Lo.v0, eg + kg * (g[0] - eg));
       }
     }
     // FP64 densities for output: reference plus the stored-form sum
@@ -659,8 +823,8 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
       a.fields[4 * nn + q] = dtt;
     }
     if constexpr ((kMode & kModeObserve) != 0) {
-      const C tn = neighbour_temperature<St, kMode>(a, src, xw, y + 1, temp, plane_b, row_b);
-      const C ts = neighbour_temperature<St, kMode>(a, src, xw, y - 1, temp, plane_b, row_b);
+      const C tn = neighbour_temperature<St, kMode>(a, msrc, Lo, xw, y + 1, temp);
+      const C ts = neighbour_temperature<St, kMode>(a, msrc, Lo, xw, y - 1, temp);
       acc[0] += dra;
       acc[1] += drb;
       acc[2] += dtt;
