@@ -161,7 +161,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--config", default="large", choices=sorted(workloads.CONFIGS))
     ap.add_argument("--precision", default="fp32", choices=sorted(BYTES_PER_POP))
-    ap.add_argument("--cpu-steps", type=int, default=2,
+    ap.add_argument("--cpu-steps", type=int, default=25,
                     help="oracle steps for the CPU baseline (0 to skip)")
     ap.add_argument("--study", choices=["precision"], default=None,
                     help="instead of the benchmark, print the precision study (storages vs the "

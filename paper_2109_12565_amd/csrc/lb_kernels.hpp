@@ -513,9 +513,31 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
 
   const int lx = a.lx, ly = a.ly;
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * BX;
-  const int y0 = blockIdx.y * a.rows_per_block;
+  // Tile order. Workgroups are dispatched to the eight XCDs round-robin by
+  // linear id, and each XCD has its own L2; the linear id is remapped so
+  // that each XCD receives a contiguous run of tiles (strip fastest), and
+  // tiles that share halo columns run on the same L2 at the same time.
+  // Odd row chunks march downwards, so two neighbouring chunks reach their
+  // shared halo rows at the same time (both at the start or both at the end).
+  const int nbx = gridDim.x;
+  const int ntiles = gridDim.x * gridDim.y;
+  const int lin = blockIdx.y * nbx + blockIdx.x;
+#if defined(TLB_NO_XCD_REMAP)
+  const int tile = lin;
+#else
+  constexpr int kXcds = 8;
+  const int xcd = lin % kXcds;
+  const int tile = xcd * (ntiles / kXcds) + min(xcd, ntiles % kXcds) + lin / kXcds;
+#endif
+  const int chunk = tile / nbx;
+  const int x0 = (tile - chunk * nbx) * BX;
+  const int y0 = chunk * a.rows_per_block;
   const int y1 = min(y0 + a.rows_per_block, ly);
+#if defined(TLB_NO_ZIGZAG)
+  const bool down = false;
+#else
+  const bool down = (chunk & 1) != 0;
+#endif
   const O row_b = (O)a.pitch * sizeof(T);
   const O plane_b = (O)a.pop_stride * sizeof(T);
   const PopMem<St, kMode> msrc(a.src, (uint64_t)plane_b * 27);
@@ -579,10 +601,10 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
   // iteration waits on memory once. With tau = tau_g = 1 the collision
   // returns the equilibria, so a kept row is only its moments.
   auto iterate = [&](int k, C (&kw)[kKept], uint32_t& lw, const C (&ku)[kKept], uint32_t lu) {
-    const int r = y0 - 2 + k;
-    const int y = r - 2;
+    const int r = down ? y1 + 1 - k : y0 - 2 + k;
+    const int y = down ? r + 2 : r - 2;
     const int slot = k % R;
-    const bool out = k >= 4 && y < y1 && own_valid;
+    const bool out = k >= 4 && y >= y0 && y < y1 && own_valid;
     const bool out_fluid = out && !((kMode & kModeSolid) != 0 && (lu & kSelfSolid));
     const O yrow = (O)(y < 0 ? 0 : y) * row_b;
     C g[9];
@@ -653,7 +675,7 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
     const int s0 = tid + 2;
     int rs[5];
 #pragma unroll
-    for (int d = 0; d < 5; ++d) rs[d] = (k + 2 + d) % R;  // d = dy + 2
+    for (int d = 0; d < 5; ++d) rs[d] = (down ? k + 6 - d : k + 2 + d) % R;  // d = dy + 2
     C FA[2], FB[2];
 #pragma unroll
     for (int l = 0; l < 2; ++l) {
@@ -861,7 +883,7 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
     if (tid < 7) {
       double v = 0;
       for (int w = 0; w < BX / 64; ++w) v += s_acc[w][tid];
-      a.partials[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 8 + tid] = v;
+      a.partials[(size_t)lin * 8 + tid] = v;
     }
   }
 }

@@ -93,11 +93,15 @@ void with_storage(int precision, F&& f) {
   }
 }
 
-// Launch geometry: 256-wide strips for wide lattices, 64-wide otherwise; the
-// rows per block are chosen so that the grid fills the GPU's resident block
-// slots about once (the occupancy of the kernel that will run), within
-// [11, 65] rows and with rows + 4 a multiple of 3 (the row loop is unrolled
-// three times). TLB_ROWS_PER_BLOCK overrides the row count.
+// Launch geometry: 256-wide strips for wide lattices, 64-wide otherwise.
+// The row-chunk height is chosen so that the grid holds a whole number of
+// blocks per compute unit, `target` of them (at most what the kernel's
+// occupancy allows): the step is a single wave of resident blocks, and an
+// uneven count leaves some CUs with one block more than others. Storages of
+// 4 bytes and more are bandwidth bound and prefer fewer, taller chunks (less
+// halo re-read): 16 wavefronts per CU (4 blocks of 256); the 16-bit
+// storages are latency bound and prefer 20. Rows are kept in [11, 65] with rows + 4 a multiple of 3 (the row loop
+// is unrolled three times). TLB_ROWS_PER_BLOCK overrides the row count.
 tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool solid, bool tau_one) {
   tlbh::Geometry l;
   const int lx = p.lx, ly = p.ly;
@@ -113,9 +117,10 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
   with_storage(p.precision, [&](auto st) {
     per_cu = tlbh::Launcher<decltype(st)>::blocks_per_cu(l.bx, l.wide, solid, tau_one);
   });
-  const long long slots = (long long)cus * per_cu;
+  const int target_waves = storage_bytes(p.precision) >= 4 ? 16 : 20;
+  const int target = std::max(1, std::min(per_cu, target_waves / (l.bx / 64)));
   const long long strips = (lx + l.bx - 1) / l.bx;
-  long long rows = (ly * strips + slots - 1) / slots;
+  long long rows = (ly * strips + (long long)cus * target - 1) / ((long long)cus * target);
   rows = rows < 11 ? 11 : (rows > 65 ? 65 : rows);
   while ((rows + 4) % 3) ++rows;
   if (const char* env = std::getenv("TLB_ROWS_PER_BLOCK")) {
