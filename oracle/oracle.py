@@ -52,6 +52,7 @@ class _Params(ctypes.Structure):
         ("t_top", ctypes.c_double),
         ("rho_wall", ctypes.c_double * 2),
         ("dt_nominal", ctypes.c_double),
+        ("u_wall", ctypes.c_double * 2),
     ]
 
 
@@ -75,6 +76,7 @@ def _load():
         lib.ora_post_collision.argtypes = [ctypes.c_void_p, dp, dp, dp]
         lib.ora_observables.argtypes = [ctypes.c_void_p, dp]
         lib.ora_load_post_collision.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.c_int64]
+        lib.ora_stress.argtypes = [ctypes.c_void_p, dp, dp]
         lib.ora_threads.restype = ctypes.c_int
         lib.ora_threads.argtypes = [ctypes.c_void_p]
         lib.ora_set_threads.argtypes = [ctypes.c_void_p, ctypes.c_int]
@@ -100,6 +102,7 @@ class ModelParams:
     t_top: float = 0.0
     rho_wall: tuple = (0.612, 0.612)
     dt_nominal: float = 1.0
+    u_wall: tuple = (0.0, 0.0)   # x-velocity of the bottom and top walls
 
 
 OBS_NAMES = ("mass_a", "mass_b", "sum_t", "nu", "nu_top", "ke")
@@ -132,6 +135,7 @@ class Oracle:
         p.alpha_g, p.t_top = params.alpha_g, params.t_top
         p.rho_wall[0], p.rho_wall[1] = params.rho_wall
         p.dt_nominal = params.dt_nominal
+        p.u_wall[0], p.u_wall[1] = params.u_wall
         self._p = p
         lib = _load()
         self._h = lib.ora_create(ctypes.byref(p), _dp(rho_a), _dp(rho_b), _dp(temp),
@@ -191,6 +195,15 @@ class Oracle:
             raise ValueError("populations must be [27, ly, lx]")
         _load().ora_load_post_collision(self._h, _dp(pop[0:9]), _dp(pop[9:18]), _dp(pop[18:27]), int(t))
         return self
+
+    def stress(self) -> dict:
+        """xy stress of the current time, (ly, lx) each: the viscous part
+        ``sxy_visc`` and the interaction pressure tensor ``pxy_int``; the
+        total stress is their difference (zero at solid cells)."""
+        ly, lx = self.shape
+        out = {k: np.empty((ly, lx)) for k in ("sxy_visc", "pxy_int")}
+        _load().ora_stress(self._h, _dp(out["sxy_visc"]), _dp(out["pxy_int"]))
+        return out
 
     def observables(self) -> dict:
         out = np.empty(6)

@@ -47,6 +47,22 @@
  *     + 2 w_i T_w, with T_w = t_bottom[column of the solid cell] for the
  *     bottom ghost rows and for solid cells flagged 1, and T_w = t_top for
  *     the top ghost rows and for solid cells flagged 2;
+ *   - moving flat walls (Sec. 2.2, the Couette set-up of Sec. 3.2.2): the
+ *     bottom and top walls move along x with u_wall[0], u_wall[1]; a link
+ *     into a moving wall is bounced back with the momentum term of a wall
+ *     moving at u_w, f_{opp i}(x,t+1) = f*_i(x,t) - 2 w_i rho_w (c_i.u_w)
+ *     / cs^2, with rho_w the node's own density sum_j f*_{l,j}(x,t) (the
+ *     terms cancel over the links of a flat wall, so mass is conserved),
+ *     and g is anti-bounced against the even part of the equilibrium at
+ *     the wall velocity, 2 w_i T_w (1 + (c_i.u_w)^2 / (2 cs^4) - u_w^2 /
+ *     (2 cs^2)); solid cells inside the lattice do not move;
+ *   - stress (Sec. 2.1 below Eq. (14), Sec. 3.2.2): the xy stress of a
+ *     node is the viscous part -(1 - 1/(2 tau)) sum_l sum_i c_ix c_iy
+ *     (f_{l,i} - f^eq_i(rho_l, u_l)) (the non-equilibrium the collision
+ *     relaxes) minus the xy component of the interaction pressure tensor
+ *     of the pseudopotential forces, 1/2 sum_l psi_l(x) sum_c G(c)
+ *     psi(x + c) c_x c_y over the stencils and couplings of Eqs. (7),
+ *     (10), (11);
  *   - Nu (Sec. 3.3.2 Eq. (24)) uses u^H, averages over fluid nodes, takes
  *     dT/dy by central differences with the mirror value 2 T_w - T at a
  *     solid neighbour, and normalises by kappa * dt_nominal / ly;
@@ -111,6 +127,7 @@ typedef struct ora_params {
   double t_top;
   double rho_wall[2];   /* wetting densities at solid nodes (Sec. 2.2.1) */
   double dt_nominal;    /* Delta T in the Nusselt normalisation */
+  double u_wall[2];     /* x-velocity of the bottom and top walls */
 } ora_params;
 
 typedef struct ora_state {
@@ -155,6 +172,16 @@ static int solid_at(const ora_state *s, int x, int y) {
 static double wall_temperature(const ora_state *s, int x, int y) {
   int fl = solid_at(s, x, y);
   return fl == 1 ? s->t_bottom[wrapx(s, x)] : s->p.t_top;
+}
+
+/* x-velocity of the solid cell in row y: the flat walls (ghost rows below
+ * and above a non-periodic lattice) move with u_wall; solid cells inside
+ * the lattice are at rest. */
+static double wall_velocity(const ora_state *s, int y) {
+  if (s->p.periodic_y) return 0.0;
+  if (y < 0) return s->p.u_wall[0];
+  if (y >= s->p.ly) return s->p.u_wall[1];
+  return 0.0;
 }
 
 static int ora_default_threads(void) {
@@ -345,10 +372,16 @@ static void stream(ora_state *s) {
         int tx = x + CX[i], ty = y + CY[i];
         if (solid_at(s, tx, ty)) {
           int o = OPP[i];
-          s->fn[0][o * n + k] = s->fs[0][i * n + k];
-          s->fn[1][o * n + k] = s->fs[1][i * n + k];
+          double uw = wall_velocity(s, ty);
+          double cu = CX[i] * uw; /* c_i . u_w, c_i pointing into the wall */
+          for (int l = 0; l < 2; ++l) {
+            double rho_w = 0;
+            for (int j = 0; j < 9; ++j) rho_w += s->fs[l][j * n + k];
+            s->fn[l][o * n + k] = s->fs[l][i * n + k] - 2.0 * WGT[i] * rho_w * cu / CS2;
+          }
+          double even = 1.0 + cu * cu / (2.0 * CS2 * CS2) - uw * uw / (2.0 * CS2);
           s->gn[o * n + k] =
-              -s->gs[i * n + k] + 2.0 * WGT[i] * wall_temperature(s, tx, ty);
+              -s->gs[i * n + k] + 2.0 * WGT[i] * wall_temperature(s, tx, ty) * even;
         } else {
           int txw = wrapx(s, tx), tyw = ty;
           if (s->p.periodic_y) {
@@ -548,6 +581,51 @@ void ora_observables(ora_state *s, double *out) {
   out[3] = (uyt * inv - kappa * dyt * inv) / (kappa * s->p.dt_nominal / ly);
   out[4] = ntop ? 2.0 * ly / s->p.dt_nominal * (top / (double)ntop) : 0.0;
   out[5] = ke * inv;
+}
+
+/* xy stress at the current time (fluid nodes; zero at solid cells), two
+ * [ly][lx] arrays, either may be NULL:
+ *   sxy_visc  -(1 - 1/(2 tau)) sum_l sum_i c_ix c_iy (f_{l,i} - f^eq_i(rho_l, u_l))
+ *   pxy_int   1/2 sum_l [ psi_s,l(x) sum_c (G^a_l w(c) + G^r_l p(c))
+ *             psi_s,l(x+c) c_x c_y + G12 psi_x,l(x) sum_c w(c) psi_x,m(x+c)
+ *             c_x c_y ]   (m the other component)
+ * The total xy stress of the rheology is sxy_visc - pxy_int. */
+void ora_stress(ora_state *s, double *sxy_visc, double *pxy_int) {
+  macroscopic(s);
+  int lx = s->p.lx, ly = s->p.ly, n = s->n;
+  double tau = s->p.tau;
+  for (int y = 0; y < ly; ++y) {
+    for (int x = 0; x < lx; ++x) {
+      int k = y * lx + x;
+      double sv = 0, pi = 0;
+      if (!s->solid[k]) {
+        double rho = s->rho[0][k] + s->rho[1][k];
+        double ux = s->jx[k] / rho, uy = s->jy[k] / rho;
+        for (int l = 0; l < 2; ++l) {
+          double rl = s->rho[l][k];
+          double ulx = ux + tau * s->fx[l][k] / rl;
+          double uly = uy + tau * s->fy[l][k] / rl;
+          double neq = 0;
+          for (int i = 0; i < 9; ++i)
+            neq += CX[i] * CY[i] * (s->f[l][i * n + k] - equilibrium(i, rl, ulx, uly));
+          sv += -(1.0 - 0.5 / tau) * neq;
+          int m = 1 - l;
+          double self = 0, cross = 0;
+          for (int dy = -2; dy <= 2; ++dy)
+            for (int dx = -2; dx <= 2; ++dx) {
+              int c2 = dx * dx + dy * dy;
+              double gw = s->p.g_a[l] * w_of(c2) + s->p.g_r[l] * p_of(c2);
+              self += gw * padded(s, s->psi_s[l], x + dx, y + dy) * dx * dy;
+              cross += w_of(c2) * padded(s, s->psi_x[m], x + dx, y + dy) * dx * dy;
+            }
+          pi += 0.5 * padded(s, s->psi_s[l], x, y) * self;
+          pi += 0.5 * s->p.g12 * padded(s, s->psi_x[l], x, y) * cross;
+        }
+      }
+      if (sxy_visc) sxy_visc[k] = sv;
+      if (pxy_int) pxy_int[k] = pi;
+    }
+  }
 }
 
 /* Replace the state by the streaming of the given post-collision
