@@ -169,6 +169,8 @@ def main() -> int:
     ap.add_argument("--adjoint-steps", type=int, default=500,
                     help="steps of the adjoint/forward time ratio on the 1024x512 emulsion "
                          "(FP32, checkpoints every 25; 0 to skip)")
+    ap.add_argument("--u-wall", type=float, nargs=2, default=(0.0, 0.0), metavar=("UB", "UT"),
+                    help="x-velocity of the bottom and top walls (Couette walls)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before warmup, run 3 plain device copies of this many MiB (a known "
                          "traffic reference for hardware counters)")
@@ -200,7 +202,8 @@ def main() -> int:
     w = workloads.CONFIGS[args.config]()
     print(f"# bench: {w['name']} {args.precision} warmup={args.warmup} steps={args.steps}",
           file=sys.stderr, flush=True)
-    sim = Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+    params = dict(w["params"], u_wall=tuple(args.u_wall))
+    sim = Simulation(params, w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
                      t_bottom=w["t_bottom"], precision=args.precision)
     sim.step(args.warmup)
     sim.observables()
@@ -217,6 +220,12 @@ def main() -> int:
     e2.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
+    # stress fields + row averages of the same time level (Couette rheology
+    # observables): one pass of the step kernel without store, then the row
+    # reduction and the copy of 2 * ly doubles (synchronising)
+    t_rows = time.perf_counter()
+    rows = sim.row_averages()
+    t_rows = time.perf_counter() - t_rows
     step_ms = e0.elapsed_time(e1)          # the K step launches only
     total_ms = e0.elapsed_time(e2)         # whole job: steps + observables
 
@@ -244,10 +253,12 @@ def main() -> int:
         "config": {"workload": w["name"], "lx": w["lx"], "ly": w["ly"], "storage": args.precision,
                    "droplets": int(w["n_droplets"]), "solid_cells": 0 if w["solid"] is None
                    else int((w["solid"] != 0).sum()), "observables": "once at the end",
-                   "seed": w["seed"]},
+                   "u_wall": list(args.u_wall), "seed": w["seed"]},
         "roofline": roof,
         "check": {"mass_a": obs["mass_a"], "mass_b": obs["mass_b"], "nu": obs["nu"],
                   "wall_s": round(wall, 3)},
+        "row_averages": {"ms": round(t_rows * 1e3, 3), "pxy_av_mean": float(np.mean(rows["pxy_av"])),
+                         "u_av_top": float(rows["u_av"][-1])},
     }
     sim.close()
     if args.adjoint_steps > 0:

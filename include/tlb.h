@@ -88,6 +88,13 @@ typedef struct tlb_params {
   double dt_nominal;     /* Delta T in the Nusselt normalisation, != 0 */
   double rho_ref[2];     /* reference densities of the 16-bit storages */
   double t_ref;          /* reference temperature of the 16-bit storages */
+  double u_wall[2];      /* x-velocity of the bottom and top walls (Couette
+                            walls, Sec. 2.2 and Sec. 3.2.2); 0 for walls at
+                            rest. A link into a moving wall is bounced back
+                            with the momentum term 6 w_i rho c_ix u_w (rho the
+                            boundary node's own density) and g against
+                            2 w_i T_w (1 + 4.5 (c_i.u_w)^2 - 1.5 u_w^2);
+                            solid cells inside the lattice do not move */
 } tlb_params;
 
 /* Observables at time `step` (Sec. 3.1, Sec. 3.3.2 Eq. (24)); sums and means
@@ -141,6 +148,25 @@ int tlb_observables(tlb_handle *h, tlb_obs *out);
 int tlb_get_fields(tlb_handle *h, double *rho_a, double *rho_b, double *ux,
                    double *uy, double *temp);
 
+/* xy stress at the current time into host arrays of ly*lx doubles (either
+ * may be NULL; zero at solid nodes). The total stress of the rheology
+ * (Sec. 2.1 below Eq. (14), Sec. 3.2.2) is sxy_visc - pxy_int:
+ *   sxy_visc  viscous part -(1 - 1/(2 tau)) sum_l sum_i c_ix c_iy
+ *             (f_{l,i} - f^eq_i(rho_l, u_l)) of the pre-collision f(t)
+ *   pxy_int   xy component of the interaction pressure tensor of the forces
+ *             of Eqs. (7), (10), (11): 1/2 sum_l [psi_l(x) sum_c (G^a_l w(c)
+ *             + G^r_l p(c)) psi_l(x+c) c_x c_y + G12 (rho_l(x)/rho0)
+ *             sum_c w(c) (rho_m(x+c)/rho0) c_x c_y], m the other component
+ * Synchronises the stream. */
+int tlb_get_stress(tlb_handle *h, double *sxy_visc, double *pxy_int);
+
+/* Row averages over the fluid nodes of each row at the current time (the
+ * x-averaged profiles of the Couette rheology, Sec. 3.2.2): u_av[y] = mean
+ * of u^H_x, pxy_av[y] = mean of sxy_visc - pxy_int (see tlb_get_stress).
+ * Host arrays of ly doubles, either may be NULL; rows without fluid report
+ * 0. Deterministic (fixed-order FP64 sums). Synchronises the stream. */
+int tlb_row_averages(tlb_handle *h, double *u_av, double *pxy_av);
+
 /* Post-collision populations f*(t) of the current time (the state the next
  * step streams) as host doubles [27][ly][lx]; zero at solid nodes.
  * Synchronises the stream. */
@@ -163,8 +189,8 @@ int tlb_set_bottom_temperature(tlb_handle *h, const double *t_bottom);
  * next tlb_forward_taped, tlb_set_bottom_temperature or tlb_destroy; later
  * tlb_step calls do not touch it. Checkpoint memory is
  * ceil(nsteps / ckpt_every) copies of the state. Synchronises the stream.
- * Errors: TLB_EINVAL (solid cells, 16-bit storage, bad counts, state buffer
- * of 4 GiB or more, ly > 65535), TLB_ENOMEM, TLB_EDEVICE. */
+ * Errors: TLB_EINVAL (solid cells, moving walls, 16-bit storage, bad counts,
+ * state buffer of 4 GiB or more, ly > 65535), TLB_ENOMEM, TLB_EDEVICE. */
 int tlb_forward_taped(tlb_handle *h, int64_t nsteps, int32_t ckpt_every, double *loss);
 
 /* Reverse sweep of the taped run: grad_t_bottom (host, lx doubles) receives

@@ -21,9 +21,9 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "fp16dev": 2, "bf16dev": 3, "fix16dev": 4}
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = (
-    "tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_populations",
-    "tlb_set_bottom_temperature", "tlb_forward_taped", "tlb_adjoint_step", "tlb_time",
-    "tlb_destroy", "tlb_last_error",
+    "tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_stress",
+    "tlb_row_averages", "tlb_get_populations", "tlb_set_bottom_temperature",
+    "tlb_forward_taped", "tlb_adjoint_step", "tlb_time", "tlb_destroy", "tlb_last_error",
 )
 
 
@@ -43,6 +43,7 @@ class Params(ctypes.Structure):
         ("alpha_g", ctypes.c_double), ("t_top", ctypes.c_double),
         ("rho_wall", ctypes.c_double * 2), ("dt_nominal", ctypes.c_double),
         ("rho_ref", ctypes.c_double * 2), ("t_ref", ctypes.c_double),
+        ("u_wall", ctypes.c_double * 2),
     ]
 
 
@@ -77,6 +78,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tlb_observables.argtypes = [vp, ctypes.POINTER(Obs)]
     lib.tlb_get_fields.argtypes = [vp, dp, dp, dp, dp, dp]
     lib.tlb_get_populations.argtypes = [vp, dp]
+    lib.tlb_get_stress.argtypes = [vp, dp, dp]
+    lib.tlb_row_averages.argtypes = [vp, dp, dp]
     lib.tlb_set_bottom_temperature.argtypes = [vp, dp]
     lib.tlb_forward_taped.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, dp]
     lib.tlb_adjoint_step.argtypes = [vp, ctypes.c_int64, ctypes.c_double, dp]
@@ -85,9 +88,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tlb_destroy.argtypes = [vp]
     lib.tlb_last_error.argtypes = [vp]
     lib.tlb_last_error.restype = ctypes.c_char_p
-    for name in ("tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_populations",
-                 "tlb_set_bottom_temperature", "tlb_forward_taped", "tlb_adjoint_step",
-                 "tlb_destroy"):
+    for name in ("tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_stress",
+                 "tlb_row_averages", "tlb_get_populations", "tlb_set_bottom_temperature",
+                 "tlb_forward_taped", "tlb_adjoint_step", "tlb_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -123,7 +126,8 @@ class Simulation:
     ``params`` holds the model constants named as in ``tlb_params`` (tau,
     tau_g, rho0, g12, g_a, g_r, alpha_g, t_top, rho_wall, dt_nominal, and
     optionally rho_ref, t_ref for the 16-bit storages: by default rho0 for
-    both components and the mean of the two wall temperatures).
+    both components and the mean of the two wall temperatures; u_wall, the
+    x-velocities of the bottom and top walls, by default at rest).
     Field arrays are (ly, lx) with x fastest. By default the work runs on
     torch's current stream.
     """
@@ -165,6 +169,7 @@ class Simulation:
         rr = params.get("rho_ref", (params["rho0"], params["rho0"]))
         p.rho_ref[0], p.rho_ref[1] = rr
         p.t_ref = params.get("t_ref", 0.5 * (float(np.mean(t_bottom)) + params["t_top"]))
+        p.u_wall[0], p.u_wall[1] = params.get("u_wall", (0.0, 0.0))
         self.params = p
         self.precision = precision
         s = _current_stream() if stream == "torch" else stream
@@ -197,6 +202,22 @@ class Simulation:
         out = {k: np.empty((ly, lx)) for k in ("rho_a", "rho_b", "ux", "uy", "temp")}
         self._check(self._lib.tlb_get_fields(self._h, *(_dp(out[k]) for k in
                                                        ("rho_a", "rho_b", "ux", "uy", "temp"))))
+        return out
+
+    def stress(self) -> dict:
+        """xy stress of the current time, (ly, lx) each: the viscous part
+        ``sxy_visc`` and the interaction pressure tensor ``pxy_int`` (the
+        total stress is their difference)."""
+        ly, lx = self.shape
+        out = {k: np.empty((ly, lx)) for k in ("sxy_visc", "pxy_int")}
+        self._check(self._lib.tlb_get_stress(self._h, _dp(out["sxy_visc"]), _dp(out["pxy_int"])))
+        return out
+
+    def row_averages(self) -> dict:
+        """Fluid-node means of u^H_x and of the total xy stress per row, (ly,)."""
+        ly = self.shape[0]
+        out = {"u_av": np.empty(ly), "pxy_av": np.empty(ly)}
+        self._check(self._lib.tlb_row_averages(self._h, _dp(out["u_av"]), _dp(out["pxy_av"])))
         return out
 
     def populations(self) -> np.ndarray:

@@ -92,7 +92,7 @@ __device__ inline void adj_pull_node(const AdjArgs<typename St::C>& a, int x, in
   const uint32_t lm = link_mask<0u>(a.s, x, y);
   const PopMem<St, 0u> m(a.state, (uint64_t)plane_b * 27);
   const LaneOff<0u> L = lane_off<St, 0u>(x, a.s.lx, plane_b, row_b);
-  pull_fluid<St, 0u>(m, L, y, lm, f);
+  pull_fluid<St, 0u>(a.s, m, L, y, lm, f);
   pull_thermal<St, 0u>(a.s, m, L, x, y, lm, g);
 }
 

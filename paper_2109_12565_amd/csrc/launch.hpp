@@ -26,6 +26,7 @@ struct Device {
   long long pop_stride = 0;
   bool has_solid = false;
   bool tau_one = false;            // tau = tau_g = 1 path
+  bool moving = false;             // a flat wall moves (u_wall != 0)
   const uint16_t* link = nullptr;
   const uint8_t* solid = nullptr;
   const void* t_bottom = nullptr;  // compute-type copy of the bottom temperature
@@ -40,7 +41,9 @@ enum class Pass {
   kObserve,      // observable sums of time t from f*(t-1), no store
   kObserveInit,  // same at t = 0 from f(0)
   kFields,       // fields of time t from f*(t-1), no store
-  kFieldsInit    // same at t = 0 from f(0)
+  kFieldsInit,   // same at t = 0 from f(0)
+  kStress,       // fields and xy stress of time t (general path), no store
+  kStressInit    // same at t = 0 from f(0)
 };
 
 template <class St>

@@ -41,6 +41,8 @@ tlbk::StepArgs<C> make_args(const Device& d, const void* src, void* dst) {
   a.ref_a = C(p.rho_ref[0]);
   a.ref_b = C(p.rho_ref[1]);
   a.ref_t = C(p.t_ref);
+  a.uw0 = C(p.u_wall[0]);
+  a.uw1 = C(p.u_wall[1]);
   return a;
 }
 
@@ -58,18 +60,35 @@ void launch_geometry(const Device& d, const tlbk::StepArgs<typename St::C>& a) {
   else launch<St, 64, kMode>(d, a);
 }
 
-// Dispatch on solid cells and on the tau = tau_g = 1 path.
+// Dispatch on solid cells and on the tau = tau_g = 1 path (never for the
+// stress pass, which needs the pulled populations themselves).
 template <class St, unsigned kMode>
-void launch_mode(const Device& d, const void* src, void* dst) {
-  const auto a = make_args<typename St::C>(d, src, dst);
+void launch_solid_tau(const Device& d, const tlbk::StepArgs<typename St::C>& a) {
   constexpr unsigned S = tlbk::kModeSolid, T1 = tlbk::kModeTauOne;
-  if (d.has_solid) {
+  if constexpr ((kMode & tlbk::kModeStress) != 0) {
+    if (d.has_solid) launch_geometry<St, kMode | S>(d, a);
+    else launch_geometry<St, kMode>(d, a);
+  } else if (d.has_solid) {
     if (d.tau_one) launch_geometry<St, kMode | S | T1>(d, a);
     else launch_geometry<St, kMode | S>(d, a);
   } else {
     if (d.tau_one) launch_geometry<St, kMode | T1>(d, a);
     else launch_geometry<St, kMode>(d, a);
   }
+}
+
+// Dispatch on moving walls (a separate kernel, so walls at rest pay nothing
+// for it; passes that read f(0) in place pull nothing and need no variant).
+template <class St, unsigned kMode>
+void launch_mode(const Device& d, const void* src, void* dst) {
+  const auto a = make_args<typename St::C>(d, src, dst);
+  if constexpr ((kMode & tlbk::kModeInit) == 0) {
+    if (d.moving) {
+      launch_solid_tau<St, kMode | tlbk::kModeMoving>(d, a);
+      return;
+    }
+  }
+  launch_solid_tau<St, kMode>(d, a);
 }
 
 template <class St, int BX, unsigned kMode>
@@ -113,6 +132,10 @@ void Launcher<St>::step(const Device& d, Pass pass, const void* src, void* dst) 
     case Pass::kObserveInit: detail::launch_mode<St, kModeObserve | kModeInit>(d, src, dst); break;
     case Pass::kFields: detail::launch_mode<St, kModeFields>(d, src, dst); break;
     case Pass::kFieldsInit: detail::launch_mode<St, kModeFields | kModeInit>(d, src, dst); break;
+    case Pass::kStress: detail::launch_mode<St, kModeFields | kModeStress>(d, src, dst); break;
+    case Pass::kStressInit:
+      detail::launch_mode<St, kModeFields | kModeStress | kModeInit>(d, src, dst);
+      break;
   }
 }
 

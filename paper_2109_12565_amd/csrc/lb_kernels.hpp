@@ -100,6 +100,7 @@ template <typename T_> struct Store {
   using C = T_;
   static constexpr bool kDev = false;
   static constexpr bool kFix = false;
+  static constexpr bool kFast = false;  // library expm1, IEEE division
   __device__ static C decode(T v) { return v; }
   __device__ static T encode(C v) { return v; }
   __device__ static C load(const T* p) { return decode(*p); }
@@ -113,6 +114,7 @@ struct StoreF16Dev {
   using C = float;
   static constexpr bool kDev = true;
   static constexpr bool kFix = false;
+  static constexpr bool kFast = true;   // cheaper psi and reciprocals
   __device__ static C grid(C v) { return v; }
   __device__ static C decode(T v) { return (float)__builtin_bit_cast(_Float16, v); }
   __device__ static T encode(C v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
@@ -125,6 +127,7 @@ struct StoreBF16Dev {
   using C = float;
   static constexpr bool kDev = true;
   static constexpr bool kFix = false;
+  static constexpr bool kFast = true;   // cheaper psi and reciprocals
   __device__ static C grid(C v) { return v; }
   __device__ static C decode(T v) { return __uint_as_float((uint32_t)v << 16); }
   __device__ static T encode(C v) {
@@ -146,6 +149,7 @@ struct StoreFix16Dev {
   using C = float;
   static constexpr bool kDev = true;
   static constexpr bool kFix = true;
+  static constexpr bool kFast = true;   // cheaper psi and reciprocals
   static constexpr float kScale = 32768.0f;
   __device__ static C decode(T v) { return (float)v * (1.0f / kScale); }
   __device__ static T encode(C v) { return (int16_t)(int)(v * kScale); }  // v is on the grid
@@ -173,6 +177,7 @@ struct StepArgs {
   C ga0, ga1, gr0, gr1;
   C alpha_g, t_top, rho_wall0, rho_wall1;
   C ref_a, ref_b, ref_t;    // references of the 16-bit deviation storages
+  C uw0, uw1;               // x-velocity of the bottom and top walls (kModeMoving)
 };
 
 // Kernel variants.
@@ -183,17 +188,24 @@ enum : unsigned {
   kModeFields = 8u,   // write the fields
   kModeSolid = 16u,   // solid cells present: use the link masks
   kModeWide = 32u,    // 64-bit byte offsets (population buffer >= 4 GiB)
-  kModeTauOne = 64u   // tau = tau_g = 1: the collision returns the equilibria
+  kModeTauOne = 64u,  // tau = tau_g = 1: the collision returns the equilibria
+  kModeStress = 128u, // with kModeFields: also write the xy stress fields
+  kModeMoving = 256u  // the flat walls move (momentum term in their bounce-back)
 };
 
+// rho0 (1 - exp(-rho/rho0)) of Eq. (12), evaluated as -rho0 expm1(-rho/rho0)
+// to keep full relative precision at small rho (library expm1).
 template <typename C> __device__ inline C psi_exp(C rho, C rho0, C inv_rho0) {
-  // rho0 (1 - exp(-rho/rho0)) of Eq. (12), evaluated as -rho0 expm1(-rho/rho0)
-  // to keep full relative precision at small rho.
   return -rho0 * expm1(-rho * inv_rho0);
 }
-// FP32: e^x - 1 by its Taylor polynomial of degree 8 for |x| <= 1/2
-// (truncation below 1e-8 relative) and from the hardware exp2 elsewhere,
-// where 1 - e^x >= 0.39 leaves no cancellation.
+__device__ inline float psi_exp(float rho, float rho0, float inv_rho0) {
+  return -rho0 * expm1f(-rho * inv_rho0);
+}
+// e^x - 1 for the 16-bit storages (whose rounding dominates any error
+// here): its Taylor polynomial of degree 8 for |x| <= 1/2 (truncation below
+// 1e-8 relative) and the hardware exp2 elsewhere, where 1 - e^x >= 0.39
+// leaves no cancellation. About half the instructions of expm1f; FP32
+// storage keeps the library function, whose errors do not share a sign.
 __device__ inline float expm1_fast(float x) {
   float p = fmaf(x, 1.0f / 40320.0f, 1.0f / 5040.0f);
   p = fmaf(x, p, 1.0f / 720.0f);
@@ -206,14 +218,19 @@ __device__ inline float expm1_fast(float x) {
   const float large = __builtin_amdgcn_exp2f(x * 1.44269504088896341f) - 1.0f;
   return fabsf(x) <= 0.5f ? small : large;
 }
-__device__ inline float psi_exp(float rho, float rho0, float inv_rho0) {
-  return -rho0 * expm1_fast(-rho * inv_rho0);
+// psi_s and reciprocals as a storage policy computes them: library expm1
+// and IEEE division, or the cheaper forms for the 16-bit storages (kFast).
+template <class St>
+__device__ inline typename St::C psi_of(typename St::C rho, typename St::C rho0,
+                                        typename St::C inv_rho0) {
+  if constexpr (St::kFast) return -rho0 * expm1_fast(-rho * inv_rho0);
+  else return psi_exp(rho, rho0, inv_rho0);
 }
-
-// Reciprocal: the hardware approximation (1 ulp) in FP32, IEEE division in
-// FP64.
-template <typename C> __device__ inline C recip(C v) { return C(1) / v; }
-template <> __device__ inline float recip<float>(float v) { return __builtin_amdgcn_rcpf(v); }
+template <class St>
+__device__ inline typename St::C recip(typename St::C v) {
+  if constexpr (St::kFast) return __builtin_amdgcn_rcpf(v);  // 1 ulp
+  else return typename St::C(1) / v;
+}
 
 template <unsigned kMode>
 using Off = std::conditional_t<(kMode & kModeWide) != 0, uint64_t, uint32_t>;
@@ -381,12 +398,68 @@ __device__ inline C source_wall_temperature(const StepArgs<C>& a, int x, int r) 
   return a.t_top;
 }
 
+// Momentum term of moving flat walls (the Couette walls of Sec. 2.2): a
+// population bounced back at a wall that moves with u_w along x gains
+// 6 w_i rho_w c_ix u_w, rho_w the node's own density at the previous time
+// level (the sum of its post-collision populations). Only the diagonal links
+// carry it (c_ix = 0 on the straight one), and the two diagonals of a wall
+// cancel, so mass is conserved. Row 0 sees the bottom wall, row ly - 1 the
+// top one; solid cells inside the lattice do not move.
+template <class St, unsigned kMode, typename C>
+__device__ inline void moving_wall_fluid(const StepArgs<C>& a, const PopMem<St, kMode>& m,
+                                         const LaneOff<kMode>& L, int r, C (&f)[18]) {
+  using O = Off<kMode>;
+  const O p9 = L.plane_b * 9;
+  C ra = 0, rb = 0;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const O s = (O)j * L.plane_b + (O)r * L.row_b;
+    ra += m.ld(s, L.v0);
+    rb += m.ld(s + p9, L.v0);
+  }
+  if constexpr (St::kDev) {
+    ra += a.ref_a;
+    rb += a.ref_b;
+  }
+  if (r == 0) {  // links 5 (c_x = +1) and 6 (c_x = -1) come from the bottom wall
+    const C k = C(6) * w_dir<C>(5) * a.uw0;
+    f[5] = St::grid(f[5] + k * ra);
+    f[14] = St::grid(f[14] + k * rb);
+    f[6] = St::grid(f[6] - k * ra);
+    f[15] = St::grid(f[15] - k * rb);
+  }
+  if (r == a.ly - 1) {  // links 8 (c_x = +1) and 7 (c_x = -1) from the top wall
+    const C k = C(6) * w_dir<C>(8) * a.uw1;
+    f[8] = St::grid(f[8] + k * ra);
+    f[17] = St::grid(f[17] + k * rb);
+    f[7] = St::grid(f[7] - k * ra);
+    f[16] = St::grid(f[16] - k * rb);
+  }
+}
+
+// Factor of the wall temperature in the anti-bounce-back of direction I at
+// row r: the even part of the equilibrium at the wall velocity,
+// 1 + 4.5 (c_I.u_w)^2 - 1.5 u_w^2, for a link whose source is a moving flat
+// wall; 1 otherwise.
+template <int I, unsigned kMode, typename C>
+__device__ inline C wall_even_factor(const StepArgs<C>& a, int r) {
+  if constexpr ((kMode & kModeMoving) == 0) {
+    return C(1);
+  } else {
+    constexpr int cx = Dir<I>::cx, cy = Dir<I>::cy;
+    const int sr = r - cy;
+    if (sr >= 0 && sr < a.ly) return C(1);
+    const C u = sr < 0 ? a.uw0 : a.uw1;
+    return C(1) + (C(4.5) * C(cx * cx) - C(1.5)) * u * u;
+  }
+}
+
 // Pull f_A (f[0..8]) and f_B (f[9..17]) of row r at lane column L, in
 // stored form. Opposite directions have equal weights, so a bounced value
 // keeps its deviation reference.
 template <class St, unsigned kMode, typename C>
-__device__ inline void pull_fluid(const PopMem<St, kMode>& m, const LaneOff<kMode>& L, int r,
-                                  uint32_t lm, C (&f)[18]) {
+__device__ inline void pull_fluid(const StepArgs<C>& a, const PopMem<St, kMode>& m,
+                                  const LaneOff<kMode>& L, int r, uint32_t lm, C (&f)[18]) {
   using O = Off<kMode>;
   const O p9 = L.plane_b * 9;
   if constexpr ((kMode & kModeInit) != 0) {
@@ -408,6 +481,9 @@ __device__ inline void pull_fluid(const PopMem<St, kMode>& m, const LaneOff<kMod
     TLB_PULL_F(0, true) TLB_PULL_F(1, true) TLB_PULL_F(2, true) TLB_PULL_F(3, true)
     TLB_PULL_F(4, true) TLB_PULL_F(5, true) TLB_PULL_F(6, true) TLB_PULL_F(7, true)
     TLB_PULL_F(8, true)
+    if constexpr ((kMode & kModeMoving) != 0) {
+      if (r == 0 || r == a.ly - 1) moving_wall_fluid(a, m, L, r, f);
+    }
   } else {
     TLB_PULL_F(0, false) TLB_PULL_F(1, false) TLB_PULL_F(2, false) TLB_PULL_F(3, false)
     TLB_PULL_F(4, false) TLB_PULL_F(5, false) TLB_PULL_F(6, false) TLB_PULL_F(7, false)
@@ -437,7 +513,7 @@ __device__ inline void pull_thermal(const StepArgs<C>& a, const PopMem<St, kMode
     C v = m.ld(o.s, o.v);                                                         \
     if constexpr (B && I != 0) {                                                  \
       if (bb) {                                                                   \
-        C tw = source_wall_temperature<I, kMode>(a, x, r);                        \
+        C tw = source_wall_temperature<I, kMode>(a, x, r) * wall_even_factor<I, kMode>(a, r); \
         if constexpr (St::kDev) tw -= a.ref_t;                                    \
         v = St::grid(C(2) * w_dir<C>(I) * tw - v);                                \
       }                                                                           \
@@ -560,8 +636,8 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
   const LaneOff<kMode> Lo = lane_off<St, kMode>(xw, lx, plane_b, row_b);
   const LaneOff<kMode> Lh = lane_off<St, kMode>(hx, lx, plane_b, row_b);
 
-  const C psi_w0 = psi_exp(a.rho_wall0, a.rho0, a.inv_rho0);
-  const C psi_w1 = psi_exp(a.rho_wall1, a.rho0, a.inv_rho0);
+  const C psi_w0 = psi_of<St>(a.rho_wall0, a.rho0, a.inv_rho0);
+  const C psi_w1 = psi_of<St>(a.rho_wall1, a.rho0, a.inv_rho0);
 
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
 
@@ -576,15 +652,15 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
     if (r >= 0 && r < ly) {
       lm = link_mask<kMode>(a, x, r);
       if (!((kMode & kModeSolid) != 0 && (lm & kSelfSolid))) {
-        pull_fluid<St, kMode>(msrc, L, r, lm, f);
+        pull_fluid<St, kMode>(a, msrc, L, r, lm, f);
         ra = sum9(f);
         rb = sum9(f + 9);
         if constexpr (St::kDev) {
           ra += a.ref_a;
           rb += a.ref_b;
         }
-        pa = psi_exp(ra, a.rho0, a.inv_rho0);
-        pb = psi_exp(rb, a.rho0, a.inv_rho0);
+        pa = psi_of<St>(ra, a.rho0, a.inv_rho0);
+        pb = psi_of<St>(rb, a.rho0, a.inv_rho0);
         pulled = true;
       }
     }
@@ -644,6 +720,10 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
         a.fields[2 * nn + q] = 0.0;
         a.fields[3 * nn + q] = 0.0;
         a.fields[4 * nn + q] = (double)solid_temperature(a, xo, y);
+        if constexpr ((kMode & kModeStress) != 0) {
+          a.fields[5 * nn + q] = 0.0;
+          a.fields[6 * nn + q] = 0.0;
+        }
       }
       return;
     }
@@ -734,14 +814,14 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
 
     // ---- velocities
     const C rho = ra + rb;
-    const C inv_rho = recip(rho);
+    const C inv_rho = recip<St>(rho);
     const C ux = jx * inv_rho, uy = jy * inv_rho;
     const C Fx = FA[0] + FB[0], Fy = FA[1] + FB[1];
     const C hx = ux + C(0.5) * Fx * inv_rho;
     const C hy = uy + C(0.5) * Fy * inv_rho;
 
     if constexpr ((kMode & kModeStore) != 0) {
-      const C tA = a.tau * recip(ra), tB = a.tau * recip(rb);
+      const C tA = a.tau * recip<St>(ra), tB = a.tau * recip<St>(rb);
       const C uax = ux + FA[0] * tA, uay = uy + FA[1] * tA;
       const C ubx = ux + FB[0] * tB, uby = uy + FB[1] * tB;
       const C ua2 = uax * uax + uay * uay;
@@ -843,6 +923,49 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
       a.fields[2 * nn + q] = (double)hx;
       a.fields[3 * nn + q] = (double)hy;
       a.fields[4 * nn + q] = dtt;
+      if constexpr ((kMode & kModeStress) != 0) {
+        static_assert(!kTauOne, "the stress needs the pulled populations");
+        // viscous part: -(1 - 1/(2 tau)) sum_l sum_i c_ix c_iy (f_{l,i} -
+        // f^eq_i(rho_l, u_l)); the deviation references carry no xy moment
+        const C tA = a.tau * recip<St>(ra), tB = a.tau * recip<St>(rb);
+        const C uax = ux + FA[0] * tA, uay = uy + FA[1] * tA;
+        const C ubx = ux + FB[0] * tB, uby = uy + FB[1] * tB;
+        const C pia = (fa[5] + fa[7]) - (fa[6] + fa[8]);
+        const C pib = (fb[5] + fb[7]) - (fb[6] + fb[8]);
+        const C visc = -(C(1) - C(0.5) * a.inv_tau) * ((pia - ra * uax * uay) + (pib - rb * ubx * uby));
+        // interaction pressure tensor: 1/2 sum_l psi_l(x) sum_c G(c) psi_l(x+c)
+        // c_x c_y (self) and 1/2 G12 sum_l psi_x,l(x) sum_c w(c) psi_x,m(x+c)
+        // c_x c_y (cross); c and -c share c_x c_y, so each pair is one term
+        C pint = 0;
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+          const C ga = l == 0 ? a.ga0 : a.ga1;
+          const C gr = l == 0 ? a.gr0 : a.gr1;
+          C self = 0;
+#pragma unroll
+          for (int dx = 1; dx <= 2; ++dx) {
+#pragma unroll
+            for (int dy = -2; dy <= 2; ++dy) {
+              if (dy == 0) continue;
+              const int c2 = dx * dx + dy * dy;
+              const C gw = ga * w_c2<C>(c2) + gr * p_c2<C>(c2);
+              self += gw * C(dx * dy) *
+                      (s_psi[l][rs[dy + 2]][s0 + dx] + s_psi[l][rs[2 - dy]][s0 - dx]);
+            }
+          }
+          const int m = 1 - l;
+          C cross = 0;
+#pragma unroll
+          for (int dy = -1; dy <= 1; dy += 2)
+            cross += w_c2<C>(2) * C(dy) *
+                     (s_rho[m][rs[dy + 2]][s0 + 1] + s_rho[m][rs[2 - dy]][s0 - 1]);
+          const C rl = l == 0 ? ra : rb;
+          pint += C(0.5) * s_psi[l][rs[2]][s0] * self +
+                  C(0.5) * a.g12 * a.inv_rho0 * a.inv_rho0 * rl * cross;
+        }
+        a.fields[5 * nn + q] = (double)visc;
+        a.fields[6 * nn + q] = (double)pint;
+      }
     }
     if constexpr ((kMode & kModeObserve) != 0) {
       const C tn = neighbour_temperature<St, kMode>(a, msrc, Lo, xw, y + 1, temp);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 
 namespace tlbk {
 
@@ -36,6 +37,42 @@ __global__ __launch_bounds__(256) void lb_reduce_observables(ObsArgs a) {
     a.out[3] = (s[3][0] * inv - a.kappa * s[4][0] * inv) / (a.kappa * a.dt_nominal / a.ly);
     a.out[4] = a.n_top > 0 ? 2.0 * a.ly / a.dt_nominal * (s[6][0] / a.n_top) : 0.0;
     a.out[5] = s[5][0] * inv;
+  }
+}
+
+// Row averages over fluid nodes (the x-averages of the Couette rheology):
+// one block per row sums u^H_x (field plane 2) and the total xy stress
+// (plane 5 minus plane 6) in a fixed order. Rows without fluid report 0.
+__global__ __launch_bounds__(256) void lb_row_averages(const double* __restrict__ fields,
+                                                       const uint8_t* __restrict__ solid, int lx,
+                                                       int ly, double* __restrict__ u_av,
+                                                       double* __restrict__ pxy_av) {
+  __shared__ double su[256], sp[256], sn[256];
+  const int tid = threadIdx.x, y = blockIdx.x;
+  const size_t nn = (size_t)lx * ly;
+  double u = 0, pxy = 0, n = 0;
+  for (int x = tid; x < lx; x += 256) {
+    const size_t q = (size_t)y * lx + x;
+    if (solid[q] != 0) continue;
+    u += fields[2 * nn + q];
+    pxy += fields[5 * nn + q] - fields[6 * nn + q];
+    n += 1.0;
+  }
+  su[tid] = u;
+  sp[tid] = pxy;
+  sn[tid] = n;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      su[tid] += su[tid + h];
+      sp[tid] += sp[tid + h];
+      sn[tid] += sn[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    u_av[y] = sn[0] > 0 ? su[0] / sn[0] : 0.0;
+    pxy_av[y] = sn[0] > 0 ? sp[0] / sn[0] : 0.0;
   }
 }
 

@@ -38,7 +38,8 @@ struct tlb_handle {
   void* t_bottom = nullptr;        // C-typed copy of the bottom temperature
   double* partials = nullptr;
   double* obs = nullptr;           // [6]
-  double* fields = nullptr;        // [5][ly][lx], allocated on first use
+  double* fields = nullptr;        // [7][ly][lx], allocated on first use
+  double* rows = nullptr;          // [2][ly] row averages, allocated on first use
   double* export_buf = nullptr;    // [27][ly][lx], allocated on first use
   double n_fluid = 0, n_top = 0;
   tlbh::Geometry launch{};
@@ -141,6 +142,7 @@ tlbh::Device device_view(const tlb_handle* h) {
   d.pop_stride = h->pop_stride;
   d.has_solid = h->has_solid;
   d.tau_one = h->tau_one;
+  d.moving = h->p.u_wall[0] != 0.0 || h->p.u_wall[1] != 0.0;
   d.link = h->link;
   d.solid = h->solid;
   d.t_bottom = h->t_bottom;
@@ -157,11 +159,15 @@ void launch_pass(const tlb_handle* h, tlbh::Pass pass, const void* src, void* ds
 
 // Re-run the step that produced f*(t) without storing, to evaluate the
 // moments, forces and u^H of time t (observables or fields).
-int evaluate_time_level(tlb_handle* h, bool fields) {
+enum class Level { kObserve, kFields, kStress };
+
+int evaluate_time_level(tlb_handle* h, Level what) {
   const void* src = h->buf[1 - h->cur];
   using tlbh::Pass;
-  const Pass pass = h->t == 0 ? (fields ? Pass::kFieldsInit : Pass::kObserveInit)
-                              : (fields ? Pass::kFields : Pass::kObserve);
+  const bool init = h->t == 0;
+  Pass pass = init ? Pass::kObserveInit : Pass::kObserve;
+  if (what == Level::kFields) pass = init ? Pass::kFieldsInit : Pass::kFields;
+  if (what == Level::kStress) pass = init ? Pass::kStressInit : Pass::kStress;
   launch_pass(h, pass, src, nullptr);
   TLB_HIP(h, hipGetLastError());
   return TLB_OK;
@@ -240,6 +246,8 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
     return fail(nullptr, TLB_EINVAL, "tlb_init: unknown precision %d", p->precision);
   if (!std::isfinite(p->rho_ref[0]) || !std::isfinite(p->rho_ref[1]) || !std::isfinite(p->t_ref))
     return fail(nullptr, TLB_EINVAL, "tlb_init: rho_ref and t_ref must be finite");
+  if (!std::isfinite(p->u_wall[0]) || !std::isfinite(p->u_wall[1]))
+    return fail(nullptr, TLB_EINVAL, "tlb_init: u_wall must be finite");
   if (!(p->tau > 0.5) || !(p->tau_g > 0.5) || !finite_positive(p->rho0) || !(p->dt_nominal != 0) ||
       !std::isfinite(p->dt_nominal))
     return fail(nullptr, TLB_EINVAL, "tlb_init: need tau > 1/2, tau_g > 1/2, rho0 > 0, dt_nominal != 0");
@@ -382,7 +390,7 @@ int tlb_step(tlb_handle* h, int64_t nsteps) {
 
 int tlb_observables(tlb_handle* h, tlb_obs* out) {
   if (!h || !out) return fail(h, TLB_EINVAL, "tlb_observables: NULL argument");
-  int rc = evaluate_time_level(h, false);
+  int rc = evaluate_time_level(h, Level::kObserve);
   if (rc != TLB_OK) return rc;
   tlbk::ObsArgs oa{};
   oa.partials = h->partials;
@@ -414,13 +422,48 @@ int tlb_get_fields(tlb_handle* h, double* rho_a, double* rho_b, double* ux, doub
                    double* temp) {
   if (!h) return fail(nullptr, TLB_EINVAL, "tlb_get_fields: NULL handle");
   const size_t n = (size_t)h->p.lx * h->p.ly;
-  if (!h->fields) TLB_HIP(h, hipMalloc(&h->fields, 5 * n * sizeof(double)));
-  int rc = evaluate_time_level(h, true);
+  if (!h->fields) TLB_HIP(h, hipMalloc(&h->fields, 7 * n * sizeof(double)));
+  int rc = evaluate_time_level(h, Level::kFields);
   if (rc != TLB_OK) return rc;
   double* outs[5] = {rho_a, rho_b, ux, uy, temp};
   for (int k = 0; k < 5; ++k)
     if (outs[k])
       TLB_HIP(h, hipMemcpyAsync(outs[k], h->fields + k * n, n * sizeof(double),
+                                hipMemcpyDeviceToHost, h->stream));
+  TLB_HIP(h, hipStreamSynchronize(h->stream));
+  return TLB_OK;
+}
+
+int tlb_get_stress(tlb_handle* h, double* sxy_visc, double* pxy_int) {
+  if (!h) return fail(nullptr, TLB_EINVAL, "tlb_get_stress: NULL handle");
+  const size_t n = (size_t)h->p.lx * h->p.ly;
+  if (!h->fields) TLB_HIP(h, hipMalloc(&h->fields, 7 * n * sizeof(double)));
+  int rc = evaluate_time_level(h, Level::kStress);
+  if (rc != TLB_OK) return rc;
+  double* outs[2] = {sxy_visc, pxy_int};
+  for (int k = 0; k < 2; ++k)
+    if (outs[k])
+      TLB_HIP(h, hipMemcpyAsync(outs[k], h->fields + (5 + k) * n, n * sizeof(double),
+                                hipMemcpyDeviceToHost, h->stream));
+  TLB_HIP(h, hipStreamSynchronize(h->stream));
+  return TLB_OK;
+}
+
+int tlb_row_averages(tlb_handle* h, double* u_av, double* pxy_av) {
+  if (!h) return fail(nullptr, TLB_EINVAL, "tlb_row_averages: NULL handle");
+  const int lx = h->p.lx, ly = h->p.ly;
+  const size_t n = (size_t)lx * ly;
+  if (!h->fields) TLB_HIP(h, hipMalloc(&h->fields, 7 * n * sizeof(double)));
+  if (!h->rows) TLB_HIP(h, hipMalloc(&h->rows, 2 * (size_t)ly * sizeof(double)));
+  int rc = evaluate_time_level(h, Level::kStress);
+  if (rc != TLB_OK) return rc;
+  hipLaunchKernelGGL(tlbk::lb_row_averages, dim3(ly), dim3(256), 0, h->stream, h->fields, h->solid,
+                     lx, ly, h->rows, h->rows + ly);
+  TLB_HIP(h, hipGetLastError());
+  double* outs[2] = {u_av, pxy_av};
+  for (int k = 0; k < 2; ++k)
+    if (outs[k])
+      TLB_HIP(h, hipMemcpyAsync(outs[k], h->rows + (size_t)k * ly, ly * sizeof(double),
                                 hipMemcpyDeviceToHost, h->stream));
   TLB_HIP(h, hipStreamSynchronize(h->stream));
   return TLB_OK;
@@ -471,6 +514,8 @@ int tlb_forward_taped(tlb_handle* h, int64_t nsteps, int32_t ckpt_every, double*
     return fail(h, TLB_EINVAL, "tlb_forward_taped: the adjoint needs FP64 or FP32 storage");
   if (h->launch.wide)
     return fail(h, TLB_EINVAL, "tlb_forward_taped: state buffer of 4 GiB or more");
+  if (h->p.u_wall[0] != 0.0 || h->p.u_wall[1] != 0.0)
+    return fail(h, TLB_EINVAL, "tlb_forward_taped: the adjoint needs walls at rest");
   if (h->p.ly > 65535)
     return fail(h, TLB_EINVAL, "tlb_forward_taped: ly > 65535 rows");
   h->tape_valid = false;
@@ -558,8 +603,8 @@ int tlb_destroy(tlb_handle* h) {
   if (!h) return TLB_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   void* ptrs[] = {h->buf[0], h->buf[1], h->link,   h->solid,      h->t_bottom,
-                  h->partials, h->obs,  h->fields, h->export_buf, h->ckpt,
-                  h->tape,     h->adj,  h->adj_scalars};
+                  h->partials, h->obs,  h->fields, h->rows,       h->export_buf,
+                  h->ckpt,     h->tape, h->adj,    h->adj_scalars};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);

@@ -116,6 +116,8 @@ def test_null_handle_calls():
     assert lib.tlb_step(None, 1) == tlb.TLB_EINVAL
     assert lib.tlb_observables(None, None) == tlb.TLB_EINVAL
     assert lib.tlb_get_fields(None, None, None, None, None, None) == tlb.TLB_EINVAL
+    assert lib.tlb_get_stress(None, None, None) == tlb.TLB_EINVAL
+    assert lib.tlb_row_averages(None, None, None) == tlb.TLB_EINVAL
     assert lib.tlb_forward_taped(None, 1, 1, None) == tlb.TLB_EINVAL
     assert lib.tlb_adjoint_step(None, 1, 1.0, None) == tlb.TLB_EINVAL
 
