@@ -77,6 +77,10 @@ def _load():
         lib.ora_observables.argtypes = [ctypes.c_void_p, dp]
         lib.ora_load_post_collision.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.c_int64]
         lib.ora_stress.argtypes = [ctypes.c_void_p, dp, dp]
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.ora_droplets.restype = ctypes.c_int64
+        lib.ora_droplets.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, i64p, i64p,
+                                     dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int32)]
         lib.ora_threads.restype = ctypes.c_int
         lib.ora_threads.argtypes = [ctypes.c_void_p]
         lib.ora_set_threads.argtypes = [ctypes.c_void_p, ctypes.c_int]
@@ -203,6 +207,27 @@ class Oracle:
         ly, lx = self.shape
         out = {k: np.empty((ly, lx)) for k in ("sxy_visc", "pxy_int")}
         _load().ora_stress(self._h, _dp(out["sxy_visc"]), _dp(out["pxy_int"]))
+        return out
+
+    def droplets(self, threshold: float = 0.8) -> dict:
+        """Droplets of the current time (bulk rho_A > threshold, 4-connected,
+        numbered by smallest node index): arrays root, size, mass, x, y, nu
+        and the node labels (ly, lx), -1 outside droplets."""
+        ly, lx = self.shape
+        lib = _load()
+        label = np.empty((ly, lx), np.int32)
+        n = lib.ora_droplets(self._h, float(threshold), 0, None, None, None, None, None, None,
+                             label.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        if n < 0:
+            raise MemoryError("oracle droplet buffers")
+        out = {"root": np.empty(n, np.int64), "size": np.empty(n, np.int64)}
+        for k in ("mass", "x", "y", "nu"):
+            out[k] = np.empty(n)
+        i64 = ctypes.POINTER(ctypes.c_int64)
+        lib.ora_droplets(self._h, float(threshold), n, out["root"].ctypes.data_as(i64),
+                         out["size"].ctypes.data_as(i64), _dp(out["mass"]), _dp(out["x"]),
+                         _dp(out["y"]), _dp(out["nu"]), None)
+        out["label"] = label
         return out
 
     def observables(self) -> dict:

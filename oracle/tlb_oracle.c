@@ -628,6 +628,142 @@ void ora_stress(ora_state *s, double *sxy_visc, double *pxy_int) {
   }
 }
 
+/* Droplets at the current time (Sec. 2.4 and Sec. 3.3.2 Eq. (25)).
+ * A droplet is a 4-connected cluster of fluid nodes whose density of the
+ * first component exceeds `threshold` (the bulk, rho_A > B_th), x periodic
+ * (and y when the lattice is periodic in y). Droplets are numbered in the
+ * order of their smallest node index k = y*lx + x (canonical labels). For
+ * droplet i:
+ *   root[i]   its smallest node index
+ *   size[i]   number of nodes
+ *   mass[i]   sum of rho_A over its nodes
+ *   cx, cy    centre of mass sum rho_A X / sum rho_A, with each node's x
+ *             taken within half a period of the root's x (wrapped back into
+ *             [0, lx) at the end) and likewise y when periodic
+ *   nu[i]     (u_y T - kappa dT/dy) / (kappa dt_nominal / ly) at the centre,
+ *             u_y = u^H_y, dT/dy by central differences with the mirror
+ *             value at solid neighbours (as in Nu), each field bilinearly
+ *             interpolated between the four nodes around the centre (x
+ *             periodic; y clamped to the lattice); solid nodes enter with
+ *             u_y = 0, T = their wall temperature and dT/dy = 0
+ * label (ly*lx, optional) receives the droplet number of each node, -1
+ * outside droplets. At most cap droplets are written; returns the count. */
+static double node_dTdy(const ora_state *s, int x, int y) {
+  int lx = s->p.lx, ly = s->p.ly;
+  int k = y * lx + x;
+  if (s->solid[k]) return 0.0;
+  double tt = s->temp[k], tn, ts;
+  if (solid_at(s, x, y + 1)) tn = 2.0 * wall_temperature(s, x, y + 1) - tt;
+  else tn = s->temp[((y + 1) % ly) * lx + x];
+  if (solid_at(s, x, y - 1)) ts = 2.0 * wall_temperature(s, x, y - 1) - tt;
+  else ts = s->temp[((y - 1 + ly) % ly) * lx + x];
+  return 0.5 * (tn - ts);
+}
+
+static double bilinear(const double *f, int lx, int ly, int periodic_y, double x, double y) {
+  if (!periodic_y) y = y < 0 ? 0 : (y > ly - 1 ? ly - 1 : y);
+  int x0 = (int)floor(x), y0 = (int)floor(y);
+  double ax = x - x0, ay = y - y0;
+  int x1 = x0 + 1, y1 = y0 + 1;
+  x0 = ((x0 % lx) + lx) % lx;
+  x1 = ((x1 % lx) + lx) % lx;
+  if (periodic_y) {
+    y0 = ((y0 % ly) + ly) % ly;
+    y1 = ((y1 % ly) + ly) % ly;
+  } else if (y1 > ly - 1) {
+    y1 = ly - 1;
+  }
+  return (1 - ax) * (1 - ay) * f[y0 * lx + x0] + ax * (1 - ay) * f[y0 * lx + x1] +
+         (1 - ax) * ay * f[y1 * lx + x0] + ax * ay * f[y1 * lx + x1];
+}
+
+int64_t ora_droplets(ora_state *s, double threshold, int64_t cap, int64_t *root,
+                     int64_t *size, double *mass, double *cx, double *cy, double *nu,
+                     int32_t *label) {
+  macroscopic(s);
+  int lx = s->p.lx, ly = s->p.ly, n = s->n, per_y = s->p.periodic_y;
+  int32_t *lab = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int *queue = (int *)malloc(sizeof(int) * (size_t)n);
+  double *uy = (double *)malloc(sizeof(double) * (size_t)n);
+  double *dty = (double *)malloc(sizeof(double) * (size_t)n);
+  double *tt = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!lab || !queue || !uy || !dty || !tt) {
+    free(lab); free(queue); free(uy); free(dty); free(tt);
+    return -1;
+  }
+  for (int k = 0; k < n; ++k) {
+    double hx = 0, hy = 0;
+    if (!s->solid[k]) hydro_velocity(s, k, &hx, &hy);
+    uy[k] = hy;
+    dty[k] = node_dTdy(s, k % lx, k / lx);
+    tt[k] = s->solid[k] ? wall_temperature(s, k % lx, k / lx) : s->temp[k];
+    lab[k] = -1;
+  }
+  double kappa = CS2 * (s->p.tau_g - 0.5);
+  int64_t count = 0;
+  /* flood fill from each unlabelled bulk node in increasing index order */
+  for (int k0 = 0; k0 < n; ++k0) {
+    if (lab[k0] >= 0 || s->solid[k0] || !(s->rho[0][k0] > threshold)) continue;
+    int head = 0, tail = 0;
+    queue[tail++] = k0;
+    lab[k0] = (int32_t)count;
+    int xr = k0 % lx, yr = k0 / lx;
+    double m = 0, mx = 0, my = 0;
+    int64_t sz = 0;
+    while (head < tail) {
+      int k = queue[head++];
+      int x = k % lx, y = k / lx;
+      double r = s->rho[0][k];
+      double dx = x - xr, dy = y - yr;
+      if (dx > 0.5 * lx) dx -= lx;
+      if (dx < -0.5 * lx) dx += lx;
+      if (per_y) {
+        if (dy > 0.5 * ly) dy -= ly;
+        if (dy < -0.5 * ly) dy += ly;
+      }
+      m += r;
+      mx += r * (xr + dx);
+      my += r * (yr + dy);
+      sz += 1;
+      const int nx[4] = {x + 1, x - 1, x, x};
+      const int ny[4] = {y, y, y + 1, y - 1};
+      for (int j = 0; j < 4; ++j) {
+        int yy = ny[j];
+        if (yy < 0 || yy >= ly) {
+          if (!per_y) continue;
+          yy = (yy + ly) % ly;
+        }
+        int kk = yy * lx + wrapx(s, nx[j]);
+        if (lab[kk] >= 0 || s->solid[kk] || !(s->rho[0][kk] > threshold)) continue;
+        lab[kk] = (int32_t)count;
+        queue[tail++] = kk;
+      }
+    }
+    if (count < cap) {
+      double X = mx / m, Y = my / m;
+      X = fmod(X, (double)lx);
+      if (X < 0) X += lx;
+      if (per_y) {
+        Y = fmod(Y, (double)ly);
+        if (Y < 0) Y += ly;
+      }
+      double u = bilinear(uy, lx, ly, per_y, X, Y);
+      double t = bilinear(tt, lx, ly, per_y, X, Y);
+      double g = bilinear(dty, lx, ly, per_y, X, Y);
+      if (root) root[count] = k0;
+      if (size) size[count] = sz;
+      if (mass) mass[count] = m;
+      if (cx) cx[count] = X;
+      if (cy) cy[count] = Y;
+      if (nu) nu[count] = (u * t - kappa * g) / (kappa * s->p.dt_nominal / ly);
+    }
+    count += 1;
+  }
+  if (label) memcpy(label, lab, sizeof(int32_t) * (size_t)n);
+  free(lab); free(queue); free(uy); free(dty); free(tt);
+  return count;
+}
+
 /* Replace the state by the streaming of the given post-collision
  * populations (three [9][ly][lx] arrays) and set the time to t: the state
  * becomes f(t) = stream(f*(t-1)). Used to check one step of another
