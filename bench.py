@@ -226,6 +226,11 @@ def main() -> int:
     t_rows = time.perf_counter()
     rows = sim.row_averages()
     t_rows = time.perf_counter() - t_rows
+    # droplet detection of the same time level: fields pass, labelling,
+    # exact per-droplet sums, droplet Nusselt numbers, copy of the results
+    t_drop = time.perf_counter()
+    drops = sim.droplets(0.8)
+    t_drop = time.perf_counter() - t_drop
     step_ms = e0.elapsed_time(e1)          # the K step launches only
     total_ms = e0.elapsed_time(e2)         # whole job: steps + observables
 
@@ -259,6 +264,8 @@ def main() -> int:
                   "wall_s": round(wall, 3)},
         "row_averages": {"ms": round(t_rows * 1e3, 3), "pxy_av_mean": float(np.mean(rows["pxy_av"])),
                          "u_av_top": float(rows["u_av"][-1])},
+        "droplets": {"ms": round(t_drop * 1e3, 3), "count": int(len(drops["root"])),
+                     "threshold": 0.8, "nu_mean": float(np.mean(drops["nu"])) if len(drops["nu"]) else None},
     }
     sim.close()
     if args.adjoint_steps > 0:

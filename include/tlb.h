@@ -112,6 +112,15 @@ typedef struct tlb_obs {
   double mass_a, mass_b, sum_t, nu, nu_top, ke;
 } tlb_obs;
 
+/* One droplet (Sec. 2.4; droplet Nusselt number of Sec. 3.3.2 Eq. (25)). */
+typedef struct tlb_droplet {
+  int64_t root;   /* smallest node index y*lx + x of the droplet */
+  int64_t size;   /* number of nodes */
+  double mass;    /* sum of rho_A over its nodes */
+  double x, y;    /* centre of mass (x in [0, lx)) */
+  double nu;      /* droplet Nusselt number at the centre */
+} tlb_droplet;
+
 typedef struct tlb_handle tlb_handle;
 
 /* Create a handle and set the state at t = 0 to the equilibria of the given
@@ -166,6 +175,25 @@ int tlb_get_stress(tlb_handle *h, double *sxy_visc, double *pxy_int);
  * Host arrays of ly doubles, either may be NULL; rows without fluid report
  * 0. Deterministic (fixed-order FP64 sums). Synchronises the stream. */
 int tlb_row_averages(tlb_handle *h, double *u_av, double *pxy_av);
+
+/* Droplets at the current time. A droplet is a 4-connected cluster of fluid
+ * nodes whose rho_A exceeds `threshold` (the bulk, B_th = 0.8 in the paper's
+ * runs), x periodic; droplets are numbered in the order of their smallest
+ * node index (independent of scheduling). For each: its size, mass sum
+ * rho_A, centre of mass (each node's x taken within half a period of the
+ * smallest node's x, the result wrapped into [0, lx)), and the droplet
+ * Nusselt number (u_y T - kappa dT/dy) / (kappa dt_nominal / ly) with u^H_y,
+ * T and dT/dy (central differences, mirror value at solid neighbours; solid
+ * nodes enter with u = 0, their wall temperature and dT/dy = 0) bilinearly
+ * interpolated at the centre (x periodic, y clamped to [0, ly-1]).
+ *   out     host array of cap entries (may be NULL if cap == 0)
+ *   count   receives the number of droplets (may exceed cap: only the first
+ *           cap are written)
+ *   labels  host, ly*lx, or NULL: droplet number of each node, -1 outside
+ * Sums are exact (fixed point, order independent). Synchronises the stream.
+ * Errors: TLB_EINVAL, TLB_ENOMEM, TLB_EDEVICE. */
+int tlb_droplets(tlb_handle *h, double threshold, tlb_droplet *out, int64_t cap,
+                 int64_t *count, int32_t *labels);
 
 /* Post-collision populations f*(t) of the current time (the state the next
  * step streams) as host doubles [27][ly][lx]; zero at solid nodes.

@@ -22,7 +22,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "fp16dev": 2, "bf16dev": 3, "fix16dev": 4}
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = (
     "tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_stress",
-    "tlb_row_averages", "tlb_get_populations", "tlb_set_bottom_temperature",
+    "tlb_row_averages", "tlb_droplets", "tlb_get_populations", "tlb_set_bottom_temperature",
     "tlb_forward_taped", "tlb_adjoint_step", "tlb_time", "tlb_destroy", "tlb_last_error",
 )
 
@@ -53,6 +53,11 @@ class Obs(ctypes.Structure):
                 ("ke", ctypes.c_double)]
 
 
+class Droplet(ctypes.Structure):
+    _fields_ = [("root", ctypes.c_int64), ("size", ctypes.c_int64), ("mass", ctypes.c_double),
+                ("x", ctypes.c_double), ("y", ctypes.c_double), ("nu", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -80,6 +85,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tlb_get_populations.argtypes = [vp, dp]
     lib.tlb_get_stress.argtypes = [vp, dp, dp]
     lib.tlb_row_averages.argtypes = [vp, dp, dp]
+    lib.tlb_droplets.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Droplet), ctypes.c_int64,
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
     lib.tlb_set_bottom_temperature.argtypes = [vp, dp]
     lib.tlb_forward_taped.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, dp]
     lib.tlb_adjoint_step.argtypes = [vp, ctypes.c_int64, ctypes.c_double, dp]
@@ -89,7 +96,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tlb_last_error.argtypes = [vp]
     lib.tlb_last_error.restype = ctypes.c_char_p
     for name in ("tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_stress",
-                 "tlb_row_averages", "tlb_get_populations", "tlb_set_bottom_temperature",
+                 "tlb_row_averages", "tlb_droplets", "tlb_get_populations",
+                 "tlb_set_bottom_temperature",
                  "tlb_forward_taped", "tlb_adjoint_step", "tlb_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -218,6 +226,30 @@ class Simulation:
         ly = self.shape[0]
         out = {"u_av": np.empty(ly), "pxy_av": np.empty(ly)}
         self._check(self._lib.tlb_row_averages(self._h, _dp(out["u_av"]), _dp(out["pxy_av"])))
+        return out
+
+    def droplets(self, threshold: float = 0.8, labels: bool = False) -> dict:
+        """Droplets of the current time: arrays root, size, mass, x, y, nu
+        (numbered by smallest node index) and, if asked, the node labels
+        (ly, lx) with -1 outside droplets."""
+        ly, lx = self.shape
+        count = ctypes.c_int64()
+        lab = np.empty((ly, lx), np.int32) if labels else None
+        lab_p = lab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if labels else None
+        cap = min(ly * lx, 1 << 18)
+        arr = (Droplet * cap)()
+        self._check(self._lib.tlb_droplets(self._h, float(threshold), arr, cap, ctypes.byref(count),
+                                           lab_p))
+        n = count.value
+        if n > cap:  # more droplets than the first guess: ask again with room for all
+            arr = (Droplet * n)()
+            self._check(self._lib.tlb_droplets(self._h, float(threshold), arr, n,
+                                               ctypes.byref(count), None))
+        out = {k: np.array([getattr(arr[i], k) for i in range(n)],
+                           dtype=np.int64 if k in ("root", "size") else np.float64)
+               for k, _ in Droplet._fields_}
+        if labels:
+            out["label"] = lab
         return out
 
     def populations(self) -> np.ndarray:

@@ -1,0 +1,276 @@
+// Droplet detection on the GPU (Sec. 2.4) and the droplet Nusselt number
+// (Sec. 3.3.2 Eq. (25)).
+//
+// A droplet is a 4-connected cluster of fluid nodes whose density of the
+// first component exceeds the bulk threshold B_th (x periodic). Clusters are
+// found by a lock-free union-find: every node starts as its own parent, each
+// bulk node unites with its bulk neighbours to the right (periodic) and
+// above, linking the larger root under the smaller one with an atomic
+// minimum, and a final pass points every node at its root. The root of a
+// cluster is therefore its smallest node index, and droplets are numbered in
+// the order of their roots (canonical, independent of scheduling).
+//
+// Per-droplet sums (node count, sum rho_A, sum rho_A X, sum rho_A Y) are
+// exact: each term is rounded once to a multiple of 2^-40 and split into a
+// high and a low 32-bit part that are added with 64-bit integer atomics, so
+// the result does not depend on the order of the additions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tlbk {
+
+struct DropArgs {
+  const double* fields;     // [7][ly][lx]: rho_A, rho_B, u^H_x, u^H_y, T, ...
+  const uint8_t* solid;     // [ly*lx]
+  const double* t_bottom;   // [lx] (FP64 copy)
+  int32_t* parent;          // [ly*lx] union-find parents, -1 outside droplets
+  int32_t* rid;             // [ly*lx] droplet number of each root
+  int32_t* block_count;     // [nblocks] roots per block, then exclusive offsets
+  int64_t* acc;             // [count][7] size, mass hi/lo, mx hi/lo, my hi/lo
+  int64_t* roots;           // [count] root node of each droplet
+  double* out;              // [count][6] root, size, mass, x, y, nu
+  int32_t* label;           // [ly*lx] droplet number, -1 outside
+  int* error;               // set when a bounded loop runs out
+  double threshold, t_top, kappa, dt_nominal;
+  int lx, ly, n, count;
+};
+
+constexpr int kDropItems = 16;                 // nodes per thread in the counting passes
+constexpr int kDropTile = 256 * kDropItems;    // nodes per block in the counting passes
+
+__device__ inline int32_t load_parent(const int32_t* p, int q) {
+  return __hip_atomic_load(p + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of q, halving the path on the way (q is pointed at its grandparent,
+// still an ancestor in its cluster). Parents only ever decrease and
+// parent[q] <= q, so the walk strictly descends: at most n steps (`cap`);
+// running out sets the error flag instead of looping on.
+__device__ inline int32_t find_root(int32_t* parent, int32_t q, int cap, int* error) {
+  for (int it = 0; it < cap; ++it) {
+    const int32_t p = load_parent(parent, q);
+    if (p == q) return q;
+    const int32_t g = load_parent(parent, p);
+    if (g == p) return p;
+    atomicMin(parent + q, g);
+    q = g;
+  }
+  atomicOr(error, 1);
+  return q;
+}
+
+// Unite the clusters of a and b (both bulk nodes). An atomic minimum links
+// the larger root under the smaller; if that node was no longer a root, the
+// walk continues from the parent it had (a strictly smaller index).
+__device__ inline void unite(int32_t* parent, int32_t a, int32_t b, int cap, int* error) {
+  for (int it = 0; it < cap; ++it) {
+    a = find_root(parent, a, cap, error);
+    b = find_root(parent, b, cap, error);
+    if (a == b) return;
+    if (a < b) {
+      const int32_t t = a;
+      a = b;
+      b = t;
+    }
+    const int32_t old = atomicMin(parent + a, b);
+    if (old == a) return;
+    a = old;
+  }
+  atomicOr(error, 1);
+}
+
+__device__ inline bool is_bulk(const DropArgs& a, int q) {
+  return a.solid[q] == 0 && a.fields[q] > a.threshold;
+}
+
+__global__ __launch_bounds__(256) void drop_init(DropArgs a) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= a.n) return;
+  a.parent[q] = is_bulk(a, q) ? q : -1;
+}
+
+__global__ __launch_bounds__(256) void drop_union(DropArgs a) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= a.n || a.parent[q] < 0) return;
+  const int x = q % a.lx, y = q / a.lx;
+  const int right = y * a.lx + (x + 1 == a.lx ? 0 : x + 1);
+  if (right != q && a.parent[right] >= 0) unite(a.parent, q, right, a.n + 1, a.error);
+  if (y + 1 < a.ly) {
+    const int up = q + a.lx;
+    if (a.parent[up] >= 0) unite(a.parent, q, up, a.n + 1, a.error);
+  }
+}
+
+__global__ __launch_bounds__(256) void drop_compress(DropArgs a) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= a.n || a.parent[q] < 0) return;
+  atomicMin(a.parent + q, find_root(a.parent, q, a.n + 1, a.error));
+}
+
+// Roots per tile of kDropTile nodes.
+__global__ __launch_bounds__(256) void drop_count_roots(DropArgs a) {
+  __shared__ int s[256];
+  const int base = blockIdx.x * kDropTile + threadIdx.x * kDropItems;
+  int c = 0;
+  for (int j = 0; j < kDropItems; ++j) {
+    const int q = base + j;
+    if (q < a.n && a.parent[q] == q) ++c;
+  }
+  s[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.block_count[blockIdx.x] = s[0];
+}
+
+// Exclusive scan of the tile counts (one block); block_count[nblocks] gets
+// the total.
+__global__ __launch_bounds__(256) void drop_scan_tiles(int32_t* count, int nblocks) {
+  __shared__ int s[256];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < nblocks; b0 += 256) {
+    const int i = b0 + threadIdx.x;
+    const int v = i < nblocks ? count[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {  // inclusive Hillis-Steele scan
+      const int t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nblocks) count[i] = carry + s[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 255) carry += s[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) count[nblocks] = carry;
+}
+
+// Droplet number of every root: tile offset plus the rank within the tile.
+__global__ __launch_bounds__(256) void drop_number_roots(DropArgs a) {
+  __shared__ int s[256];
+  const int base = blockIdx.x * kDropTile + threadIdx.x * kDropItems;
+  int c = 0;
+  for (int j = 0; j < kDropItems; ++j) {
+    const int q = base + j;
+    if (q < a.n && a.parent[q] == q) ++c;
+  }
+  s[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int id = a.block_count[blockIdx.x] + s[threadIdx.x] - c;
+  for (int j = 0; j < kDropItems; ++j) {
+    const int q = base + j;
+    if (q < a.n && a.parent[q] == q) {
+      a.rid[q] = id;
+      a.roots[id] = q;
+      ++id;
+    }
+  }
+}
+
+// Fixed-point term: v rounded to a multiple of 2^-40, split into a high
+// part (multiples of 2^-8) and a low part in [0, 2^32) units of 2^-40.
+__device__ inline void add_fixed(int64_t* hi, int64_t* lo, double v) {
+  const int64_t f = __double2ll_rn(v * 1099511627776.0);  // 2^40
+  const int64_t h = f >> 32;
+  const int64_t l = f - (h << 32);
+  atomicAdd(reinterpret_cast<unsigned long long*>(hi), (unsigned long long)h);
+  atomicAdd(reinterpret_cast<unsigned long long*>(lo), (unsigned long long)l);
+}
+
+__device__ inline double fixed_value(int64_t hi, int64_t lo) {
+  return ((double)hi * 4294967296.0 + (double)lo) * (1.0 / 1099511627776.0);
+}
+
+// Per node: its droplet number, and its terms of the droplet's sums (x
+// taken within half a period of the root's x).
+__global__ __launch_bounds__(256) void drop_accumulate(DropArgs a) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= a.n) return;
+  const int32_t root = a.parent[q];
+  if (root < 0) {
+    a.label[q] = -1;
+    return;
+  }
+  const int d = a.rid[root];
+  a.label[q] = d;
+  const int x = q % a.lx, y = q / a.lx, xr = root % a.lx, yr = root / a.lx;
+  double dx = (double)(x - xr);
+  if (dx > 0.5 * a.lx) dx -= a.lx;
+  if (dx < -0.5 * a.lx) dx += a.lx;
+  const double r = a.fields[q];
+  int64_t* c = a.acc + (size_t)d * 7;
+  atomicAdd(reinterpret_cast<unsigned long long*>(c), 1ull);
+  add_fixed(c + 1, c + 2, r);
+  add_fixed(c + 3, c + 4, r * ((double)xr + dx));
+  add_fixed(c + 5, c + 6, r * (double)(yr + (y - yr)));
+}
+
+// Temperature gradient dT/dy at node (x, y) by central differences with
+// the mirror value 2 T_w - T at a solid neighbour (0 at solid nodes).
+__device__ inline double node_dtdy(const DropArgs& a, int x, int y) {
+  const size_t nn = (size_t)a.lx * a.ly;
+  const double* T = a.fields + 4 * nn;
+  const int q = y * a.lx + x;
+  if (a.solid[q] != 0) return 0.0;
+  const double t = T[q];
+  double tn, ts;
+  if (y + 1 >= a.ly) tn = 2.0 * a.t_top - t;
+  else if (a.solid[q + a.lx] != 0) tn = 2.0 * T[q + a.lx] - t;
+  else tn = T[q + a.lx];
+  if (y - 1 < 0) ts = 2.0 * a.t_bottom[x] - t;
+  else if (a.solid[q - a.lx] != 0) ts = 2.0 * T[q - a.lx] - t;
+  else ts = T[q - a.lx];
+  return 0.5 * (tn - ts);
+}
+
+// Per droplet: centre of mass, and Eq. (25) with u^H_y, T and dT/dy
+// interpolated bilinearly at the centre (x periodic, y clamped).
+__global__ __launch_bounds__(256) void drop_finalize(DropArgs a) {
+  const int d = blockIdx.x * 256 + threadIdx.x;
+  if (d >= a.count) return;
+  const int64_t* c = a.acc + (size_t)d * 7;
+  const double m = fixed_value(c[1], c[2]);
+  double X = fixed_value(c[3], c[4]) / m;
+  double Y = fixed_value(c[5], c[6]) / m;
+  X = fmod(X, (double)a.lx);
+  if (X < 0) X += a.lx;
+  const double yc = Y < 0 ? 0.0 : (Y > a.ly - 1 ? (double)(a.ly - 1) : Y);
+  int x0 = (int)floor(X), y0 = (int)floor(yc);
+  const double ax = X - x0, ay = yc - y0;
+  int x1 = x0 + 1, y1 = y0 + 1;
+  x0 %= a.lx;
+  x1 %= a.lx;
+  if (y1 > a.ly - 1) y1 = a.ly - 1;
+  const size_t nn = (size_t)a.lx * a.ly;
+  const double* uy = a.fields + 3 * nn;
+  const double* T = a.fields + 4 * nn;
+  const int q00 = y0 * a.lx + x0, q01 = y0 * a.lx + x1, q10 = y1 * a.lx + x0, q11 = y1 * a.lx + x1;
+  const double w00 = (1 - ax) * (1 - ay), w01 = ax * (1 - ay), w10 = (1 - ax) * ay, w11 = ax * ay;
+  const double u = w00 * uy[q00] + w01 * uy[q01] + w10 * uy[q10] + w11 * uy[q11];
+  const double t = w00 * T[q00] + w01 * T[q01] + w10 * T[q10] + w11 * T[q11];
+  const double g = w00 * node_dtdy(a, x0, y0) + w01 * node_dtdy(a, x1, y0) +
+                   w10 * node_dtdy(a, x0, y1) + w11 * node_dtdy(a, x1, y1);
+  double* o = a.out + (size_t)d * 6;
+  o[0] = (double)a.roots[d];
+  o[1] = (double)c[0];
+  o[2] = m;
+  o[3] = X;
+  o[4] = Y;
+  o[5] = (u * t - a.kappa * g) / (a.kappa * a.dt_nominal / a.ly);
+}
+
+}  // namespace tlbk

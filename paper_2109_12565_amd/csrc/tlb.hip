@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "tlb.h"
+#include "droplets.hpp"
 #include "launch.hpp"
 #include "lb_kernels.hpp"
 #include "lb_reduce.hpp"
@@ -40,6 +41,13 @@ struct tlb_handle {
   double* obs = nullptr;           // [6]
   double* fields = nullptr;        // [7][ly][lx], allocated on first use
   double* rows = nullptr;          // [2][ly] row averages, allocated on first use
+  // droplet detection, allocated on first use
+  int32_t* drop_nodes = nullptr;   // [3][ly*lx] parent, root number, label
+  int32_t* drop_tiles = nullptr;   // [tiles + 1] roots per tile, offsets
+  int* drop_error = nullptr;
+  double* drop_tb = nullptr;       // [lx] FP64 bottom temperature
+  void* drop_acc = nullptr;        // per droplet: sums, roots, results
+  size_t drop_acc_cap = 0;
   double* export_buf = nullptr;    // [27][ly][lx], allocated on first use
   double n_fluid = 0, n_top = 0;
   tlbh::Geometry launch{};
@@ -469,6 +477,112 @@ int tlb_row_averages(tlb_handle* h, double* u_av, double* pxy_av) {
   return TLB_OK;
 }
 
+int tlb_droplets(tlb_handle* h, double threshold, tlb_droplet* out, int64_t cap, int64_t* count,
+                 int32_t* labels) {
+  if (!h || !count) return fail(h, TLB_EINVAL, "tlb_droplets: NULL handle or count");
+  if (cap < 0 || (cap > 0 && !out))
+    return fail(h, TLB_EINVAL, "tlb_droplets: need cap >= 0 and an output array when cap > 0");
+  if (!std::isfinite(threshold)) return fail(h, TLB_EINVAL, "tlb_droplets: threshold not finite");
+  const int lx = h->p.lx, ly = h->p.ly;
+  const int n = lx * ly;  // below 2^30 (checked at init)
+  const int tiles = (n + tlbk::kDropTile - 1) / tlbk::kDropTile;
+  if (!h->fields) TLB_HIP(h, hipMalloc(&h->fields, 7 * (size_t)n * sizeof(double)));
+  if (!h->drop_nodes) TLB_HIP(h, hipMalloc(&h->drop_nodes, 3 * (size_t)n * sizeof(int32_t)));
+  if (!h->drop_tiles) TLB_HIP(h, hipMalloc(&h->drop_tiles, (size_t)(tiles + 1) * sizeof(int32_t)));
+  if (!h->drop_error) TLB_HIP(h, hipMalloc(&h->drop_error, sizeof(int)));
+  if (!h->drop_tb) TLB_HIP(h, hipMalloc(&h->drop_tb, (size_t)lx * sizeof(double)));
+  int rc = evaluate_time_level(h, Level::kFields);
+  if (rc != TLB_OK) return rc;
+  // FP64 copy of the bottom temperature (the handle keeps the compute type)
+  {
+    std::vector<double> tb(lx);
+    if (is_fp64(h)) {
+      TLB_HIP(h, hipMemcpyAsync(h->drop_tb, h->t_bottom, lx * sizeof(double),
+                                hipMemcpyDeviceToDevice, h->stream));
+    } else {
+      std::vector<float> tf(lx);
+      TLB_HIP(h, hipMemcpyAsync(tf.data(), h->t_bottom, lx * sizeof(float), hipMemcpyDeviceToHost,
+                                h->stream));
+      TLB_HIP(h, hipStreamSynchronize(h->stream));
+      for (int x = 0; x < lx; ++x) tb[x] = tf[x];
+      TLB_HIP(h, hipMemcpyAsync(h->drop_tb, tb.data(), lx * sizeof(double), hipMemcpyHostToDevice,
+                                h->stream));
+    }
+  }
+  tlbk::DropArgs a{};
+  a.fields = h->fields;
+  a.solid = h->solid;
+  a.t_bottom = h->drop_tb;
+  a.parent = h->drop_nodes;
+  a.rid = h->drop_nodes + n;
+  a.label = h->drop_nodes + 2 * (size_t)n;
+  a.block_count = h->drop_tiles;
+  a.error = h->drop_error;
+  a.threshold = threshold;
+  a.t_top = h->p.t_top;
+  a.kappa = (h->p.tau_g - 0.5) / 3.0;
+  a.dt_nominal = h->p.dt_nominal;
+  a.lx = lx;
+  a.ly = ly;
+  a.n = n;
+  const dim3 nodes((n + 255) / 256), block(256);
+  TLB_HIP(h, hipMemsetAsync(h->drop_error, 0, sizeof(int), h->stream));
+  hipLaunchKernelGGL(tlbk::drop_init, nodes, block, 0, h->stream, a);
+  hipLaunchKernelGGL(tlbk::drop_union, nodes, block, 0, h->stream, a);
+  hipLaunchKernelGGL(tlbk::drop_compress, nodes, block, 0, h->stream, a);
+  hipLaunchKernelGGL(tlbk::drop_count_roots, dim3(tiles), block, 0, h->stream, a);
+  hipLaunchKernelGGL(tlbk::drop_scan_tiles, dim3(1), block, 0, h->stream, h->drop_tiles, tiles);
+  TLB_HIP(h, hipGetLastError());
+  int32_t total = 0;
+  int err = 0;
+  TLB_HIP(h, hipMemcpyAsync(&total, h->drop_tiles + tiles, sizeof(int32_t), hipMemcpyDeviceToHost,
+                            h->stream));
+  TLB_HIP(h, hipMemcpyAsync(&err, h->drop_error, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  TLB_HIP(h, hipStreamSynchronize(h->stream));
+  if (err) return fail(h, TLB_EDEVICE, "tlb_droplets: cluster walk exceeded its bound");
+  *count = total;
+  // per droplet: 7 int64 sums, the root, 6 doubles of results
+  const size_t per = 7 * sizeof(int64_t) + sizeof(int64_t) + 6 * sizeof(double);
+  const size_t need = (size_t)(total > 0 ? total : 1) * per;
+  if (h->drop_acc_cap < need) {
+    if (h->drop_acc) TLB_HIP(h, hipFree(h->drop_acc));
+    h->drop_acc = nullptr;
+    h->drop_acc_cap = 0;
+    TLB_HIP(h, hipMalloc(&h->drop_acc, need));
+    h->drop_acc_cap = need;
+  }
+  a.acc = static_cast<int64_t*>(h->drop_acc);
+  a.roots = a.acc + 7 * (size_t)total;
+  a.out = reinterpret_cast<double*>(a.roots + total);
+  a.count = total;
+  if (total > 0)
+    TLB_HIP(h, hipMemsetAsync(a.acc, 0, 7 * (size_t)total * sizeof(int64_t), h->stream));
+  hipLaunchKernelGGL(tlbk::drop_number_roots, dim3(tiles), block, 0, h->stream, a);
+  hipLaunchKernelGGL(tlbk::drop_accumulate, nodes, block, 0, h->stream, a);
+  if (total > 0)
+    hipLaunchKernelGGL(tlbk::drop_finalize, dim3((total + 255) / 256), block, 0, h->stream, a);
+  TLB_HIP(h, hipGetLastError());
+  const int64_t m = std::min<int64_t>(cap, total);
+  std::vector<double> res((size_t)m * 6);
+  if (m > 0)
+    TLB_HIP(h, hipMemcpyAsync(res.data(), a.out, res.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              h->stream));
+  if (labels)
+    TLB_HIP(h, hipMemcpyAsync(labels, a.label, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost,
+                              h->stream));
+  TLB_HIP(h, hipStreamSynchronize(h->stream));
+  for (int64_t i = 0; i < m; ++i) {
+    const double* r = res.data() + 6 * i;
+    out[i].root = (int64_t)r[0];
+    out[i].size = (int64_t)r[1];
+    out[i].mass = r[2];
+    out[i].x = r[3];
+    out[i].y = r[4];
+    out[i].nu = r[5];
+  }
+  return TLB_OK;
+}
+
 int tlb_get_populations(tlb_handle* h, double* out) {
   if (!h || !out) return fail(h, TLB_EINVAL, "tlb_get_populations: NULL argument");
   const int lx = h->p.lx, ly = h->p.ly;
@@ -602,9 +716,10 @@ int64_t tlb_time(const tlb_handle* h) { return h ? h->t : -1; }
 int tlb_destroy(tlb_handle* h) {
   if (!h) return TLB_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
-  void* ptrs[] = {h->buf[0], h->buf[1], h->link,   h->solid,      h->t_bottom,
-                  h->partials, h->obs,  h->fields, h->rows,       h->export_buf,
-                  h->ckpt,     h->tape, h->adj,    h->adj_scalars};
+  void* ptrs[] = {h->buf[0],   h->buf[1],     h->link,       h->solid,      h->t_bottom,
+                  h->partials, h->obs,        h->fields,     h->rows,       h->export_buf,
+                  h->ckpt,     h->tape,       h->adj,        h->adj_scalars, h->drop_nodes,
+                  h->drop_tiles, h->drop_error, h->drop_tb,  h->drop_acc};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
