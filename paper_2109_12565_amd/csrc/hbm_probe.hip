@@ -3,6 +3,15 @@
 // accesses (the width the lattice kernel uses). It gives the practical
 // ceiling that the lattice kernel's HBM traffic is compared against; the
 // nominal peak of the part is 8 TB/s.
+//
+// Second part: the lattice step's memory pattern with its arithmetic taken
+// out, on a 4096 x 2048 lattice of 27 FP32 planes: every node loads the 27
+// values a pull step loads (x and y shifted by the direction's velocity,
+// periodic in x, clamped at the walls) and stores 27 values
+// (non-temporal), in 256-wide strips of 32 rows. Variants: plain block
+// order; the step kernel's XCD-aware tile order with alternating chunk
+// direction and one barrier per row; and an interleaved layout in which the
+// 27 planes of each 64-column group of a row are contiguous.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -43,6 +52,49 @@ __global__ void write_nt(v4f* __restrict__ b, size_t n) {
 __global__ void copy_f32_nt(const float* __restrict__ a, float* __restrict__ b, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     __builtin_nontemporal_store(a[i], b + i);
+}
+
+constexpr int kPLx = 4096, kPLy = 2048, kPRows = 32, kPPlanes = 27;
+__constant__ int kPcx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__constant__ int kPcy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+// Layout 0: planes [27][ly][lx]; layout 1: [ly][lx/64][27][64].
+template <int kLayout>
+__device__ inline size_t pattern_index(int row, int col, int p) {
+  if (kLayout == 0) return ((size_t)p * kPLy + row) * kPLx + col;
+  return ((size_t)row * (kPLx / 64) + (col >> 6)) * (kPPlanes * 64) + (size_t)p * 64 + (col & 63);
+}
+
+template <int kLayout, bool kOrder>
+__global__ __launch_bounds__(256) void step_pattern(const float* __restrict__ src,
+                                                    float* __restrict__ dst) {
+  const int nbx = gridDim.x, ntiles = gridDim.x * gridDim.y;
+  const int lin = blockIdx.y * nbx + blockIdx.x;
+  int tile = lin;
+  if (kOrder) {
+    const int xcd = lin % 8;
+    tile = xcd * (ntiles / 8) + min(xcd, ntiles % 8) + lin / 8;
+  }
+  const int chunk = tile / nbx, strip = tile - chunk * nbx;
+  const int x = strip * 256 + threadIdx.x;  // grid covers x in [0, kPLx) exactly
+  const int xm = x == 0 ? kPLx - 1 : x - 1, xp = x == kPLx - 1 ? 0 : x + 1;
+  const bool down = kOrder && (chunk & 1);
+  for (int k = 0; k < kPRows; ++k) {
+    const int r = down ? chunk * kPRows + kPRows - 1 - k : chunk * kPRows + k;
+    float acc = 0.f;
+#pragma unroll
+    for (int p = 0; p < kPPlanes; ++p) {
+      const int i = p % 9;
+      int sr = r - kPcy[i];
+      sr = sr < 0 ? 0 : (sr >= kPLy ? kPLy - 1 : sr);
+      const int sx = kPcx[i] > 0 ? xm : (kPcx[i] < 0 ? xp : x);
+      acc += src[pattern_index<kLayout>(sr, sx, p)];
+    }
+    if (kOrder) __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kPPlanes; ++p)
+      __builtin_nontemporal_store(acc + (float)p, dst + pattern_index<kLayout>(r, x, p));
+  }
 }
 
 int main() {
@@ -89,6 +141,38 @@ int main() {
       first = false;
     }
   }
+  std::printf("], \"step_pattern\": [");
+  CHECK(hipFree(a));
+  CHECK(hipFree(b));
+  const size_t pbytes = (size_t)kPPlanes * kPLx * kPLy * sizeof(float);
+  float *pa = nullptr, *pb = nullptr;
+  CHECK(hipMalloc(&pa, pbytes));
+  CHECK(hipMalloc(&pb, pbytes));
+  CHECK(hipMemset(pa, 0, pbytes));
+  CHECK(hipMemset(pb, 0, pbytes));
+  const char* pnames[] = {"planes_plain_order", "planes_step_order", "interleaved_step_order"};
+  const dim3 pgrid(kPLx / 256, kPLy / kPRows);
+  for (int kind = 0; kind < 3; ++kind) {
+    auto launch = [&]() {
+      if (kind == 0) hipLaunchKernelGGL((step_pattern<0, false>), pgrid, dim3(256), 0, 0, pa, pb);
+      else if (kind == 1) hipLaunchKernelGGL((step_pattern<0, true>), pgrid, dim3(256), 0, 0, pa, pb);
+      else hipLaunchKernelGGL((step_pattern<1, true>), pgrid, dim3(256), 0, 0, pa, pb);
+    };
+    launch();
+    CHECK(hipGetLastError());
+    CHECK(hipDeviceSynchronize());
+    CHECK(hipEventRecord(e0));
+    for (int it = 0; it < 20; ++it) launch();
+    CHECK(hipEventRecord(e1));
+    CHECK(hipEventSynchronize(e1));
+    float ms = 0;
+    CHECK(hipEventElapsedTime(&ms, e0, e1));
+    ms /= 20;
+    std::printf("%s{\"kernel\": \"%s\", \"us\": %.1f, \"GBps\": %.1f}", kind ? ", " : "",
+                pnames[kind], ms * 1e3, 2.0 * pbytes / ms / 1e6);
+  }
   std::printf("]}\n");
+  CHECK(hipFree(pa));
+  CHECK(hipFree(pb));
   return 0;
 }
