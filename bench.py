@@ -32,6 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # written once, plus one byte of solid flag when the lattice has solid cells.
 BYTES_PER_POP = {"fp64": 8, "fp32": 4, "fp16dev": 2, "bf16dev": 2, "fix16dev": 2}
 KERNEL_SOURCES = ("paper_2109_12565_amd/csrc/lb_kernels.hpp",
+                  "paper_2109_12565_amd/csrc/lb_step2.hpp",
                   "paper_2109_12565_amd/csrc/launch_impl.hpp",
                   "paper_2109_12565_amd/csrc/tlb.hip")
 
@@ -44,15 +45,15 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, precision: str):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
+def measured_traffic(workload: str, precision: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_hash") != kernel_hash():
+    if rec.get("kernel_hash") != kernel_hash() or kernel not in rec.get("kernel", ""):
         return None
     return rec.get("bytes_per_launch")
 
@@ -233,20 +234,48 @@ def main() -> int:
     t_drop = time.perf_counter() - t_drop
     step_ms = e0.elapsed_time(e1)          # the K step launches only
     total_ms = e0.elapsed_time(e2)         # whole job: steps + observables
+    # single-step launches timed on their own (each call of one step is one
+    # launch of the single-step kernel), after everything reported above
+    n_one = 20
+    e3, e4 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+    e3.record(stream)
+    for _ in range(n_one):
+        sim.step(1)
+    e4.record(stream)
+    torch.cuda.synchronize()
+    single_s = e3.elapsed_time(e4) * 1e-3 / n_one
 
+    # launches of the timed region: tlb_step runs fused two-step launches
+    # while at least three steps remain and ends with single steps
+    launch = sim.launch_info()
+    n_fused = (args.steps - 1) // 2 if launch["fused_rows"] > 0 and args.steps >= 3 else 0
+    n_single = args.steps - 2 * n_fused
     nodes = w["lx"] * w["ly"]
     mlups = nodes * args.steps / (total_ms * 1e-3) / 1e6
-    per_launch_s = step_ms * 1e-3 / args.steps
     bpn = 54 * BYTES_PER_POP[args.precision] + (1 if w["solid"] is not None else 0)
+    if n_fused > 0:
+        kernel, updates = "lb_step2_kernel", 2
+        per_launch_s = (step_ms * 1e-3 - n_single * single_s) / n_fused
+    else:
+        kernel, updates = "lb_step_kernel", 1
+        per_launch_s = step_ms * 1e-3 / args.steps
+    # algorithmic bytes per launch: every population read once and written
+    # once per launch, whether the launch advances one step or two
     achieved = bpn * nodes / per_launch_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "lb_step_kernel", "bytes_per_node": bpn, "nodes_per_launch": nodes,
-            "launch_us": round(per_launch_s * 1e6, 2)}
-    traffic = measured_traffic(w["name"], args.precision)
+            "kernel": kernel, "bytes_per_node": bpn, "nodes_per_launch": nodes,
+            "updates_per_node": updates, "launch_us": round(per_launch_s * 1e6, 2),
+            "launches": {"fused": n_fused, "single": n_single}}
+    traffic = measured_traffic(w["name"], args.precision, kernel)
     if traffic is not None:
         roof["traffic"] = round(traffic / per_launch_s / 1e9, 1)
         roof["traffic_bytes_per_launch"] = traffic
+    single_gbs = bpn * nodes / single_s / 1e9
+    roof["single_step_kernel"] = {"kernel": "lb_step_kernel", "launch_us": round(single_s * 1e6, 2),
+                                  "achieved": round(single_gbs, 1),
+                                  "frac": round(single_gbs / HBM_PEAK_GBS, 4),
+                                  "mlups": round(nodes / single_s / 1e6, 1)}
 
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,

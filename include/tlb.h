@@ -235,6 +235,20 @@ int tlb_adjoint_step(tlb_handle *h, int64_t nsteps, double seed, double *grad_t_
 /* Current time step. Returns -1 for a NULL handle. */
 int64_t tlb_time(const tlb_handle *h);
 
+/* Launch geometry chosen by tlb_init for the step kernels (Sec. 2.5 maps the
+ * lattice onto GPU threads; here a block of `bx` threads marches over a
+ * chunk of `rows` rows of a `bx`-column strip). fused_rows > 0 means that
+ * tlb_step advances pairs of steps with the fused two-step kernel (tau =
+ * tau_g = 1, FP32 / FP64, walls at rest; strips of fused_strip stored
+ * columns, chunks of fused_rows rows); every tlb_step call still ends with a
+ * single step. Host struct, written by the call. Returns TLB_EINVAL on a
+ * NULL argument. */
+typedef struct tlb_launch {
+  int32_t bx, rows, grid_x, grid_y;
+  int32_t fused_rows, fused_strip, fused_grid_x, fused_grid_y;
+} tlb_launch;
+int tlb_launch_info(const tlb_handle *h, tlb_launch *out);
+
 /* Free the handle and its device memory. NULL is accepted. */
 int tlb_destroy(tlb_handle *h);
 

@@ -23,7 +23,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "fp16dev": 2, "bf16dev": 3, "fix16dev": 4}
 EXPORTS = (
     "tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_stress",
     "tlb_row_averages", "tlb_droplets", "tlb_get_populations", "tlb_set_bottom_temperature",
-    "tlb_forward_taped", "tlb_adjoint_step", "tlb_time", "tlb_destroy", "tlb_last_error",
+    "tlb_forward_taped", "tlb_adjoint_step", "tlb_time", "tlb_launch_info", "tlb_destroy",
+    "tlb_last_error",
 )
 
 
@@ -51,6 +52,12 @@ class Obs(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("mass_a", ctypes.c_double), ("mass_b", ctypes.c_double),
                 ("sum_t", ctypes.c_double), ("nu", ctypes.c_double), ("nu_top", ctypes.c_double),
                 ("ke", ctypes.c_double)]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in
+                ("bx", "rows", "grid_x", "grid_y",
+                 "fused_rows", "fused_strip", "fused_grid_x", "fused_grid_y")]
 
 
 class Droplet(ctypes.Structure):
@@ -92,13 +99,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tlb_adjoint_step.argtypes = [vp, ctypes.c_int64, ctypes.c_double, dp]
     lib.tlb_time.argtypes = [vp]
     lib.tlb_time.restype = ctypes.c_int64
+    lib.tlb_launch_info.argtypes = [vp, ctypes.POINTER(Launch)]
     lib.tlb_destroy.argtypes = [vp]
     lib.tlb_last_error.argtypes = [vp]
     lib.tlb_last_error.restype = ctypes.c_char_p
     for name in ("tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_stress",
                  "tlb_row_averages", "tlb_droplets", "tlb_get_populations",
                  "tlb_set_bottom_temperature",
-                 "tlb_forward_taped", "tlb_adjoint_step", "tlb_destroy"):
+                 "tlb_forward_taped", "tlb_adjoint_step", "tlb_launch_info", "tlb_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -195,6 +203,13 @@ class Simulation:
     @property
     def t(self) -> int:
         return int(self._lib.tlb_time(self._h))
+
+    def launch_info(self) -> dict:
+        """Launch geometry of the step kernels (fused_rows > 0: the fused
+        two-step kernel advances pairs of steps)."""
+        g = Launch()
+        self._check(self._lib.tlb_launch_info(self._h, ctypes.byref(g)))
+        return {k: getattr(g, k) for k, _ in Launch._fields_}
 
     def step(self, n: int = 1) -> "Simulation":
         self._check(self._lib.tlb_step(self._h, int(n)))

@@ -15,7 +15,17 @@ struct Geometry {
   int rows = 1;      // rows per block chunk
   bool wide = false; // 64-bit byte offsets (population buffer >= 4 GiB)
   dim3 grid;
+  // fused two-step kernel (tau = tau_g = 1, FP32 / FP64, walls at rest);
+  // rows2 == 0: not used
+  int rows2 = 0;     // rows per block chunk
+  int strip2 = 0;    // stored columns per strip (kStep2Lanes - kStep2Halo at most)
+  dim3 grid2;
 };
+
+// Lanes per block of the two-step kernel and the columns of each strip that
+// only feed the others (5 on each side).
+constexpr int kStep2Lanes = 256;
+constexpr int kStep2Halo = 10;
 
 // Everything a launch needs from a handle.
 struct Device {
@@ -43,13 +53,17 @@ enum class Pass {
   kFields,       // fields of time t from f*(t-1), no store
   kFieldsInit,   // same at t = 0 from f(0)
   kStress,       // fields and xy stress of time t (general path), no store
-  kStressInit    // same at t = 0 from f(0)
+  kStressInit,   // same at t = 0 from f(0)
+  kStep2         // f*(t) -> f*(t+2), fused two-step kernel (Geometry::rows2 > 0)
 };
 
 template <class St>
 struct Launcher {
   // Resident blocks per CU of the step kernel for this geometry.
   static int blocks_per_cu(int bx, bool wide, bool solid, bool tau_one);
+  // Resident blocks per CU of the two-step kernel; 0 where the storage has
+  // no two-step kernel.
+  static int step2_blocks_per_cu(bool solid);
   static void step(const Device& d, Pass pass, const void* src, void* dst);
   // f(0) = equilibria of the initial fields (rho_a, rho_b, temp, ux0, uy0;
   // the velocities may be null).

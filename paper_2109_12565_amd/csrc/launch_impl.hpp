@@ -3,6 +3,7 @@
 
 #include "launch.hpp"
 #include "lb_kernels.hpp"
+#include "lb_step2.hpp"
 
 namespace tlbh {
 
@@ -108,7 +109,46 @@ int occupancy_geometry(int bx, bool wide) {
   return occupancy<St, 64, kMode>();
 }
 
+template <class St, unsigned kMode>
+void launch_step2_kernel(const Device& d, const tlbk::StepArgs<typename St::C>& a) {
+  hipLaunchKernelGGL((tlbk::lb_step2_kernel<St, kStep2Lanes, kMode>), d.geo.grid2,
+                     dim3(kStep2Lanes), 0, d.stream, a, d.geo.strip2);
+}
+
+template <class St>
+void launch_step2(const Device& d, const void* src, void* dst) {
+  if constexpr (!St::kDev && !St::kFix) {
+    auto a = make_args<typename St::C>(d, src, dst);
+    a.rows_per_block = d.geo.rows2;
+    constexpr unsigned M = tlbk::kModeStore | tlbk::kModeTauOne;
+    if (d.has_solid) launch_step2_kernel<St, M | tlbk::kModeSolid>(d, a);
+    else launch_step2_kernel<St, M>(d, a);
+  }
+}
+
+template <class St, unsigned kMode>
+int step2_occupancy() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, tlbk::lb_step2_kernel<St, kStep2Lanes, kMode>, kStep2Lanes, 0) != hipSuccess ||
+      n < 1)
+    n = 1;
+  return n;
+}
+
 }  // namespace detail
+
+template <class St>
+int Launcher<St>::step2_blocks_per_cu(bool solid) {
+  if constexpr (!St::kDev && !St::kFix) {
+    constexpr unsigned M = tlbk::kModeStore | tlbk::kModeTauOne;
+    return solid ? detail::step2_occupancy<St, M | tlbk::kModeSolid>()
+                 : detail::step2_occupancy<St, M>();
+  } else {
+    (void)solid;
+    return 0;
+  }
+}
 
 template <class St>
 int Launcher<St>::blocks_per_cu(int bx, bool wide, bool solid, bool tau_one) {
@@ -136,6 +176,7 @@ void Launcher<St>::step(const Device& d, Pass pass, const void* src, void* dst) 
     case Pass::kStressInit:
       detail::launch_mode<St, kModeFields | kModeStress | kModeInit>(d, src, dst);
       break;
+    case Pass::kStep2: detail::launch_step2<St>(d, src, dst); break;
   }
 }
 

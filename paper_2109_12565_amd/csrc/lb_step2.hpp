@@ -1,0 +1,433 @@
+// Fused two-step update f*(t) -> f*(t+2) for tau = tau_g = 1 (arXiv:2109.12565,
+// Sec. 2), FP32 and FP64 storage, walls at rest.
+//
+// At tau = tau_g = 1 the BGK collision (Eqs. (2), (16)) returns the
+// equilibria (Eqs. (3), (18)), so the post-collision populations of a node
+// are fixed by nine moments: rho_A and u_A, rho_B and u_B (the velocities
+// shifted by the force, Eq. (6)), T and u^H. One launch therefore advances
+// two time steps while the 27 population planes cross HBM once:
+//
+//   level 1  the ordinary step on the populations of time t read from HBM
+//            (pull with half-way bounce-back and anti-bounce-back, Sec. 2.2;
+//            moments; psi in an LDS ring; forces, Eqs. (7)-(11), (22);
+//            velocities), ending in the nine moments of each node, which go
+//            to an LDS ring instead of HBM;
+//   level 2  pulls each population of time t+1 from the moments of its
+//            source node (the rest population as the remainder of the zeroth
+//            moment, as the single step stores it), then completes the step
+//            and stores f*(t+2) with 27 aligned stores.
+//
+// The level-2 pull evaluates the expressions with which the single-step
+// kernel forms and stores its equilibria, so two fused steps give the
+// numbers of two single steps up to the rounding of multiply-adds, which the
+// compiler may contract differently in the two kernels.
+//
+// Halo. Level-2 collisions of a lane need level-2 densities of the lanes
+// within 2, which need level-1 moments within 3, which need level-1
+// densities within 5. A block of BT lanes computes BT consecutive (periodic)
+// columns and stores the middle ones; neighbouring strips overlap by 10
+// columns, so no lane does halo work of another kind. In y the chunk's rows
+// are extended by 5 rows of level 1 on each side.
+//
+// Row pipeline. Iteration k handles four rows in two phases separated by
+// barriers (up-marching chunk; a down-marching chunk mirrors the offsets):
+//   phase 1  issue the HBM pulls of row ra (f) and of row rb = ra - 2 (g);
+//            level-2 pull of row rc = ra - 4 from the moment ring into the
+//            level-2 density ring; level-1 densities of row ra into the
+//            level-1 density ring;
+//   phase 2  level-1 forces and moments of row rb into the moment ring;
+//            level-2 forces, collision and stores of row rd = ra - 6.
+// The density rings hold 5 rows and the moment ring 3 (rows by absolute
+// index); each ring row written in one phase is read only after the next
+// barrier and overwritten only after every read of it.
+#pragma once
+
+#include "lb_kernels.hpp"
+
+namespace tlbk {
+
+// Ring slot of row r for a ring of R rows (r >= -8 R).
+template <int R>
+__device__ inline int ring_slot(int r) {
+  return (r + 8 * R) % R;
+}
+
+// Even and odd parts of the equilibrium of the direction pair P, opp(P):
+// f^eq_P = S + D, f^eq_opp(P) = S - D (Eqs. (3), (18)); the same expressions
+// as the single-step collision.
+template <int P, typename C>
+__device__ inline void eq_even_odd(C rho, C ux, C uy, C u2, C& S, C& D) {
+  constexpr int cx = Dir<P>::cx, cy = Dir<P>::cy;
+  constexpr C w = w_dir<C>(P);
+  const C cu = C(cx) * ux + C(cy) * uy;
+  S = w * rho * (C(1) + C(4.5) * cu * cu - C(1.5) * u2);
+  D = C(3) * w * rho * cu;
+}
+
+// Forces on both components at ring column s0, rows rs[0..4] = dy -2..2:
+// self interaction with nearest-neighbour attraction and 25-point repulsion
+// (Eqs. (10), (11), weights of Fig. 1(b)), cross repulsion with
+// psi = rho / rho0 (Eqs. (7), (8)), buoyancy (Eq. (22)). Same arithmetic as
+// the single-step kernel.
+template <typename C, int R, int W>
+__device__ inline void step2_forces(const StepArgs<C>& a, const C (&s_rho)[2][R][W],
+                                    const C (&s_psi)[2][R][W], const int (&rs)[5], int s0, C ra,
+                                    C rb, C temp, C (&FA)[2], C (&FB)[2]) {
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+    C ax = 0, ay = 0, qx = 0, qy = 0;
+#pragma unroll
+    for (int dy = -2; dy <= 2; ++dy) {
+#pragma unroll
+      for (int dx = 1; dx <= 2; ++dx) {
+        const int c2 = dx * dx + dy * dy;
+        const C diff = s_psi[l][rs[dy + 2]][s0 + dx] - s_psi[l][rs[dy + 2]][s0 - dx];
+        qx += (p_c2<C>(c2) * C(dx)) * diff;
+        if (c2 <= 2) ax += (w_c2<C>(c2) * C(dx)) * diff;
+      }
+    }
+#pragma unroll
+    for (int dx = -2; dx <= 2; ++dx) {
+#pragma unroll
+      for (int dy = 1; dy <= 2; ++dy) {
+        const int c2 = dx * dx + dy * dy;
+        const C diff = s_psi[l][rs[dy + 2]][s0 + dx] - s_psi[l][rs[2 - dy]][s0 + dx];
+        qy += (p_c2<C>(c2) * C(dy)) * diff;
+        if (c2 <= 2) ay += (w_c2<C>(c2) * C(dy)) * diff;
+      }
+    }
+    const C psi_here = s_psi[l][rs[2]][s0];
+    const C ga = l == 0 ? a.ga0 : a.ga1;
+    const C gr = l == 0 ? a.gr0 : a.gr1;
+    C* F = l == 0 ? FA : FB;
+    F[0] = -psi_here * (ga * ax + gr * qx);
+    F[1] = -psi_here * (ga * ay + gr * qy);
+  }
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+    const int m = 1 - l;
+    C sx = 0, sy = 0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int c2 = 1 + dy * dy;
+      sx += w_c2<C>(c2) * (s_rho[m][rs[dy + 2]][s0 + 1] - s_rho[m][rs[dy + 2]][s0 - 1]);
+    }
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int c2 = 1 + dx * dx;
+      sy += w_c2<C>(c2) * (s_rho[m][rs[3]][s0 + dx] - s_rho[m][rs[1]][s0 + dx]);
+    }
+    const C rl = l == 0 ? ra : rb;
+    const C pre = -a.g12 * rl * a.inv_rho0 * a.inv_rho0;
+    C* F = l == 0 ? FA : FB;
+    F[0] += pre * sx;
+    F[1] += pre * sy;
+  }
+  FA[1] += ra * a.alpha_g * temp;
+  FB[1] += rb * a.alpha_g * temp;
+}
+
+// Moments of a level-1 node kept in the moment ring.
+enum : int { kMa = 0, kMuax, kMuay, kMb, kMubx, kMuby, kMt, kMhx, kMhy, kMoments };
+
+// Level-2 pull of direction I (1..8) at a node from the moment ring: the
+// value f*_I(x - c_I) of the source node, or, across a solid link, the
+// node's own f*_opp(I) (bounce-back) and 2 w_I T_w - g*_opp(I) (anti-
+// bounce-back). Both alternatives belong to the pair of I, so a lane
+// selects its ring cell and the sign of the odd part.
+template <int I, unsigned kMode, typename C, int RM, int WM>
+__device__ inline void pull_level2(const StepArgs<C>& a, const C (&sm)[kMoments][RM][WM],
+                                   int slot_own, int col_own, int x, int r, uint32_t lm,
+                                   C (&fa)[9], C (&fb)[9], C (&g)[9]) {
+  constexpr int P = (I == 1 || I == 2 || I == 5 || I == 6) ? I : Dir<I>::opp;
+  const bool bb = ((lm >> I) & 1u) != 0u;
+  const int s = bb ? slot_own : ring_slot<RM>(r - Dir<I>::cy);
+  const int c = bb ? col_own : col_own - Dir<I>::cx;
+  const C da = sm[kMa][s][c], uax = sm[kMuax][s][c], uay = sm[kMuay][s][c];
+  const C db = sm[kMb][s][c], ubx = sm[kMubx][s][c], uby = sm[kMuby][s][c];
+  const C dt = sm[kMt][s][c], hx = sm[kMhx][s][c], hy = sm[kMhy][s][c];
+  const C ua2 = uax * uax + uay * uay;
+  const C ub2 = ubx * ubx + uby * uby;
+  const C uh2 = hx * hx + hy * hy;
+  C Sa, Da, Sb, Db, Sg, Dg;
+  eq_even_odd<P>(da, uax, uay, ua2, Sa, Da);
+  eq_even_odd<P>(db, ubx, uby, ub2, Sb, Db);
+  eq_even_odd<P>(dt, hx, hy, uh2, Sg, Dg);
+  const bool plus = (P == I) != bb;
+  fa[I] = plus ? Sa + Da : Sa - Da;
+  fb[I] = plus ? Sb + Db : Sb - Db;
+  C v = plus ? Sg + Dg : Sg - Dg;
+  if (bb) {
+    const C tw = source_wall_temperature<I, kMode>(a, x, r);
+    v = C(2) * w_dir<C>(I) * tw - v;
+  }
+  g[I] = v;
+}
+
+template <class St, int BT, unsigned kMode>
+__global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a, int strip_w) {
+  using C = typename St::C;
+  using O = Off<kMode>;
+  static_assert(!St::kDev && !St::kFix, "two-step kernel: FP32 / FP64 storage only");
+  static_assert((kMode & kModeTauOne) != 0 && (kMode & kModeStore) != 0, "tau = 1 store pass");
+  static_assert((kMode & (kModeMoving | kModeWide | kModeInit | kModeObserve | kModeFields)) == 0,
+                "walls at rest, 32-bit offsets, no observables");
+  constexpr int kH = 5;          // left halo lanes
+  constexpr int R1 = 5, RM = 3;  // density ring rows, moment ring rows
+  constexpr int W = BT + 4;      // density ring row: lanes plus 2 padding columns each side
+  constexpr int WM = BT + 2;     // moment ring row: 1 padding column each side
+  __shared__ C s1_rho[2][R1][W];
+  __shared__ C s1_psi[2][R1][W];
+  __shared__ C s2_rho[2][R1][W];
+  __shared__ C s2_psi[2][R1][W];
+  __shared__ C sm[kMoments][RM][WM];
+
+  const int lx = a.lx, ly = a.ly;
+  const int tid = threadIdx.x;
+  // XCD-aware tile order and alternating chunk direction, as in the single
+  // step (each XCD receives a contiguous run of tiles).
+  const int nbx = gridDim.x;
+  const int ntiles = gridDim.x * gridDim.y;
+  const int lin = blockIdx.y * nbx + blockIdx.x;
+  constexpr int kXcds = 8;
+  const int xcd = lin % kXcds;
+  const int tile = xcd * (ntiles / kXcds) + min(xcd, ntiles % kXcds) + lin / kXcds;
+  const int chunk = tile / nbx;
+  const int x0 = (tile - chunk * nbx) * strip_w;
+  const int y0 = chunk * a.rows_per_block;
+  const int y1 = min(y0 + a.rows_per_block, ly);
+  const bool down = (chunk & 1) != 0;
+
+  const O row_b = (O)a.pitch * sizeof(C);
+  const O plane_b = (O)a.pop_stride * sizeof(C);
+  const PopMem<St, kMode> msrc(a.src, (uint64_t)plane_b * 27);
+  const PopMem<St, kMode> mdst(a.dst, (uint64_t)plane_b * 27);
+
+  // lane column (periodic); lanes kH .. kH + strip_w - 1 inside the lattice
+  // store, the others compute halo columns only
+  const int xl = x0 - kH + tid;
+  const int xw = ((xl % lx) + lx) % lx;
+  const bool out_lane = tid >= kH && tid < kH + strip_w && xl < lx;
+  const LaneOff<kMode> Lo = lane_off<St, kMode>(xw, lx, plane_b, row_b);
+  const int c1 = tid + 2;  // column in the density rings
+  const int cm = tid + 1;  // column in the moment ring
+
+  const C psi_w0 = psi_of<St>(a.rho_wall0, a.rho0, a.inv_rho0);
+  const C psi_w1 = psi_of<St>(a.rho_wall1, a.rho0, a.inv_rho0);
+  constexpr bool kSolid = (kMode & kModeSolid) != 0;
+
+  // Level 1, phase 1: pull row ra from HBM, densities and psi into ring 1,
+  // keep rho_A, rho_B, j (tau = 1: the moments are all the collision needs).
+  auto level1_density = [&](int r, C (&kw)[4], uint32_t& lw) {
+    C ra = a.rho_wall0, rb = a.rho_wall1, pa = psi_w0, pb = psi_w1;
+    lw = kSelfSolid;
+    if (r >= 0 && r < ly) {
+      lw = link_mask<kMode>(a, xw, r);
+      if (!(kSolid && (lw & kSelfSolid))) {
+        C f[18];
+        pull_fluid<St, kMode>(a, msrc, Lo, r, lw, f);
+        kw[0] = sum9(f);
+        kw[1] = sum9(f + 9);
+        kw[2] = momentum_x(f, f + 9);
+        kw[3] = momentum_y(f, f + 9);
+        ra = kw[0];
+        rb = kw[1];
+        pa = psi_of<St>(ra, a.rho0, a.inv_rho0);
+        pb = psi_of<St>(rb, a.rho0, a.inv_rho0);
+      }
+    }
+    const int s = ring_slot<R1>(r);
+    s1_rho[0][s][c1] = ra;
+    s1_rho[1][s][c1] = rb;
+    s1_psi[0][s][c1] = pa;
+    s1_psi[1][s][c1] = pb;
+  };
+
+  // Level 1, phase 2: forces and velocities of fluid row r; its nine
+  // moments into the moment ring.
+  auto level1_moments = [&](int r, const C (&ku)[4], const C (&g)[9]) {
+    const C Da = ku[0], Db = ku[1], jx = ku[2], jy = ku[3];
+    const C ra = Da, rb = Db;
+    const C Dt = sum9(g);
+    const C temp = Dt;
+    int rs[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) rs[d] = ring_slot<R1>(r - 2 + d);
+    C FA[2], FB[2];
+    step2_forces(a, s1_rho, s1_psi, rs, c1, ra, rb, temp, FA, FB);
+    const C rho = ra + rb;
+    const C inv_rho = recip<St>(rho);
+    const C ux = jx * inv_rho, uy = jy * inv_rho;
+    const C Fx = FA[0] + FB[0], Fy = FA[1] + FB[1];
+    const C hx = ux + C(0.5) * Fx * inv_rho;
+    const C hy = uy + C(0.5) * Fy * inv_rho;
+    const C tA = a.tau * recip<St>(ra), tB = a.tau * recip<St>(rb);
+    const C uax = ux + FA[0] * tA, uay = uy + FA[1] * tA;
+    const C ubx = ux + FB[0] * tB, uby = uy + FB[1] * tB;
+    const int s = ring_slot<RM>(r);
+    sm[kMa][s][cm] = Da;
+    sm[kMuax][s][cm] = uax;
+    sm[kMuay][s][cm] = uay;
+    sm[kMb][s][cm] = Db;
+    sm[kMubx][s][cm] = ubx;
+    sm[kMuby][s][cm] = uby;
+    sm[kMt][s][cm] = Dt;
+    sm[kMhx][s][cm] = hx;
+    sm[kMhy][s][cm] = hy;
+  };
+
+  // Level 2, phase 1: pull row r from the moment ring; densities and psi
+  // into ring 2; keep rho_A, rho_B, j, T.
+  auto level2_density = [&](int r, C (&kw)[5], uint32_t& lw) {
+    C ra = a.rho_wall0, rb = a.rho_wall1, pa = psi_w0, pb = psi_w1;
+    lw = kSelfSolid;
+    if (r >= 0 && r < ly) {
+      lw = link_mask<kMode>(a, xw, r);
+      if (!(kSolid && (lw & kSelfSolid))) {
+        const int so = ring_slot<RM>(r);
+        C fa[9], fb[9], g[9];
+        {
+          // rest populations: the zeroth moments minus the moving equilibria
+          const C da = sm[kMa][so][cm], uax = sm[kMuax][so][cm], uay = sm[kMuay][so][cm];
+          const C db = sm[kMb][so][cm], ubx = sm[kMubx][so][cm], uby = sm[kMuby][so][cm];
+          const C dt = sm[kMt][so][cm], hx = sm[kMhx][so][cm], hy = sm[kMhy][so][cm];
+          const C ua2 = uax * uax + uay * uay;
+          const C ub2 = ubx * ubx + uby * uby;
+          const C uh2 = hx * hx + hy * hy;
+          C sa = 0, sb = 0, sg = 0;
+#define TLB_REST(P)                                \
+  {                                                \
+    C Sa, Dla, Sb, Dlb, Sg, Dlg;                   \
+    eq_even_odd<P>(da, uax, uay, ua2, Sa, Dla);    \
+    eq_even_odd<P>(db, ubx, uby, ub2, Sb, Dlb);    \
+    eq_even_odd<P>(dt, hx, hy, uh2, Sg, Dlg);      \
+    sa += (Sa + Dla) + (Sa - Dla);                 \
+    sb += (Sb + Dlb) + (Sb - Dlb);                 \
+    sg += (Sg + Dlg) + (Sg - Dlg);                 \
+  }
+          TLB_REST(1) TLB_REST(2) TLB_REST(5) TLB_REST(6)
+#undef TLB_REST
+          fa[0] = da - sa;
+          fb[0] = db - sb;
+          g[0] = dt - sg;
+        }
+        pull_level2<1, kMode>(a, sm, so, cm, xw, r, lw, fa, fb, g);
+        pull_level2<2, kMode>(a, sm, so, cm, xw, r, lw, fa, fb, g);
+        pull_level2<3, kMode>(a, sm, so, cm, xw, r, lw, fa, fb, g);
+        pull_level2<4, kMode>(a, sm, so, cm, xw, r, lw, fa, fb, g);
+        pull_level2<5, kMode>(a, sm, so, cm, xw, r, lw, fa, fb, g);
+        pull_level2<6, kMode>(a, sm, so, cm, xw, r, lw, fa, fb, g);
+        pull_level2<7, kMode>(a, sm, so, cm, xw, r, lw, fa, fb, g);
+        pull_level2<8, kMode>(a, sm, so, cm, xw, r, lw, fa, fb, g);
+        kw[0] = sum9(fa);
+        kw[1] = sum9(fb);
+        kw[2] = momentum_x(fa, fb);
+        kw[3] = momentum_y(fa, fb);
+        kw[4] = sum9(g);
+        ra = kw[0];
+        rb = kw[1];
+        pa = psi_of<St>(ra, a.rho0, a.inv_rho0);
+        pb = psi_of<St>(rb, a.rho0, a.inv_rho0);
+      }
+    }
+    const int s = ring_slot<R1>(r);
+    s2_rho[0][s][c1] = ra;
+    s2_rho[1][s][c1] = rb;
+    s2_psi[0][s][c1] = pa;
+    s2_psi[1][s][c1] = pb;
+  };
+
+  // Level 2, phase 2: collision of row r and the 27 stores of f*(t+2).
+  auto level2_collide = [&](int r, const C (&ku)[5], uint32_t lu) {
+    const O yrow = (O)r * row_b;
+    if (kSolid && (lu & kSelfSolid)) {
+#pragma unroll
+      for (int p = 0; p < 27; ++p) mdst.st((O)p * plane_b + yrow, Lo.v0, C(0));
+      return;
+    }
+    const C Da = ku[0], Db = ku[1], jx = ku[2], jy = ku[3], Dt = ku[4];
+    const C ra = Da, rb = Db, temp = Dt;
+    int rs[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) rs[d] = ring_slot<R1>(r - 2 + d);
+    C FA[2], FB[2];
+    step2_forces(a, s2_rho, s2_psi, rs, c1, ra, rb, temp, FA, FB);
+    const C rho = ra + rb;
+    const C inv_rho = recip<St>(rho);
+    const C ux = jx * inv_rho, uy = jy * inv_rho;
+    const C Fx = FA[0] + FB[0], Fy = FA[1] + FB[1];
+    const C hx = ux + C(0.5) * Fx * inv_rho;
+    const C hy = uy + C(0.5) * Fy * inv_rho;
+    const C tA = a.tau * recip<St>(ra), tB = a.tau * recip<St>(rb);
+    const C uax = ux + FA[0] * tA, uay = uy + FA[1] * tA;
+    const C ubx = ux + FB[0] * tB, uby = uy + FB[1] * tB;
+    const C ua2 = uax * uax + uay * uay;
+    const C ub2 = ubx * ubx + uby * uby;
+    const C uh2 = hx * hx + hy * hy;
+    C sa = 0, sb = 0, sg = 0;
+    const O p9 = plane_b * 9, p18 = plane_b * 18;
+#define TLB_PAIR2(I)                                        \
+  {                                                         \
+    constexpr int J = Dir<I>::opp;                          \
+    C Sa, Dla, Sb, Dlb, Sg, Dlg;                            \
+    eq_even_odd<I>(ra, uax, uay, ua2, Sa, Dla);             \
+    eq_even_odd<I>(rb, ubx, uby, ub2, Sb, Dlb);             \
+    eq_even_odd<I>(temp, hx, hy, uh2, Sg, Dlg);             \
+    const C eaI = Sa + Dla, eaJ = Sa - Dla;                 \
+    const C ebI = Sb + Dlb, ebJ = Sb - Dlb;                 \
+    const C egI = Sg + Dlg, egJ = Sg - Dlg;                 \
+    sa += eaI + eaJ;                                        \
+    sb += ebI + ebJ;                                        \
+    sg += egI + egJ;                                        \
+    const O oI = (O)I * plane_b + yrow, oJ = (O)J * plane_b + yrow; \
+    mdst.st(oI, Lo.v0, eaI);                                \
+    mdst.st(oJ, Lo.v0, eaJ);                                \
+    mdst.st(oI + p9, Lo.v0, ebI);                           \
+    mdst.st(oJ + p9, Lo.v0, ebJ);                           \
+    mdst.st(oI + p18, Lo.v0, egI);                          \
+    mdst.st(oJ + p18, Lo.v0, egJ);                          \
+  }
+    TLB_PAIR2(1) TLB_PAIR2(2) TLB_PAIR2(5) TLB_PAIR2(6)
+#undef TLB_PAIR2
+    mdst.st(yrow, Lo.v0, Da - sa);
+    mdst.st(yrow + p9, Lo.v0, Db - sb);
+    mdst.st(yrow + p18, Lo.v0, Dt - sg);
+  };
+
+  // One row iteration (see the header): ra = first + dir k.
+  const int dir = down ? -1 : 1;
+  const int first = down ? y1 - 1 + 5 : y0 - 5;
+  auto in_rows = [&](int r, int lo, int hi) { return r >= lo && r < hi && r >= 0 && r < ly; };
+  auto iterate = [&](int k, C (&k1w)[4], uint32_t& l1w, const C (&k1u)[4], uint32_t l1u,
+                     C (&k2w)[5], uint32_t& l2w, const C (&k2u)[5], uint32_t l2u) {
+    const int ra = first + dir * k;
+    const int rb = ra - 2 * dir, rc = ra - 4 * dir, rd = ra - 6 * dir;
+    const bool do_a = ra >= y0 - 5 && ra < y1 + 5;
+    const bool do_b = in_rows(rb, y0 - 3, y1 + 3) && !(kSolid && (l1u & kSelfSolid));
+    const bool do_c = rc >= y0 - 2 && rc < y1 + 2;
+    const bool do_d = out_lane && rd >= y0 && rd < y1;
+    // phase 1
+    C g[9];
+    if (do_b) pull_thermal<St, kMode>(a, msrc, Lo, xw, rb, l1u, g);
+    if (do_c) level2_density(rc, k2w, l2w);
+    if (do_a) level1_density(ra, k1w, l1w);
+    __syncthreads();
+    // phase 2
+    if (do_b) level1_moments(rb, k1u, g);
+    if (do_d) level2_collide(rd, k2u, l2u);
+    __syncthreads();
+  };
+
+  C f0[4], f1[4], f2[4];
+  C h0[5], h1[5], h2[5];
+  uint32_t l0 = kSelfSolid, l1 = kSelfSolid, l2 = kSelfSolid;
+  uint32_t m0 = kSelfSolid, m1 = kSelfSolid, m2 = kSelfSolid;
+  const int n_iter = ((y1 - y0) + 11 + 2) / 3 * 3;
+  for (int k = 0; k < n_iter; k += 3) {
+    iterate(k, f0, l0, f1, l1, h0, m0, h1, m1);
+    iterate(k + 1, f1, l1, f2, l2, h1, m1, h2, m2);
+    iterate(k + 2, f2, l2, f0, l0, h2, m2, h0, m0);
+  }
+}
+
+}  // namespace tlbk

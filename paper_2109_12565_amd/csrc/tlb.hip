@@ -138,6 +138,42 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
   }
   l.rows = (int)(rows < ly ? rows : ly);
   l.grid = dim3((unsigned)strips, (unsigned)((ly + l.rows - 1) / l.rows), 1);
+
+  // Fused two-step kernel: tau = tau_g = 1, FP32 or FP64 storage, walls at
+  // rest, 32-bit offsets. Its strips overlap by kStep2Halo columns and its
+  // chunks recompute 5 rows of the first step on each side, so it pays
+  // where the chunks can be tall and the grid still fills every CU once:
+  // chunks of at least 24 rows, one block per resident slot. TLB_STEP2=1
+  // selects it wherever it applies, TLB_STEP2=0 never.
+  const bool moving = p.u_wall[0] != 0.0 || p.u_wall[1] != 0.0;
+  const bool eligible = tau_one && !moving && !l.wide &&
+                        (p.precision == TLB_FP32 || p.precision == TLB_FP64);
+  const char* step2_env = std::getenv("TLB_STEP2");
+  const int step2_mode = step2_env ? std::atoi(step2_env) : -1;
+  if (eligible && step2_mode != 0) {
+    int per_cu2 = 0;
+    with_storage(p.precision, [&](auto st) {
+      per_cu2 = tlbh::Launcher<decltype(st)>::step2_blocks_per_cu(solid);
+    });
+    const int max_strip = tlbh::kStep2Lanes - tlbh::kStep2Halo;
+    const long long strips2 = (lx + max_strip - 1) / max_strip;
+    const int strip2 = (int)((lx + strips2 - 1) / strips2);
+    // at most one block per resident slot: a second, partial wave of blocks
+    // would take as long as the first
+    const long long slots = (long long)cus * std::max(per_cu2, 1);
+    const long long max_chunks = std::max(1LL, slots / strips2);
+    long long rows2 = (ly + max_chunks - 1) / max_chunks;
+    const bool pays = rows2 >= 24;
+    if (per_cu2 > 0 && (pays || step2_mode == 1)) {
+      if (const char* env = std::getenv("TLB_STEP2_ROWS")) {
+        int v = std::atoi(env);
+        if (v >= 1 && v <= 4096) rows2 = v;
+      }
+      l.rows2 = (int)(rows2 < ly ? rows2 : ly);
+      l.strip2 = strip2;
+      l.grid2 = dim3((unsigned)strips2, (unsigned)((ly + l.rows2 - 1) / l.rows2), 1);
+    }
+  }
   return l;
 }
 
@@ -387,12 +423,37 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
 int tlb_step(tlb_handle* h, int64_t nsteps) {
   if (!h) return fail(nullptr, TLB_EINVAL, "tlb_step: NULL handle");
   if (nsteps < 0) return fail(h, TLB_EINVAL, "tlb_step: nsteps < 0");
-  for (int64_t s = 0; s < nsteps; ++s) {
+  // Fused two-step launches first; the call always ends with a single step,
+  // so the other buffer holds f*(t-1), from which observables and fields of
+  // time t are pulled.
+  int64_t s = 0;
+  if (h->launch.rows2 > 0) {
+    for (; s + 2 < nsteps; s += 2) {
+      launch_pass(h, tlbh::Pass::kStep2, h->buf[h->cur], h->buf[1 - h->cur]);
+      h->cur = 1 - h->cur;
+      h->t += 2;
+    }
+  }
+  for (; s < nsteps; ++s) {
     launch_pass(h, tlbh::Pass::kStep, h->buf[h->cur], h->buf[1 - h->cur]);
     h->cur = 1 - h->cur;
     h->t += 1;
   }
   TLB_HIP(h, hipGetLastError());
+  return TLB_OK;
+}
+
+int tlb_launch_info(const tlb_handle* h, tlb_launch* out) {
+  if (!h || !out) return TLB_EINVAL;
+  const tlbh::Geometry& g = h->launch;
+  out->bx = g.bx;
+  out->rows = g.rows;
+  out->grid_x = (int32_t)g.grid.x;
+  out->grid_y = (int32_t)g.grid.y;
+  out->fused_rows = g.rows2;
+  out->fused_strip = g.strip2;
+  out->fused_grid_x = g.rows2 > 0 ? (int32_t)g.grid2.x : 0;
+  out->fused_grid_y = g.rows2 > 0 ? (int32_t)g.grid2.y : 0;
   return TLB_OK;
 }
 

@@ -34,7 +34,8 @@ def test_struct_layouts_match_header(tmp_path):
     """Offsets of every field as the C compiler lays out the header's structs
     equal those of the ctypes mirrors."""
     lines = []
-    for cname, cls in (("tlb_params", tlb.Params), ("tlb_obs", tlb.Obs), ("tlb_droplet", tlb.Droplet)):
+    for cname, cls in (("tlb_params", tlb.Params), ("tlb_obs", tlb.Obs), ("tlb_droplet", tlb.Droplet),
+                        ("tlb_launch", tlb.Launch)):
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
         for fname, _ in cls._fields_:
             lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
@@ -49,7 +50,8 @@ def test_struct_layouts_match_header(tmp_path):
         if line:
             cname, fname, val = line.split()
             want[(cname, fname)] = int(val)
-    for cname, cls in (("tlb_params", tlb.Params), ("tlb_obs", tlb.Obs), ("tlb_droplet", tlb.Droplet)):
+    for cname, cls in (("tlb_params", tlb.Params), ("tlb_obs", tlb.Obs), ("tlb_droplet", tlb.Droplet),
+                        ("tlb_launch", tlb.Launch)):
         assert want[(cname, "sizeof")] == ctypes.sizeof(cls)
         for fname, _ in cls._fields_:
             assert want[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
@@ -121,6 +123,7 @@ def test_null_handle_calls():
     assert lib.tlb_droplets(None, 0.8, None, 0, None, None) == tlb.TLB_EINVAL
     assert lib.tlb_forward_taped(None, 1, 1, None) == tlb.TLB_EINVAL
     assert lib.tlb_adjoint_step(None, 1, 1.0, None) == tlb.TLB_EINVAL
+    assert lib.tlb_launch_info(None, None) == tlb.TLB_EINVAL
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

@@ -1,0 +1,166 @@
+"""The fused two-step kernel (tau = tau_g = 1, FP32 / FP64, walls at rest)
+against runs made of single steps and against the oracle.
+
+The fused kernel keeps the intermediate time level as nine moments per node
+and rebuilds its populations with the same expressions the single step
+stores them with; the compiler contracts multiply-adds into fused ones
+differently in the two kernels, so the results agree to rounding, not bit
+for bit: after 18 steps the bar against single steps is 1e-13 relative in
+FP64; in FP32 it is 2e-6 for populations, densities and temperature (a few
+units in the last place) and 2e-5 of max|u| for velocities, which are small
+differences of populations. Against the oracle the bars are those of the single-step parity
+tests: FP64 <= 1e-12 relative, FP32 <= 1e-5 for densities, temperature and
+populations (3e-5 of max|u| for velocities).
+
+TLB_STEP2=1 forces the fused kernel wherever it applies (it is otherwise
+chosen only for lattices where it pays), TLB_STEP2=0 disables it, and
+TLB_STEP2_ROWS sets its chunk height, so short chunks exercise chunk edges
+in both marching directions.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle.oracle import ModelParams, Oracle
+from paper_2109_12565_amd import Simulation
+
+from test_gpu_parity import FIELDS, field_errors, pop_errors, posts_case
+
+pytestmark = pytest.mark.gpu
+
+
+def make(case, precision, monkeypatch, fused, rows=None, **extra):
+    monkeypatch.setenv("TLB_STEP2", "1" if fused else "0")
+    if rows is None:
+        monkeypatch.delenv("TLB_STEP2_ROWS", raising=False)
+    else:
+        monkeypatch.setenv("TLB_STEP2_ROWS", str(rows))
+    p = dict(case["params"], **extra)
+    sim = Simulation(p, case["rho_a"], case["rho_b"], case["temp"], solid=case.get("solid"),
+                     t_bottom=case.get("t_bottom"), precision=precision)
+    info = sim.launch_info()
+    print("launch", info)
+    return sim, info
+
+
+def droplet_case(lx, ly, seed=11):
+    """Random droplets (rho_A-rich discs of radius 6) at any lattice size."""
+    rng = np.random.default_rng(seed)
+    n = max(1, lx * ly // 600)
+    centres = [(rng.uniform(0, lx), rng.uniform(6, max(7, ly - 6))) for _ in range(n)]
+    inside = workloads.paint_discs(lx, ly, centres, 6.0)
+    return dict(params=dict(workloads.BASE_PARAMS, alpha_g=1e-3),
+                rho_a=np.where(inside, 1.36, 0.08) + rng.uniform(-0.01, 0.01, (ly, lx)),
+                rho_b=np.where(inside, 0.08, 1.36) + rng.uniform(-0.01, 0.01, (ly, lx)),
+                temp=workloads.conduction_profile(lx, ly) + rng.uniform(-1e-3, 1e-3, (ly, lx)),
+                t_bottom=workloads.bottom_temperature_noise(lx, seed=seed))
+
+
+def assert_close_state(a, b, tol, tol_u):
+    perr = pop_errors(a.populations(), b.populations())
+    ferr = field_errors(a.fields(), b.fields())
+    print("fused vs single", perr, ferr)
+    assert max(perr.values()) <= tol, perr
+    assert max(ferr[k] for k in FIELDS) <= tol, ferr
+    assert max(ferr["ux"], ferr["uy"]) <= tol_u, ferr
+    oa, ob = a.observables(), b.observables()
+    for k in ("mass_a", "mass_b", "sum_t", "nu", "nu_top", "ke"):
+        assert oa[k] == pytest.approx(ob[k], rel=tol, abs=1e-14), (k, oa[k], ob[k])
+
+
+CASES = {
+    "small": workloads.small,
+    "posts": posts_case,
+    "ragged_two_strips": lambda: droplet_case(300, 70),
+    "narrow": lambda: droplet_case(37, 20),
+    "three_strips_short": lambda: droplet_case(700, 16),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("rows", [None, 1, 7])
+def test_fused_matches_single_steps(monkeypatch, precision, name, rows):
+    case = CASES[name]()
+    fused, info = make(case, precision, monkeypatch, True, rows)
+    assert info["fused_rows"] > 0
+    single, info0 = make(case, precision, monkeypatch, False)
+    assert info0["fused_rows"] == 0
+    for n in (9, 1, 2, 6):   # odd and even calls; every call ends with a single step
+        fused.step(n)
+        single.step(n)
+    assert fused.t == single.t == 18
+    if precision == "fp64":
+        assert_close_state(fused, single, 1e-13, 1e-13)
+    else:
+        assert_close_state(fused, single, 2e-6, 2e-5)
+
+
+def test_fused_kernel_is_not_used_where_it_does_not_apply(monkeypatch):
+    w = workloads.small()
+    for precision in ("fp16dev", "bf16dev", "fix16dev"):
+        _, info = make(w, precision, monkeypatch, True)
+        assert info["fused_rows"] == 0, precision
+    _, info = make(w, "fp32", monkeypatch, True, tau=0.8)
+    assert info["fused_rows"] == 0
+    _, info = make(w, "fp32", monkeypatch, True, u_wall=(0.0, 0.01))
+    assert info["fused_rows"] == 0
+
+
+def test_fp64_fused_matches_oracle(monkeypatch):
+    case = posts_case()
+    sim, info = make(case, "fp64", monkeypatch, True, rows=5)
+    assert info["fused_rows"] > 0
+    ora = Oracle(ModelParams(**case["params"]), case["rho_a"], case["rho_b"], case["temp"],
+                 solid=case["solid"], t_bottom=case["t_bottom"])
+    sim.step(151)
+    ora.step(151)
+    errs = field_errors(sim.fields(), ora.fields())
+    assert max(errs.values()) <= 1e-12, errs
+    perr = pop_errors(sim.populations(), ora.post_collision())
+    assert max(perr.values()) <= 1e-12, perr
+
+
+def test_fp32_fused_1000_steps_matches_oracle(monkeypatch):
+    case = workloads.small()
+    sim, info = make(case, "fp32", monkeypatch, True)
+    assert info["fused_rows"] > 0
+    ora = Oracle(ModelParams(**case["params"]), case["rho_a"], case["rho_b"], case["temp"],
+                 solid=case.get("solid"), t_bottom=case.get("t_bottom"))
+    sim.step(1000)
+    ora.step(1000)
+    errs = field_errors(sim.fields(), ora.fields())
+    print("fp32 fused 1000 steps", errs)
+    assert max(errs[k] for k in FIELDS) <= 1e-5, errs
+    assert max(errs["ux"], errs["uy"]) <= 3e-5, errs
+
+
+def test_full_size_fused_steps_from_gpu_state(monkeypatch):
+    """4096 x 2048 with posts in the benchmark's own launch configuration
+    (fused kernel chosen by default): from the GPU's state after 20 steps,
+    the GPU advances 3 steps (one fused launch and a single step) and the
+    oracle 3 steps from the same state; every field and population is
+    compared."""
+    monkeypatch.delenv("TLB_STEP2", raising=False)
+    monkeypatch.delenv("TLB_STEP2_ROWS", raising=False)
+    w = workloads.large()
+    p = w["params"]
+    sim = Simulation(p, w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+                     t_bottom=w["t_bottom"], precision="fp32")
+    info = sim.launch_info()
+    print("launch", info)
+    assert info["fused_rows"] > 0
+    sim.step(20)
+    state = sim.populations()
+    sim.step(3)
+    ora = Oracle(ModelParams(**p), w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+                 t_bottom=w["t_bottom"])
+    ora.load_post_collision(state, 21)   # streams f*(20): the state of time 21
+    del state
+    ora.step(2)
+    errs = field_errors(sim.fields(), ora.fields())
+    print("large fused fields", errs)
+    assert max(errs.values()) <= 1e-5, errs
+    perr = pop_errors(sim.populations(), ora.post_collision())
+    print("large fused populations", perr)
+    assert max(perr.values()) <= 1e-5, perr
