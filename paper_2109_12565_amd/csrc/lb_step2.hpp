@@ -10,17 +10,22 @@
 //   level 1  the ordinary step on the populations of time t read from HBM
 //            (pull with half-way bounce-back and anti-bounce-back, Sec. 2.2;
 //            moments; psi in an LDS ring; forces, Eqs. (7)-(11), (22);
-//            velocities), ending in the nine moments of each node, which go
-//            to an LDS ring instead of HBM;
+//            velocities), ending in the moments of each node, which go to
+//            an LDS ring instead of HBM: per field (f_A, f_B, g) its density
+//            rho (or T), velocity u and u^2, one 16-byte vector each;
 //   level 2  pulls each population of time t+1 from the moments of its
-//            source node (the rest population as the remainder of the zeroth
-//            moment, as the single step stores it), then completes the step
-//            and stores f*(t+2) with 27 aligned stores.
+//            source node with the expressions the single step stores it
+//            with (even part S and odd part D of the pair of directions),
+//            the rest population as the remainder of the zeroth moment,
+//            then completes the step and stores f*(t+2) with 27 aligned
+//            stores.
 //
-// The level-2 pull evaluates the expressions with which the single-step
-// kernel forms and stores its equilibria, so two fused steps give the
-// numbers of two single steps up to the rounding of multiply-adds, which the
-// compiler may contract differently in the two kernels.
+// Two fused steps therefore give the numbers of two single steps up to the
+// contraction of multiply-adds, which the compiler may choose differently in
+// the two kernels. (A cheaper closed form of the equilibria rounds
+// differently in FP32, and that difference, though unbiased per population,
+// is amplified by the interface dynamics: 4e-5 against the FP64 result after
+// 1000 steps instead of 2e-6.)
 //
 // Halo. Level-2 collisions of a lane need level-2 densities of the lanes
 // within 2, which need level-1 moments within 3, which need level-1
@@ -33,8 +38,8 @@
 // barriers (up-marching chunk; a down-marching chunk mirrors the offsets):
 //   phase 1  issue the HBM pulls of row ra (f) and of row rb = ra - 2 (g);
 //            level-2 pull of row rc = ra - 4 from the moment ring into the
-//            level-2 density ring; level-1 densities of row ra into the
-//            level-1 density ring;
+//            level-2 density ring (hiding the load latency); level-1
+//            densities of row ra into the level-1 density ring;
 //   phase 2  level-1 forces and moments of row rb into the moment ring;
 //            level-2 forces, collision and stores of row rd = ra - 6.
 // The density rings hold 5 rows and the moment ring 3 (rows by absolute
@@ -127,8 +132,29 @@ __device__ inline void step2_forces(const StepArgs<C>& a, const C (&s_rho)[2][R]
   FB[1] += rb * a.alpha_g * temp;
 }
 
-// Moments of a level-1 node kept in the moment ring.
-enum : int { kMa = 0, kMuax, kMuay, kMb, kMubx, kMuby, kMt, kMhx, kMhy, kMoments };
+// Moments of a level-1 node for one field: the density (or temperature)
+// rho, the velocity u and u2 = |u|^2; the moment ring holds three per node
+// (f_A, f_B, g), read as 16-byte vectors.
+template <typename C>
+struct alignas(4 * sizeof(C)) Mom4 {
+  C rho, ux, uy, u2;
+};
+
+// Sum of the eight moving equilibria of a node in the single step's order
+// and form: ((S + D) + (S - D)) over the pairs 1, 2, 5, 6.
+template <typename C>
+__device__ inline C moving_sum(const Mom4<C>& m) {
+  C sum = 0;
+#define TLB_SUM_PAIR(P)                                 \
+  {                                                     \
+    C S, D;                                             \
+    eq_even_odd<P>(m.rho, m.ux, m.uy, m.u2, S, D);      \
+    sum += (S + D) + (S - D);                           \
+  }
+  TLB_SUM_PAIR(1) TLB_SUM_PAIR(2) TLB_SUM_PAIR(5) TLB_SUM_PAIR(6)
+#undef TLB_SUM_PAIR
+  return sum;
+}
 
 // Level-2 pull of direction I (1..8) at a node from the moment ring: the
 // value f*_I(x - c_I) of the source node, or, across a solid link, the
@@ -136,23 +162,19 @@ enum : int { kMa = 0, kMuax, kMuay, kMb, kMubx, kMuby, kMt, kMhx, kMhy, kMoments
 // bounce-back). Both alternatives belong to the pair of I, so a lane
 // selects its ring cell and the sign of the odd part.
 template <int I, unsigned kMode, typename C, int RM, int WM>
-__device__ inline void pull_level2(const StepArgs<C>& a, const C (&sm)[kMoments][RM][WM],
+__device__ inline void pull_level2(const StepArgs<C>& a, const Mom4<C> (&sm)[RM][WM][3],
                                    int slot_own, int col_own, int x, int r, uint32_t lm,
                                    C (&fa)[9], C (&fb)[9], C (&g)[9]) {
   constexpr int P = (I == 1 || I == 2 || I == 5 || I == 6) ? I : Dir<I>::opp;
   const bool bb = ((lm >> I) & 1u) != 0u;
   const int s = bb ? slot_own : ring_slot<RM>(r - Dir<I>::cy);
   const int c = bb ? col_own : col_own - Dir<I>::cx;
-  const C da = sm[kMa][s][c], uax = sm[kMuax][s][c], uay = sm[kMuay][s][c];
-  const C db = sm[kMb][s][c], ubx = sm[kMubx][s][c], uby = sm[kMuby][s][c];
-  const C dt = sm[kMt][s][c], hx = sm[kMhx][s][c], hy = sm[kMhy][s][c];
-  const C ua2 = uax * uax + uay * uay;
-  const C ub2 = ubx * ubx + uby * uby;
-  const C uh2 = hx * hx + hy * hy;
+  const Mom4<C>* src = sm[s][c];
+  const Mom4<C> ma = src[0], mb = src[1], mg = src[2];
   C Sa, Da, Sb, Db, Sg, Dg;
-  eq_even_odd<P>(da, uax, uay, ua2, Sa, Da);
-  eq_even_odd<P>(db, ubx, uby, ub2, Sb, Db);
-  eq_even_odd<P>(dt, hx, hy, uh2, Sg, Dg);
+  eq_even_odd<P>(ma.rho, ma.ux, ma.uy, ma.u2, Sa, Da);
+  eq_even_odd<P>(mb.rho, mb.ux, mb.uy, mb.u2, Sb, Db);
+  eq_even_odd<P>(mg.rho, mg.ux, mg.uy, mg.u2, Sg, Dg);
   const bool plus = (P == I) != bb;
   fa[I] = plus ? Sa + Da : Sa - Da;
   fb[I] = plus ? Sb + Db : Sb - Db;
@@ -180,7 +202,7 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   __shared__ C s1_psi[2][R1][W];
   __shared__ C s2_rho[2][R1][W];
   __shared__ C s2_psi[2][R1][W];
-  __shared__ C sm[kMoments][RM][WM];
+  __shared__ Mom4<C> sm[RM][WM][3];
 
   const int lx = a.lx, ly = a.ly;
   const int tid = threadIdx.x;
@@ -216,25 +238,28 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   const C psi_w1 = psi_of<St>(a.rho_wall1, a.rho0, a.inv_rho0);
   constexpr bool kSolid = (kMode & kModeSolid) != 0;
 
-  // Level 1, phase 1: pull row ra from HBM, densities and psi into ring 1,
-  // keep rho_A, rho_B, j (tau = 1: the moments are all the collision needs).
-  auto level1_density = [&](int r, C (&kw)[4], uint32_t& lw) {
-    C ra = a.rho_wall0, rb = a.rho_wall1, pa = psi_w0, pb = psi_w1;
+  // Level 1, phase 1: pull row ra from HBM (issued first in the phase, so
+  // the level-2 work of the phase hides the load latency), then densities
+  // and psi into ring 1 and the kept rho_A, rho_B, j (tau = 1: the moments
+  // are all the collision needs).
+  auto level1_pull = [&](int r, C (&f)[18], uint32_t& lw) {
     lw = kSelfSolid;
     if (r >= 0 && r < ly) {
       lw = link_mask<kMode>(a, xw, r);
-      if (!(kSolid && (lw & kSelfSolid))) {
-        C f[18];
-        pull_fluid<St, kMode>(a, msrc, Lo, r, lw, f);
-        kw[0] = sum9(f);
-        kw[1] = sum9(f + 9);
-        kw[2] = momentum_x(f, f + 9);
-        kw[3] = momentum_y(f, f + 9);
-        ra = kw[0];
-        rb = kw[1];
-        pa = psi_of<St>(ra, a.rho0, a.inv_rho0);
-        pb = psi_of<St>(rb, a.rho0, a.inv_rho0);
-      }
+      if (!(kSolid && (lw & kSelfSolid))) pull_fluid<St, kMode>(a, msrc, Lo, r, lw, f);
+    }
+  };
+  auto level1_density = [&](int r, const C (&f)[18], uint32_t lw, C (&kw)[4]) {
+    C ra = a.rho_wall0, rb = a.rho_wall1, pa = psi_w0, pb = psi_w1;
+    if (r >= 0 && r < ly && !(kSolid && (lw & kSelfSolid))) {
+      kw[0] = sum9(f);
+      kw[1] = sum9(f + 9);
+      kw[2] = momentum_x(f, f + 9);
+      kw[3] = momentum_y(f, f + 9);
+      ra = kw[0];
+      rb = kw[1];
+      pa = psi_of<St>(ra, a.rho0, a.inv_rho0);
+      pb = psi_of<St>(rb, a.rho0, a.inv_rho0);
     }
     const int s = ring_slot<R1>(r);
     s1_rho[0][s][c1] = ra;
@@ -264,16 +289,13 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
     const C tA = a.tau * recip<St>(ra), tB = a.tau * recip<St>(rb);
     const C uax = ux + FA[0] * tA, uay = uy + FA[1] * tA;
     const C ubx = ux + FB[0] * tB, uby = uy + FB[1] * tB;
-    const int s = ring_slot<RM>(r);
-    sm[kMa][s][cm] = Da;
-    sm[kMuax][s][cm] = uax;
-    sm[kMuay][s][cm] = uay;
-    sm[kMb][s][cm] = Db;
-    sm[kMubx][s][cm] = ubx;
-    sm[kMuby][s][cm] = uby;
-    sm[kMt][s][cm] = Dt;
-    sm[kMhx][s][cm] = hx;
-    sm[kMhy][s][cm] = hy;
+    const C ua2 = uax * uax + uay * uay;
+    const C ub2 = ubx * ubx + uby * uby;
+    const C uh2 = hx * hx + hy * hy;
+    Mom4<C>* m = sm[ring_slot<RM>(r)][cm];
+    m[0] = Mom4<C>{Da, uax, uay, ua2};
+    m[1] = Mom4<C>{Db, ubx, uby, ub2};
+    m[2] = Mom4<C>{Dt, hx, hy, uh2};
   };
 
   // Level 2, phase 1: pull row r from the moment ring; densities and psi
@@ -287,29 +309,12 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
         const int so = ring_slot<RM>(r);
         C fa[9], fb[9], g[9];
         {
-          // rest populations: the zeroth moments minus the moving equilibria
-          const C da = sm[kMa][so][cm], uax = sm[kMuax][so][cm], uay = sm[kMuay][so][cm];
-          const C db = sm[kMb][so][cm], ubx = sm[kMubx][so][cm], uby = sm[kMuby][so][cm];
-          const C dt = sm[kMt][so][cm], hx = sm[kMhx][so][cm], hy = sm[kMhy][so][cm];
-          const C ua2 = uax * uax + uay * uay;
-          const C ub2 = ubx * ubx + uby * uby;
-          const C uh2 = hx * hx + hy * hy;
-          C sa = 0, sb = 0, sg = 0;
-#define TLB_REST(P)                                \
-  {                                                \
-    C Sa, Dla, Sb, Dlb, Sg, Dlg;                   \
-    eq_even_odd<P>(da, uax, uay, ua2, Sa, Dla);    \
-    eq_even_odd<P>(db, ubx, uby, ub2, Sb, Dlb);    \
-    eq_even_odd<P>(dt, hx, hy, uh2, Sg, Dlg);      \
-    sa += (Sa + Dla) + (Sa - Dla);                 \
-    sb += (Sb + Dlb) + (Sb - Dlb);                 \
-    sg += (Sg + Dlg) + (Sg - Dlg);                 \
-  }
-          TLB_REST(1) TLB_REST(2) TLB_REST(5) TLB_REST(6)
-#undef TLB_REST
-          fa[0] = da - sa;
-          fb[0] = db - sb;
-          g[0] = dt - sg;
+          // rest populations: the zeroth moments minus the moving
+          // equilibria, as the single step stores them
+          const Mom4<C>* m = sm[so][cm];
+          fa[0] = m[0].rho - moving_sum(m[0]);
+          fb[0] = m[1].rho - moving_sum(m[1]);
+          g[0] = m[2].rho - moving_sum(m[2]);
         }
         pull_level2<1, kMode>(a, sm, so, cm, xw, r, lw, fa, fb, g);
         pull_level2<2, kMode>(a, sm, so, cm, xw, r, lw, fa, fb, g);
@@ -406,11 +411,12 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
     const bool do_b = in_rows(rb, y0 - 3, y1 + 3) && !(kSolid && (l1u & kSelfSolid));
     const bool do_c = rc >= y0 - 2 && rc < y1 + 2;
     const bool do_d = out_lane && rd >= y0 && rd < y1;
-    // phase 1
-    C g[9];
+    // phase 1: HBM loads first, then the LDS work of level 2
+    C f[18], g[9];
+    if (do_a) level1_pull(ra, f, l1w);
     if (do_b) pull_thermal<St, kMode>(a, msrc, Lo, xw, rb, l1u, g);
     if (do_c) level2_density(rc, k2w, l2w);
-    if (do_a) level1_density(ra, k1w, l1w);
+    if (do_a) level1_density(ra, f, l1w, k1w);
     __syncthreads();
     // phase 2
     if (do_b) level1_moments(rb, k1u, g);

@@ -155,7 +155,11 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
     with_storage(p.precision, [&](auto st) {
       per_cu2 = tlbh::Launcher<decltype(st)>::step2_blocks_per_cu(solid);
     });
-    const int max_strip = tlbh::kStep2Lanes - tlbh::kStep2Halo;
+    int max_strip = tlbh::kStep2Lanes - tlbh::kStep2Halo;
+    if (const char* env = std::getenv("TLB_STEP2_STRIP")) {
+      int v = std::atoi(env);
+      if (v >= 1 && v < max_strip) max_strip = v;
+    }
     const long long strips2 = (lx + max_strip - 1) / max_strip;
     const int strip2 = (int)((lx + strips2 - 1) / strips2);
     // at most one block per resident slot: a second, partial wave of blocks
