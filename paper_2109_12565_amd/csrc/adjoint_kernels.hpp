@@ -45,9 +45,13 @@ struct AdjArgs {
   int step_index;
 };
 
+// Element index of plane p at node (x, y) in a population-layout array. The
+// adjoint runs only on population buffers below 4 GiB (27 planes), so every
+// index of its arrays fits in 32 bits, which keeps the neighbour addressing
+// of the stencil transposes cheap.
 template <typename C>
-__device__ inline long long plane_index(const StepArgs<C>& a, int p, int x, int y) {
-  return (long long)p * a.pop_stride + (long long)y * a.pitch + x;
+__device__ inline uint32_t plane_index(const StepArgs<C>& a, int p, int x, int y) {
+  return (uint32_t)p * (uint32_t)a.pop_stride + (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
 }
 
 template <typename C>
@@ -77,9 +81,9 @@ __device__ inline void fbar_node(const AdjArgs<C>& a, int l, int x, int y, C& fx
     fx = fy = C(0);
     return;
   }
-  const long long q = plane_index(a.s, 0, wrapx(a.s, x), y);
-  fx = a.Fbar[q + (long long)(2 * l) * a.s.pop_stride];
-  fy = a.Fbar[q + (long long)(2 * l + 1) * a.s.pop_stride];
+  const uint32_t q = plane_index(a.s, 2 * l, wrapx(a.s, x), y);
+  fx = a.Fbar[q];
+  fy = a.Fbar[q + (uint32_t)a.s.pop_stride];
 }
 
 // Pulled populations of node (x, y) from the state (flat walls).
@@ -268,7 +272,9 @@ __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
   const C gcross = s.g12 * s.inv_rho0 * s.inv_rho0;
   const C ga[2] = {s.ga0, s.ga1}, gr[2] = {s.gr0, s.gr1};
   C psibar[2] = {0, 0}, rb[2] = {0, 0};
-  for (int dy = -2; dy <= 2; ++dy)
+  for (int dy = -2; dy <= 2; ++dy) {
+    // rows beyond the walls carry no force (F-bar is zero there)
+    if (y - dy < 0 || y - dy >= s.ly) continue;
     for (int dx = -2; dx <= 2; ++dx) {
       if (dx == 0 && dy == 0) continue;
       // neighbour x - c whose stencil reaches this node with offset c
@@ -283,6 +289,7 @@ __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
         if (c2 <= 2) rb[1 - l] -= gcross * rho_node(a, l, nx, ny) * ww * dot;
       }
     }
+  }
   for (int l = 0; l < 2; ++l) {
     const C dps = C(1) - psi_node(a, l, x, y) * s.inv_rho0;
     a.rbar[plane_index(s, l, x, y)] = rb[l] + psibar[l] * dps;

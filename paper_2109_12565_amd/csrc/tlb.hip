@@ -130,7 +130,11 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
   const int target = std::max(1, std::min(per_cu, target_waves / (l.bx / 64)));
   const long long strips = (lx + l.bx - 1) / l.bx;
   long long rows = (ly * strips + (long long)cus * target - 1) / ((long long)cus * target);
-  rows = rows < 11 ? 11 : (rows > 65 ? 65 : rows);
+  // Floor of 5 rows: each chunk pulls 4 extra rows, and lattices too small
+  // to give every CU its target waves (1024 x 512: 2 rows) trade occupancy
+  // against that overhead best there (measured 36.6 us per step at 5 rows,
+  // 39.0 at 2, 41.0 at 8, 48.0 at 11).
+  rows = rows < 5 ? 5 : (rows > 65 ? 65 : rows);
   while ((rows + 4) % 3) ++rows;
   if (const char* env = std::getenv("TLB_ROWS_PER_BLOCK")) {
     int v = std::atoi(env);
