@@ -266,7 +266,12 @@ def main() -> int:
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": kernel, "bytes_per_node": bpn, "nodes_per_launch": nodes,
             "updates_per_node": updates, "launch_us": round(per_launch_s * 1e6, 2),
-            "launches": {"fused": n_fused, "single": n_single}}
+            "launches": {"fused": n_fused, "single": n_single},
+            # what the counters show limits the kernel: the fused kernel does two
+            # steps' arithmetic per pass over HBM and is bound by vector
+            # instruction issue; the 4- and 8-byte single step by HBM
+            "limiter": "valu-issue" if n_fused > 0 or BYTES_PER_POP[args.precision] == 2
+                       else "hbm"}
     traffic = measured_traffic(w["name"], args.precision, kernel)
     if traffic is not None:
         roof["traffic"] = round(traffic / per_launch_s / 1e9, 1)
