@@ -259,13 +259,19 @@ def main() -> int:
     else:
         kernel, updates = "lb_step_kernel", 1
         per_launch_s = step_ms * 1e-3 / args.steps
-    # algorithmic bytes per launch: every population read once and written
-    # once per launch, whether the launch advances one step or two
-    achieved = bpn * nodes / per_launch_s / 1e9
+    # algorithmic bytes per launch: the method's bytes per lattice update
+    # (27 populations read and written once, plus the solid flag) times the
+    # updates one launch performs; the fused kernel moves its populations
+    # once for two updates, so the bytes it must move per launch are half of
+    # that (hbm_bytes_per_launch_min) and `traffic` is the counted HBM rate
+    achieved = bpn * nodes * updates / per_launch_s / 1e9
+    moved = bpn * nodes / per_launch_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": kernel, "bytes_per_node": bpn, "nodes_per_launch": nodes,
+            "kernel": kernel, "bytes_per_lattice_update": bpn, "nodes_per_launch": nodes,
             "updates_per_node": updates, "launch_us": round(per_launch_s * 1e6, 2),
+            "hbm_bytes_per_launch_min": bpn * nodes,
+            "frac_of_min_bytes": round(moved / HBM_PEAK_GBS, 4),
             "launches": {"fused": n_fused, "single": n_single},
             # what the counters show limits the kernel: the fused kernel does two
             # steps' arithmetic per pass over HBM and is bound by vector
