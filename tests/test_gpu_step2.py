@@ -164,3 +164,42 @@ def test_full_size_fused_steps_from_gpu_state(monkeypatch):
     perr = pop_errors(sim.populations(), ora.post_collision())
     print("large fused populations", perr)
     assert max(perr.values()) <= 1e-5, perr
+
+
+@pytest.mark.parametrize("lx,ly", [(5, 3), (64, 1), (7, 2), (250, 9)])
+def test_fused_edge_shapes_fp64(monkeypatch, lx, ly):
+    """Lattices narrower than the kernel's halo (columns wrap several times
+    across one block), a single row (both walls on it), and a strip just
+    above one block's stored width. Velocities get 1e-11 of max|u|: on these
+    lattices max|u| is small (about 1e-4 on the single row), while u carries
+    the absolute rounding of its populations."""
+    case = droplet_case(lx, ly, seed=lx + ly)
+    fused, info = make(case, "fp64", monkeypatch, True)
+    assert info["fused_rows"] > 0
+    single, _ = make(case, "fp64", monkeypatch, False)
+    for n in (7, 4):
+        fused.step(n)
+        single.step(n)
+    assert_close_state(fused, single, 1e-13, 1e-11)
+
+
+def test_fused_launch_geometry(monkeypatch):
+    """At 4096 x 2048 the fused grid fits one block per resident slot, its
+    strips cover the lattice with at most 246 stored columns each, and its
+    chunks are at least 24 rows tall; TLB_STEP2_ROWS and TLB_STEP2_STRIP
+    override the choice."""
+    w = workloads.large()
+    lx, ly = w["lx"], w["ly"]
+    sim, info = make(w, "fp32", monkeypatch, True)
+    sim.close()
+    assert 24 <= info["fused_rows"] <= ly and info["fused_strip"] <= 246
+    assert info["fused_grid_x"] * info["fused_strip"] >= lx
+    assert (info["fused_grid_x"] - 1) * info["fused_strip"] < lx
+    assert info["fused_grid_y"] * info["fused_rows"] >= ly
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert info["fused_grid_x"] * info["fused_grid_y"] <= 2 * cus
+    monkeypatch.setenv("TLB_STEP2_STRIP", "200")
+    sim, info2 = make(w, "fp32", monkeypatch, True, rows=40)
+    sim.close()
+    assert info2["fused_rows"] == 40 and info2["fused_strip"] <= 200
