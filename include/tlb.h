@@ -143,7 +143,13 @@ int tlb_init(tlb_handle **out, const tlb_params *p, const double *rho_a,
 
 /* Advance nsteps >= 0 time steps of Eqs. (1) and (16): per node, pull
  * streaming with bounce-back / anti-bounce-back at solid links, moments,
- * forces, velocity shift (Eq. (6)) and BGK collision. Enqueues only. */
+ * forces, velocity shift (Eq. (6)) and BGK collision. Enqueues only. With
+ * tau = tau_g = 1 (the collision then returns the equilibria of Eqs. (3),
+ * (18)), FP32 or FP64 storage and walls at rest, pairs of steps may run as
+ * one fused launch (see tlb_launch_info); the last step of a call is always
+ * a single step, and results agree with single steps to rounding. Returns
+ * TLB_EINVAL for nsteps < 0 or a NULL handle, TLB_EDEVICE on a launch
+ * failure. */
 int tlb_step(tlb_handle *h, int64_t nsteps);
 
 /* Observables at the current time (synchronises the stream). Returns

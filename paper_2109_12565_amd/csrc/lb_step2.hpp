@@ -22,10 +22,8 @@
 //
 // Two fused steps therefore give the numbers of two single steps up to the
 // contraction of multiply-adds, which the compiler may choose differently in
-// the two kernels. (A cheaper closed form of the equilibria rounds
-// differently in FP32, and that difference, though unbiased per population,
-// is amplified by the interface dynamics: 4e-5 against the FP64 result after
-// 1000 steps instead of 2e-6.)
+// the two kernels. The pulled values and the ones subtracted for the rest
+// population must round alike, though (see pull_level2).
 //
 // Halo. Level-2 collisions of a lane need level-2 densities of the lanes
 // within 2, which need level-1 moments within 3, which need level-1
@@ -276,8 +274,8 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
     s1_psi[1][s][c1] = pb;
   };
 
-  // Level 1, phase 2: forces and velocities of fluid row r; its nine
-  // moments into the moment ring.
+  // Level 1, phase 2: forces and velocities of fluid row r; per field its
+  // density (or temperature), velocity and u^2 into the moment ring.
   auto level1_moments = [&](int r, const C (&ku)[4], const C (&g)[9]) {
     const C Da = ku[0], Db = ku[1], jx = ku[2], jy = ku[3];
     const C ra = Da, rb = Db;
