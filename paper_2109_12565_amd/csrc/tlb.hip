@@ -148,7 +148,7 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
   // chunks recompute 5 rows of the first step on each side, so it pays
   // where the chunks can be tall and the grid still fills every CU once:
   // chunks of at least 24 rows, one block per resident slot. TLB_STEP2=1
-  // selects it wherever it applies, TLB_STEP2=0 never.
+  // selects it wherever it applies (FP64 included), TLB_STEP2=0 never.
   const bool moving = p.u_wall[0] != 0.0 || p.u_wall[1] != 0.0;
   const bool eligible = tau_one && !moving && !l.wide &&
                         (p.precision == TLB_FP32 || p.precision == TLB_FP64);
@@ -171,7 +171,10 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
     const long long slots = (long long)cus * std::max(per_cu2, 1);
     const long long max_chunks = std::max(1LL, slots / strips2);
     long long rows2 = (ly + max_chunks - 1) / max_chunks;
-    const bool pays = rows2 >= 24;
+    // it pays with tall chunks and at least two resident blocks per CU: FP64
+    // (139 KB of LDS, one block per CU) measured 1577 us per fused launch
+    // against 2 x 766 us of single steps at 4096 x 2048
+    const bool pays = rows2 >= 24 && per_cu2 >= 2;
     if (per_cu2 > 0 && (pays || step2_mode == 1)) {
       if (const char* env = std::getenv("TLB_STEP2_ROWS")) {
         int v = std::atoi(env);
