@@ -100,6 +100,19 @@ __device__ inline void adj_pull_node(const AdjArgs<typename St::C>& a, int x, in
   pull_thermal<St, 0u>(a.s, m, L, x, y, lm, g);
 }
 
+// Pulled temperature populations of node (x, y) only (flat walls).
+template <class St>
+__device__ inline void adj_pull_thermal_node(const AdjArgs<typename St::C>& a, int x, int y,
+                                             typename St::C (&g)[9]) {
+  using O = Off<0>;
+  const O row_b = (O)a.s.pitch * sizeof(typename St::T);
+  const O plane_b = (O)a.s.pop_stride * sizeof(typename St::T);
+  const uint32_t lm = link_mask<0u>(a.s, x, y);
+  const PopMem<St, 0u> m(a.state, (uint64_t)plane_b * 27);
+  const LaneOff<0u> L = lane_off<St, 0u>(x, a.s.lx, plane_b, row_b);
+  pull_thermal<St, 0u>(a.s, m, L, x, y, lm, g);
+}
+
 template <class St>
 __global__ __launch_bounds__(256) void adj_density(AdjArgs<typename St::C> a) {
   using C = typename St::C;
@@ -123,8 +136,8 @@ __global__ __launch_bounds__(256) void adj_top_row_sum(AdjArgs<typename St::C> a
   double acc = 0;
   const int y = a.s.ly - 1;
   for (int x = threadIdx.x; x < a.s.lx; x += 256) {
-    C f[18], g[9];
-    adj_pull_node<St>(a, x, y, f, g);
+    C g[9];
+    adj_pull_thermal_node<St>(a, x, y, g);
     acc += (double)sum9(g) - (double)a.s.t_top;
   }
   part[threadIdx.x] = acc;
