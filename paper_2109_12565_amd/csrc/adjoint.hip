@@ -45,7 +45,6 @@ void Adjoint<St>::reverse_step(const Device& d, const AdjointWork& w, const void
   hipLaunchKernelGGL((tlbk::adj_local<St>), grid, block, 0, d.stream, a);
   hipLaunchKernelGGL((tlbk::adj_scatter<St>), grid, block, 0, d.stream, a);
   hipLaunchKernelGGL((tlbk::adj_pull<St>), grid, block, 0, d.stream, a);
-  hipLaunchKernelGGL((tlbk::adj_grad_tb<St>), dim3((lx + 255) / 256), block, 0, d.stream, a);
 }
 
 template struct Adjoint<tlbk::Store<double>>;

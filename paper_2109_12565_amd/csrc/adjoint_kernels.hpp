@@ -17,9 +17,9 @@
 //   adj_scatter  per node: the transpose of the force stencils (the node's
 //                density enters its neighbours' forces) -> dL/drho_l;
 //   adj_pull     per node: the transpose of the pull (each post-collision
-//                value is pulled exactly once) -> lambda(t);
-//   adj_grad_tb  per column: the anti-bounce-back source 2 w_i T_b of the
-//                bottom links -> dL/dT_b.
+//                value is pulled exactly once) -> lambda(t); its bottom-row
+//                blocks also take the anti-bounce-back source 2 w_i T_b of
+//                the bottom links -> dL/dT_b per column.
 // Densities and pseudopotentials of the step's pulled state are precomputed
 // by adj_density; the forward quantities of a node are recomputed from them
 // and from the node's pulled populations.
@@ -309,6 +309,19 @@ __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
   }
 }
 
+// dL/dT_b(c) += sum of 2 w_i gbar_i(x, 0) over the bottom links whose solid
+// source lies in column c: i = 2 at x = c, i = 5 at x = c + 1, i = 6 at
+// x = c - 1 (gbar = dL/d of the pulled g, complete once adj_local is done).
+template <class St>
+__device__ inline void grad_tb_column(const AdjArgs<typename St::C>& a, int c) {
+  using C = typename St::C;
+  const StepArgs<C>& s = a.s;
+  const double v = 2.0 * ((double)w_dir<C>(2) * (double)a.fbar[plane_index(s, 18 + 2, c, 0)] +
+                          (double)w_dir<C>(5) * (double)a.fbar[plane_index(s, 18 + 5, wrapx(s, c + 1), 0)] +
+                          (double)w_dir<C>(6) * (double)a.fbar[plane_index(s, 18 + 6, wrapx(s, c - 1), 0)]);
+  a.grad[c] += v;
+}
+
 // Transpose of the pull: f*_i(y) was pulled by the node y + c_i, or, when
 // that node is a wall, by y itself as direction opp(i) (bounce-back; with a
 // minus sign for g, anti-bounce-back).
@@ -330,21 +343,10 @@ __global__ __launch_bounds__(256) void adj_pull(AdjArgs<typename St::C> a) {
     const C gv = a.fbar[plane_index(s, 18 + si, sx, sy)];
     a.lam[plane_index(s, 18 + i, x, y)] = wall ? -gv : gv;
   }
+  // the bottom row's blocks also accumulate dL/dT_b of their columns
+  if (y == 0) grad_tb_column<St>(a, x);
 }
 
-// dL/dT_b(c) += sum of 2 w_i gbar_i(x, 0) over the bottom links whose solid
-// source lies in column c: i = 2 at x = c, i = 5 at x = c + 1, i = 6 at
-// x = c - 1.
-template <class St>
-__global__ __launch_bounds__(256) void adj_grad_tb(AdjArgs<typename St::C> a) {
-  using C = typename St::C;
-  const StepArgs<C>& s = a.s;
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= s.lx) return;
-  const double v = 2.0 * ((double)w_dir<C>(2) * (double)a.fbar[plane_index(s, 18 + 2, c, 0)] +
-                          (double)w_dir<C>(5) * (double)a.fbar[plane_index(s, 18 + 5, wrapx(s, c + 1), 0)] +
-                          (double)w_dir<C>(6) * (double)a.fbar[plane_index(s, 18 + 6, wrapx(s, c - 1), 0)]);
-  a.grad[c] += v;
-}
+
 
 }  // namespace tlbk
