@@ -292,6 +292,10 @@ def main() -> int:
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total_ms / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        # the paper's own figure (Sec. 2.5), other hardware, lattice and
+        # precision not stated: context, not a baseline for this workload
+        "paper_context": {"mlups": 525, "hardware": "NVIDIA Titan V", "lattice": "not stated",
+                          "precision": "not stated"},
         "dtype": {"fp32": "f32", "fp64": "f64", "fp16dev": "f16-storage/f32",
                   "bf16dev": "bf16-storage/f32", "fix16dev": "i16-storage/f32"}[args.precision],
         "data": "synthetic",
