@@ -155,6 +155,40 @@ def precision_study(steps: int, every: int, storages) -> dict:
     return out
 
 
+def companion_runs(config: str, precision: str) -> dict:
+    """Throughput of the storages and lattice the headline metric compares
+    with, measured in the same process: FP16 deviations on the benchmark
+    lattice (FP32 if the main run used another storage) and FP32 on the
+    1024x512 lattice; HIP events around tlb_step(K) plus one observables
+    call, as in the main measurement."""
+    import torch
+
+    from paper_2109_12565_amd import Simulation
+
+    def run(name, prec, steps, warmup):
+        w = workloads.CONFIGS[name]()
+        with Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+                        t_bottom=w["t_bottom"], precision=prec) as sim:
+            sim.step(warmup)
+            sim.observables()
+            e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+            torch.cuda.synchronize()
+            e0.record()
+            sim.step(steps)
+            sim.observables()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            launch = sim.launch_info()
+        return {"workload": w["name"], "storage": prec, "steps": steps,
+                "mlups": round(w["lx"] * w["ly"] * steps / (ms * 1e-3) / 1e6, 1),
+                "ms_per_step": round(ms / steps, 4), "fused": launch["fused_rows"] > 0}
+
+    other = "fp16dev" if precision != "fp16dev" else "fp32"
+    return {"other_storage": run(config, other, 300, 20),
+            "fp32_1024x512": run("mid", "fp32", 2000, 50)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +206,9 @@ def main() -> int:
                          "(FP32, checkpoints every 25; 0 to skip)")
     ap.add_argument("--u-wall", type=float, nargs=2, default=(0.0, 0.0), metavar=("UB", "UT"),
                     help="x-velocity of the bottom and top walls (Couette walls)")
+    ap.add_argument("--companions", type=int, default=1,
+                    help="also time the other storage on the same lattice and FP32 on the "
+                         "1024x512 lattice (0 to skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before warmup, run 3 plain device copies of this many MiB (a known "
                          "traffic reference for hardware counters)")
@@ -312,6 +349,8 @@ def main() -> int:
                      "threshold": 0.8, "nu_mean": float(np.mean(drops["nu"])) if len(drops["nu"]) else None},
     }
     sim.close()
+    if args.companions:
+        out["companions"] = companion_runs(args.config, args.precision)
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint_ratio(args.adjoint_steps, 25, "fp32")
     if args.cpu_steps > 0:
