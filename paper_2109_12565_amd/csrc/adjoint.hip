@@ -36,12 +36,13 @@ void Adjoint<St>::top_row_term(const Device& d, const AdjointWork& w, const void
 
 template <class St>
 void Adjoint<St>::reverse_step(const Device& d, const AdjointWork& w, const void* state, int in,
-                               double kappa_top) {
+                               double kappa_top, const void* next_state, bool density_ready) {
   auto a = adjoint_args<St>(d, w, state, in);
   a.kappa_top = static_cast<typename St::C>(kappa_top);
+  a.next_state = next_state;
   const int lx = d.p->lx, ly = d.p->ly;
   const dim3 grid((lx + 255) / 256, ly), block(256);
-  hipLaunchKernelGGL((tlbk::adj_density<St>), grid, block, 0, d.stream, a);
+  if (!density_ready) hipLaunchKernelGGL((tlbk::adj_density<St>), grid, block, 0, d.stream, a);
   hipLaunchKernelGGL((tlbk::adj_local<St>), grid, block, 0, d.stream, a);
   hipLaunchKernelGGL((tlbk::adj_scatter<St>), grid, block, 0, d.stream, a);
   hipLaunchKernelGGL((tlbk::adj_pull<St>), grid, block, 0, d.stream, a);

@@ -19,7 +19,9 @@
 //   adj_pull     per node: the transpose of the pull (each post-collision
 //                value is pulled exactly once) -> lambda(t); its bottom-row
 //                blocks also take the anti-bounce-back source 2 w_i T_b of
-//                the bottom links -> dL/dT_b per column.
+//                the bottom links -> dL/dT_b per column; where the next
+//                reverse step's state is at hand it also does that step's
+//                adj_density.
 // Densities and pseudopotentials of the step's pulled state are precomputed
 // by adj_density; the forward quantities of a node are recomputed from them
 // and from the node's pulled populations.
@@ -41,6 +43,8 @@ struct AdjArgs {
   C* rbar;               // dL/drho from the stencil transpose (2 planes)
   double* grad;          // [lx] accumulated dL/dT_b
   double* loss_terms;    // per-step loss terms (forward)
+  const void* next_state;  // state of the next reverse step, or null: adj_pull
+                           // then also fills aux for it
   C kappa_top;           // dL/dT of each top-row node for this step
   int step_index;
 };
@@ -113,18 +117,31 @@ __device__ inline void adj_pull_thermal_node(const AdjArgs<typename St::C>& a, i
   pull_thermal<St, 0u>(a.s, m, L, x, y, lm, g);
 }
 
+// Densities and pseudopotentials of `state` pulled at node (x, y), into aux.
 template <class St>
-__global__ __launch_bounds__(256) void adj_density(AdjArgs<typename St::C> a) {
+__device__ inline void density_node(const AdjArgs<typename St::C>& a, const void* state, int x,
+                                    int y) {
   using C = typename St::C;
-  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-  if (x >= a.s.lx) return;
-  C f[18], g[9];
-  adj_pull_node<St>(a, x, y, f, g);
+  using O = Off<0>;
+  const O row_b = (O)a.s.pitch * sizeof(typename St::T);
+  const O plane_b = (O)a.s.pop_stride * sizeof(typename St::T);
+  const uint32_t lm = link_mask<0u>(a.s, x, y);
+  const PopMem<St, 0u> m(state, (uint64_t)plane_b * 27);
+  const LaneOff<0u> L = lane_off<St, 0u>(x, a.s.lx, plane_b, row_b);
+  C f[18];
+  pull_fluid<St, 0u>(a.s, m, L, y, lm, f);
   const C ra = sum9(f), rb = sum9(f + 9);
   a.aux[plane_index(a.s, 0, x, y)] = ra;
   a.aux[plane_index(a.s, 1, x, y)] = rb;
   a.aux[plane_index(a.s, 2, x, y)] = psi_exp(ra, a.s.rho0, a.s.inv_rho0);
   a.aux[plane_index(a.s, 3, x, y)] = psi_exp(rb, a.s.rho0, a.s.inv_rho0);
+}
+
+template <class St>
+__global__ __launch_bounds__(256) void adj_density(AdjArgs<typename St::C> a) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= a.s.lx) return;
+  density_node<St>(a, a.state, x, y);
 }
 
 // Forward loss term of one step: sum over the top row of T - T_top from the
@@ -345,6 +362,9 @@ __global__ __launch_bounds__(256) void adj_pull(AdjArgs<typename St::C> a) {
   }
   // the bottom row's blocks also accumulate dL/dT_b of their columns
   if (y == 0) grad_tb_column<St>(a, x);
+  // densities of the next reverse step's state: aux is free again once
+  // adj_local and adj_scatter of this step are done
+  if (a.next_state) density_node<St>(a, a.next_state, x, y);
 }
 
 

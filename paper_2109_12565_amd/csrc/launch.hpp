@@ -95,9 +95,12 @@ struct Adjoint {
   static void top_row_term(const Device& d, const AdjointWork& w, const void* state, int k);
   // Reverse step of state -> next state: lambda[1 - in] from lambda[in]
   // (dL/d of the next state), adding the top-row loss term with weight
-  // kappa_top and accumulating dL/dT_b into w.grad.
+  // kappa_top and accumulating dL/dT_b into w.grad. density_ready: the
+  // densities of `state` are already in w.aux (done by the previous reverse
+  // step); next_state (or null): the state of the following reverse step,
+  // whose densities this step then prepares.
   static void reverse_step(const Device& d, const AdjointWork& w, const void* state, int in,
-                           double kappa_top);
+                           double kappa_top, const void* next_state, bool density_ready);
 };
 
 }  // namespace tlbh

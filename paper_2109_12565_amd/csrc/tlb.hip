@@ -769,10 +769,16 @@ int tlb_adjoint_step(tlb_handle* h, int64_t nsteps, double seed, double* grad_t_
                     : static_cast<char*>(h->tape) + (size_t)(j - 1) * sb;
     };
     for (int j = 1; j < len; ++j) launch_pass(h, tlbh::Pass::kStep, slot(j - 1), slot(j));
+    // within a segment each reverse step also prepares the densities of the
+    // next one's state (the previous slot); the segment's first step (j = 0)
+    // cannot, the previous segment is not recomputed yet
+    bool ready = false;
     for (int j = len - 1; j >= 0; --j) {
+      void* next = j > 0 ? slot(j - 1) : nullptr;
       with_adjoint_storage(h, [&](auto st) {
-        tlbh::Adjoint<decltype(st)>::reverse_step(d, w, slot(j), in, kappa_top);
+        tlbh::Adjoint<decltype(st)>::reverse_step(d, w, slot(j), in, kappa_top, next, ready);
       });
+      ready = next != nullptr;
       in = 1 - in;
     }
   }
