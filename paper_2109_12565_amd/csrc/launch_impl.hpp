@@ -121,8 +121,14 @@ void launch_step2(const Device& d, const void* src, void* dst) {
     auto a = make_args<typename St::C>(d, src, dst);
     a.rows_per_block = d.geo.rows2;
     constexpr unsigned M = tlbk::kModeStore | tlbk::kModeTauOne;
-    if (d.has_solid) launch_step2_kernel<St, M | tlbk::kModeSolid>(d, a);
-    else launch_step2_kernel<St, M>(d, a);
+    constexpr unsigned S = tlbk::kModeSolid, V = tlbk::kModeMoving;
+    if (d.moving) {
+      if (d.has_solid) launch_step2_kernel<St, M | S | V>(d, a);
+      else launch_step2_kernel<St, M | V>(d, a);
+    } else {
+      if (d.has_solid) launch_step2_kernel<St, M | S>(d, a);
+      else launch_step2_kernel<St, M>(d, a);
+    }
   }
 }
 

@@ -1,5 +1,5 @@
 // Fused two-step update f*(t) -> f*(t+2) for tau = tau_g = 1 (arXiv:2109.12565,
-// Sec. 2), FP32 and FP64 storage, walls at rest.
+// Sec. 2), FP32 and FP64 storage, flat walls at rest or moving along x.
 //
 // At tau = tau_g = 1 the BGK collision (Eqs. (2), (16)) returns the
 // equilibria (Eqs. (3), (18)), so the post-collision populations of a node
@@ -186,7 +186,7 @@ __device__ inline void pull_level2(const StepArgs<C>& a, const Mom4<C> (&sm)[RM]
   fb[I] = plus ? Sb + Db : Sb - Db;
   C v = plus ? Sg + Dg : Sg - Dg;
   if (bb) {
-    const C tw = source_wall_temperature<I, kMode>(a, x, r);
+    const C tw = source_wall_temperature<I, kMode>(a, x, r) * wall_even_factor<I, kMode>(a, r);
     v = C(2) * w_dir<C>(I) * tw - v;
   }
   g[I] = v;
@@ -198,8 +198,8 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   using O = Off<kMode>;
   static_assert(!St::kDev && !St::kFix, "two-step kernel: FP32 / FP64 storage only");
   static_assert((kMode & kModeTauOne) != 0 && (kMode & kModeStore) != 0, "tau = 1 store pass");
-  static_assert((kMode & (kModeMoving | kModeWide | kModeInit | kModeObserve | kModeFields)) == 0,
-                "walls at rest, 32-bit offsets, no observables");
+  static_assert((kMode & (kModeWide | kModeInit | kModeObserve | kModeFields)) == 0,
+                "32-bit offsets, no observables");
   constexpr int kH = 5;          // left halo lanes
   constexpr int R1 = 5, RM = 3;  // density ring rows, moment ring rows
   constexpr int W = BT + 4;      // density ring row: lanes plus 2 padding columns each side
@@ -337,6 +337,29 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
           TLB_PULL2(false)
         }
 #undef TLB_PULL2
+        if constexpr ((kMode & kModeMoving) != 0) {
+          // moving flat walls (Sec. 2.2): the bounced diagonal links of rows
+          // 0 and ly - 1 gain 6 w_i rho_w c_ix u_w, rho_w the node's own
+          // zeroth moment at the intermediate level
+          if (r == 0 || r == ly - 1) {
+            const Mom4<C>* m = sm[so][cm];
+            const C rwa = m[0].rho, rwb = m[1].rho;
+            if (r == 0) {
+              const C k = C(6) * w_dir<C>(5) * a.uw0;
+              fa[5] += k * rwa;
+              fb[5] += k * rwb;
+              fa[6] -= k * rwa;
+              fb[6] -= k * rwb;
+            }
+            if (r == ly - 1) {
+              const C k = C(6) * w_dir<C>(8) * a.uw1;
+              fa[8] += k * rwa;
+              fb[8] += k * rwb;
+              fa[7] -= k * rwa;
+              fb[7] -= k * rwb;
+            }
+          }
+        }
         kw[0] = sum9(fa);
         kw[1] = sum9(fb);
         kw[2] = momentum_x(fa, fb);

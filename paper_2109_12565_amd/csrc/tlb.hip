@@ -143,14 +143,13 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
   l.rows = (int)(rows < ly ? rows : ly);
   l.grid = dim3((unsigned)strips, (unsigned)((ly + l.rows - 1) / l.rows), 1);
 
-  // Fused two-step kernel: tau = tau_g = 1, FP32 or FP64 storage, walls at
-  // rest, 32-bit offsets. Its strips overlap by kStep2Halo columns and its
+  // Fused two-step kernel: tau = tau_g = 1, FP32 or FP64 storage, 32-bit
+  // offsets. Its strips overlap by kStep2Halo columns and its
   // chunks recompute 5 rows of the first step on each side, so it pays
   // where the chunks can be tall and the grid still fills every CU once:
   // chunks of at least 24 rows, one block per resident slot. TLB_STEP2=1
   // selects it wherever it applies (FP64 included), TLB_STEP2=0 never.
-  const bool moving = p.u_wall[0] != 0.0 || p.u_wall[1] != 0.0;
-  const bool eligible = tau_one && !moving && !l.wide &&
+  const bool eligible = tau_one && !l.wide &&
                         (p.precision == TLB_FP32 || p.precision == TLB_FP64);
   const char* step2_env = std::getenv("TLB_STEP2");
   const int step2_mode = step2_env ? std::atoi(step2_env) : -1;

@@ -1,8 +1,8 @@
-"""The fused two-step kernel (tau = tau_g = 1, FP32 / FP64, walls at rest)
-against runs made of single steps and against the oracle.
+"""The fused two-step kernel (tau = tau_g = 1, FP32 / FP64, flat walls at
+rest or moving) against runs made of single steps and against the oracle.
 
-The fused kernel keeps the intermediate time level as nine moments per node
-and rebuilds its populations with the same expressions the single step
+The fused kernel keeps the intermediate time level as moments per node
+(density, velocity and u^2 of each field) and rebuilds its populations with the same expressions the single step
 stores them with; the compiler contracts multiply-adds into fused ones
 differently in the two kernels, so the results agree to rounding, not bit
 for bit: after 18 steps the bar against single steps is 1e-13 relative in
@@ -103,8 +103,6 @@ def test_fused_kernel_is_not_used_where_it_does_not_apply(monkeypatch):
         assert info["fused_rows"] == 0, precision
     _, info = make(w, "fp32", monkeypatch, True, tau=0.8)
     assert info["fused_rows"] == 0
-    _, info = make(w, "fp32", monkeypatch, True, u_wall=(0.0, 0.01))
-    assert info["fused_rows"] == 0
 
 
 def test_fp64_fused_matches_oracle(monkeypatch):
@@ -203,3 +201,56 @@ def test_fused_launch_geometry(monkeypatch):
     sim, info2 = make(w, "fp32", monkeypatch, True, rows=40)
     sim.close()
     assert info2["fused_rows"] == 40 and info2["fused_strip"] <= 200
+
+
+U_WALL = (-0.01, 0.02)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["small", "posts"])
+def test_fused_moving_walls_match_single_steps(monkeypatch, precision, name):
+    """Couette walls (Sec. 2.2): the second level adds the wall momentum to
+    the bounced diagonal links with the node's own intermediate zeroth
+    moment as rho_w, which equals the sum of its stored populations in the
+    single step up to rounding."""
+    case = CASES[name]()
+    fused, info = make(case, precision, monkeypatch, True, rows=7, u_wall=U_WALL)
+    assert info["fused_rows"] > 0
+    single, _ = make(case, precision, monkeypatch, False, u_wall=U_WALL)
+    for n in (9, 1, 2, 6):
+        fused.step(n)
+        single.step(n)
+    if precision == "fp64":
+        assert_close_state(fused, single, 1e-13, 1e-13)
+    else:
+        assert_close_state(fused, single, 2e-6, 2e-5)
+
+
+def test_fp64_fused_moving_walls_match_oracle(monkeypatch):
+    case = posts_case()
+    sim, info = make(case, "fp64", monkeypatch, True, rows=5, u_wall=U_WALL)
+    assert info["fused_rows"] > 0
+    ora = Oracle(ModelParams(**dict(case["params"], u_wall=U_WALL)), case["rho_a"], case["rho_b"],
+                 case["temp"], solid=case["solid"], t_bottom=case["t_bottom"])
+    sim.step(151)
+    ora.step(151)
+    errs = field_errors(sim.fields(), ora.fields())
+    assert max(errs.values()) <= 1e-12, errs
+    perr = pop_errors(sim.populations(), ora.post_collision())
+    assert max(perr.values()) <= 1e-12, perr
+
+
+def test_fp32_fused_moving_walls_500_steps(monkeypatch):
+    """The single path's Couette bar (FP32 after 500 steps under shear:
+    1e-5 for densities and temperature, 3e-5 of max|u| for velocities)."""
+    case = workloads.small()
+    sim, info = make(case, "fp32", monkeypatch, True, u_wall=U_WALL)
+    assert info["fused_rows"] > 0
+    ora = Oracle(ModelParams(**dict(case["params"], u_wall=U_WALL)), case["rho_a"], case["rho_b"],
+                 case["temp"], solid=case.get("solid"), t_bottom=case.get("t_bottom"))
+    sim.step(500)
+    ora.step(500)
+    errs = field_errors(sim.fields(), ora.fields())
+    print("fp32 fused moving walls 500 steps", errs)
+    assert max(errs[k] for k in FIELDS) <= 1e-5, errs
+    assert max(errs["ux"], errs["uy"]) <= 3e-5, errs
