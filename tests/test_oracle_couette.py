@@ -113,3 +113,28 @@ def test_layered_state_has_no_xy_stress():
     s = o.stress()
     assert np.abs(s["pxy_int"]).max() < 1e-16
     assert np.abs(s["sxy_visc"]).max() < 1e-16
+
+
+@pytest.mark.parametrize("tau,tau_g", [(1.0, 1.0), (0.8, 0.7)])
+def test_uniform_translation_with_comoving_walls_is_stationary(tau, tau_g):
+    """Galilean check of both moving-wall rules (Sec. 2.2): a uniform fluid
+    moving along x with the walls, at the walls' temperature, with wetting
+    densities equal to the fluid's (so no force acts), is an exact steady
+    state. Bounce-back with the momentum term returns f^eq_opp(rho, u_w), and
+    anti-bounce-back against the even part 2 w_i T_w (1 + 4.5 (c_i.u_w)^2
+    - 1.5 u_w^2) returns g^eq(T_w, u_w) at every wall link, for any tau;
+    any other u_w^2 factor in the thermal rule moves the populations of the
+    wall rows away from the equilibrium at the first step."""
+    lx, ly, uw, tw = 8, 12, 0.05, 0.7
+    ra, rb = np.full((ly, lx), 0.6), np.full((ly, lx), 0.4)
+    p = ModelParams(**dict(workloads.BASE_PARAMS, tau=tau, tau_g=tau_g, alpha_g=0.0,
+                           rho_wall=(0.6, 0.4), t_top=tw, u_wall=(uw, uw)))
+    o = Oracle(p, ra, rb, np.full((ly, lx), tw), t_bottom=np.full(lx, tw),
+               ux0=np.full((ly, lx), uw), uy0=np.zeros((ly, lx)), threads=1)
+    start = o.populations()
+    o.step(150)
+    np.testing.assert_allclose(o.populations(), start, rtol=1e-13, atol=0)
+    f = o.fields()
+    np.testing.assert_allclose(f["ux"], uw, rtol=1e-13)
+    assert np.abs(f["uy"]).max() < 1e-15
+    np.testing.assert_allclose(f["temp"], tw, rtol=1e-14)

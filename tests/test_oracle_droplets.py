@@ -96,3 +96,33 @@ def test_conduction_gives_unit_droplet_nusselt():
     d = oracle_of(mask, **FREE).droplets(0.8)
     assert len(d["root"]) == 2
     np.testing.assert_allclose(d["nu"], 1.0, rtol=1e-12)
+
+
+def test_droplet_nusselt_with_flow_on_linear_fields():
+    """Eq. (25) with the flow on, at t = 0 (fields = the initial ones; no
+    forces act without couplings): a 12 x 9 block droplet of uniform density
+    (centre of mass (19.5, 18): between columns, on a row), u^H_y = U + s x
+    and T = a + b x + c y. Bilinear interpolation reproduces the linear
+    fields at the centre and the central difference gives dT/dy = c, so
+    Nu_d = ((U + s X)(a + b X + c Y) - kappa c) / (kappa dt_nominal / ly).
+    The product of the interpolated u_y and T differs from the interpolated
+    product by s b a_x (1 - a_x), and swapped x/y weights move the centre, so
+    either mistake changes Nu_d."""
+    lx, ly = 48, 40
+    inside = np.zeros((ly, lx), bool)
+    inside[14:23, 14:26] = True
+    x = np.arange(lx)[None, :] * np.ones((ly, 1))
+    y = np.arange(ly)[:, None] * np.ones((1, lx))
+    a, b, c, u0, s = 0.3, 0.01, 0.02, 0.01, 0.002
+    tau_g, dtn = 0.8, 0.7
+    kappa = (tau_g - 0.5) / 3.0
+    ra = np.where(inside, RHO_IN, RHO_OUT)
+    rb = np.where(inside, RHO_OUT, RHO_IN)
+    o = Oracle(ModelParams(**dict(workloads.BASE_PARAMS, tau_g=tau_g, dt_nominal=dtn, **FREE)),
+               ra, rb, a + b * x + c * y, ux0=np.full((ly, lx), 0.003), uy0=u0 + s * x, threads=1)
+    d = o.droplets(0.8)
+    assert len(d["root"]) == 1 and d["size"][0] == 12 * 9
+    X, Y = 19.5, 18.0
+    assert d["x"][0] == pytest.approx(X, abs=1e-12) and d["y"][0] == pytest.approx(Y, abs=1e-12)
+    expect = ((u0 + s * X) * (a + b * X + c * Y) - kappa * c) / (kappa * dtn / ly)
+    assert d["nu"][0] == pytest.approx(expect, rel=1e-12)

@@ -147,6 +147,30 @@ def test_buoyancy_force_and_half_force_velocity():
         assert o.observables()["ke"] == pytest.approx(expect * expect, rel=1e-12)
 
 
+def test_convective_nusselt_in_uniform_buoyant_flow():
+    """Nu (Eq. (24)) with the flow on: a uniform fluid moving with u_y = U at
+    uniform temperature T0 in a fully periodic box, accelerated by buoyancy
+    (Eq. (22)). T stays T0 and dT/dy = 0, while u^H_y(t) = U + (t + 1/2)
+    alpha_g T0 (rho u^H = rho u + F/2, F = rho alpha_g T0), so
+    Nu(t) = u^H_y T0 / (kappa dt_nominal / ly) with kappa = (tau_g - 1/2)/3.
+    Taking u instead of u^H, dropping the convective term, or a wrong
+    normalisation each changes Nu."""
+    ly, lx = 6, 5
+    t0, ag, u0, tau_g, dtn = 0.8, 3e-4, 0.01, 0.8, 0.5
+    kappa = (tau_g - 0.5) / 3.0
+    ra, rb = np.full((ly, lx), 0.7), np.full((ly, lx), 0.2)
+    o = Oracle(_params(alpha_g=ag, tau_g=tau_g, dt_nominal=dtn), ra, rb, np.full((ly, lx), t0),
+               ux0=np.zeros((ly, lx)), uy0=np.full((ly, lx), u0), periodic_y=True)
+    for t in (0, 1, 9, 40):
+        if t:
+            o.step(t - o.t)
+        uh = u0 + (t + 0.5) * ag * t0
+        obs = o.observables()
+        assert obs["nu"] == pytest.approx(uh * t0 / (kappa * dtn / ly), rel=1e-12), t
+        assert obs["ke"] == pytest.approx(uh * uh, rel=1e-12), t
+        np.testing.assert_allclose(o.fields()["temp"], t0, rtol=1e-14)
+
+
 # ------------------------------------------------------------- invariants
 
 
