@@ -58,20 +58,41 @@ def measured_traffic(workload: str, precision: str, kernel: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(w: dict, sample_steps: int) -> dict:
-    """FP64 oracle (C, OpenMP over rows) on the full lattice of the workload
-    for a few steps; MLUPS over the step loop only."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w: dict, sample_steps: int, single_steps: int) -> dict:
+    """FP64 oracle (C, OpenMP over rows) on the full lattice of the workload:
+    `sample_steps` steps on all the threads the host gives the process, then
+    `single_steps` on one thread; MLUPS over the step loop only."""
     from oracle.oracle import ModelParams, Oracle
 
-    ora = Oracle(ModelParams(**w["params"]), w["rho_a"], w["rho_b"], w["temp"],
-                 solid=w["solid"], t_bottom=w["t_bottom"])
-    t0 = time.perf_counter()
-    ora.step(sample_steps)
-    dt = time.perf_counter() - t0
-    lups = w["lx"] * w["ly"] * sample_steps
-    return {"value": lups / dt / 1e6, "unit": "MLUPS", "cores": ora.threads, "kind": "oracle",
-            "sample": f"{sample_steps} steps of the full {w['lx']}x{w['ly']} lattice, FP64, "
-                      f"{dt:.1f} s"}
+    def run(steps, threads):
+        ora = Oracle(ModelParams(**w["params"]), w["rho_a"], w["rho_b"], w["temp"],
+                     solid=w["solid"], t_bottom=w["t_bottom"], threads=threads)
+        t0 = time.perf_counter()
+        ora.step(steps)
+        dt = time.perf_counter() - t0
+        return w["lx"] * w["ly"] * steps / dt / 1e6, dt, ora.threads
+
+    mlups, dt, threads = run(sample_steps, None)
+    out = {"value": mlups, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": f"{sample_steps} steps of the full {w['lx']}x{w['ly']} lattice, FP64, "
+                     f"{dt:.1f} s"}
+    if single_steps > 0:
+        m1, dt1, _ = run(single_steps, 1)
+        out["single_thread"] = {"value": m1, "unit": "MLUPS", "cores": 1,
+                                "sample": f"{single_steps} steps of the same lattice, {dt1:.1f} s"}
+    return out
 
 
 def adjoint_ratio(steps: int, ckpt: int, precision: str) -> dict:
@@ -197,7 +218,9 @@ def main() -> int:
     ap.add_argument("--config", default="large", choices=sorted(workloads.CONFIGS))
     ap.add_argument("--precision", default="fp32", choices=sorted(BYTES_PER_POP))
     ap.add_argument("--cpu-steps", type=int, default=25,
-                    help="oracle steps for the CPU baseline (0 to skip)")
+                    help="oracle steps for the CPU baseline on all host threads (0 to skip)")
+    ap.add_argument("--cpu-steps-1t", type=int, default=2,
+                    help="oracle steps for the one-thread CPU baseline (0 to skip)")
     ap.add_argument("--study", choices=["precision"], default=None,
                     help="instead of the benchmark, print the precision study (storages vs the "
                          "FP64 oracle on the 512x256 crop)")
@@ -269,10 +292,31 @@ def main() -> int:
     t_drop = time.perf_counter()
     drops = sim.droplets(0.8)
     t_drop = time.perf_counter() - t_drop
-    step_ms = e0.elapsed_time(e1)          # the K step launches only
     total_ms = e0.elapsed_time(e2)         # whole job: steps + observables
-    # single-step launches timed on their own (each call of one step is one
-    # launch of the single-step kernel), after everything reported above
+
+    # Launch durations, measured directly with HIP events on the library's
+    # stream (torch's current stream): tlb_step(n) with fused launches runs
+    # (n - 1) // 2 of them and one or two single steps, so two calls whose
+    # step counts differ by 2 (b - a) differ by exactly b - a fused launches;
+    # without the fused kernel they differ by that many single steps.
+    launch = sim.launch_info()
+    fused = launch["fused_rows"] > 0
+
+    def call_ms(n, reps=3):
+        best = float("inf")
+        for _ in range(reps):
+            ea, eb = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+            ea.record(stream)
+            sim.step(n)
+            eb.record(stream)
+            torch.cuda.synchronize()
+            best = min(best, ea.elapsed_time(eb))
+        return best
+
+    ka, kb = 2, 12
+    per_launch_s = (call_ms(2 * kb + 1) - call_ms(2 * ka + 1)) * 1e-3 / (2 * (kb - ka) if not fused
+                                                                         else (kb - ka))
+    # the single step that ends every call (it also forms the observable sums)
     n_one = 20
     e3, e4 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
     e3.record(stream)
@@ -282,31 +326,27 @@ def main() -> int:
     torch.cuda.synchronize()
     single_s = e3.elapsed_time(e4) * 1e-3 / n_one
 
-    # launches of the timed region: tlb_step runs fused two-step launches
-    # while at least three steps remain and ends with single steps
-    launch = sim.launch_info()
-    n_fused = (args.steps - 1) // 2 if launch["fused_rows"] > 0 and args.steps >= 3 else 0
+    n_fused = (args.steps - 1) // 2 if fused and args.steps >= 3 else 0
     n_single = args.steps - 2 * n_fused
     nodes = w["lx"] * w["ly"]
     mlups = nodes * args.steps / (total_ms * 1e-3) / 1e6
     bpn = 54 * BYTES_PER_POP[args.precision] + (1 if w["solid"] is not None else 0)
-    if n_fused > 0:
-        kernel, updates = "lb_step2_kernel", 2
-        per_launch_s = (step_ms * 1e-3 - n_single * single_s) / n_fused
-    else:
-        kernel, updates = "lb_step_kernel", 1
-        per_launch_s = step_ms * 1e-3 / args.steps
+    kernel, updates = ("lb_step2_kernel", 2) if n_fused > 0 else ("lb_step_kernel", 1)
+    if fused and n_fused == 0:  # fused kernel chosen, but too few steps to use it
+        per_launch_s = single_s
     # algorithmic bytes per launch: the method's bytes per lattice update
     # (27 populations read and written once, plus the solid flag) times the
     # updates one launch performs; the fused kernel moves its populations
     # once for two updates, so the bytes it must move per launch are half of
-    # that (hbm_bytes_per_launch_min) and `traffic` is the counted HBM rate
+    # that (hbm_bytes_per_launch_min); `traffic` is the counted HBM rate
     achieved = bpn * nodes * updates / per_launch_s / 1e9
     moved = bpn * nodes / per_launch_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": kernel, "bytes_per_lattice_update": bpn, "nodes_per_launch": nodes,
             "updates_per_node": updates, "launch_us": round(per_launch_s * 1e6, 2),
+            "launch_timing": f"HIP events: tlb_step({2 * kb + 1}) minus tlb_step({2 * ka + 1}), "
+                             f"best of 3 each, over {kb - ka if fused else 2 * (kb - ka)} launches",
             "hbm_bytes_per_launch_min": bpn * nodes,
             "frac_of_min_bytes": round(moved / HBM_PEAK_GBS, 4),
             "launches": {"fused": n_fused, "single": n_single},
@@ -317,10 +357,14 @@ def main() -> int:
                        else "hbm"}
     traffic = measured_traffic(w["name"], args.precision, kernel)
     if traffic is not None:
+        # counted HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated) over the
+        # launch time measured here, and that rate as a fraction of peak
         roof["traffic"] = round(traffic / per_launch_s / 1e9, 1)
         roof["traffic_bytes_per_launch"] = traffic
+        roof["traffic_frac"] = round(traffic / per_launch_s / 1e9 / HBM_PEAK_GBS, 4)
     single_gbs = bpn * nodes / single_s / 1e9
-    roof["single_step_kernel"] = {"kernel": "lb_step_kernel", "launch_us": round(single_s * 1e6, 2),
+    roof["single_step_kernel"] = {"kernel": "lb_step_kernel (with the observable sums)",
+                                  "launch_us": round(single_s * 1e6, 2),
                                   "achieved": round(single_gbs, 1),
                                   "frac": round(single_gbs / HBM_PEAK_GBS, 4),
                                   "mlups": round(nodes / single_s / 1e6, 1)}
@@ -354,7 +398,7 @@ def main() -> int:
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint_ratio(args.adjoint_steps, 25, "fp32")
     if args.cpu_steps > 0:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.cpu_steps_1t)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -145,15 +145,19 @@ int tlb_init(tlb_handle **out, const tlb_params *p, const double *rho_a,
  * streaming with bounce-back / anti-bounce-back at solid links, moments,
  * forces, velocity shift (Eq. (6)) and BGK collision. Enqueues only. With
  * tau = tau_g = 1 (the collision then returns the equilibria of Eqs. (3),
- * (18)), FP32 or FP64 storage and walls at rest, pairs of steps may run as
- * one fused launch (see tlb_launch_info); the last step of a call is always
- * a single step, and results agree with single steps to rounding. Returns
- * TLB_EINVAL for nsteps < 0 or a NULL handle, TLB_EDEVICE on a launch
- * failure. */
+ * (18)), pairs of steps may run as one fused launch where the handle's
+ * storage and lattice allow it (see tlb_launch_info; flat walls at rest or
+ * moving, posts allowed); the last step of a call is always a single step,
+ * which also forms the observable sums of the new time, and results agree
+ * with single steps to rounding. Returns TLB_EINVAL for nsteps < 0 or a
+ * NULL handle, TLB_EDEVICE on a launch failure. */
 int tlb_step(tlb_handle *h, int64_t nsteps);
 
-/* Observables at the current time (synchronises the stream). Returns
- * TLB_ENUMERIC if a component mass is not finite. */
+/* Observables at the current time (synchronises the stream). After
+ * tlb_init and tlb_step the sums are already on the device (formed by the
+ * last step); after a taped run or a new bottom temperature the time level
+ * is evaluated again. Returns TLB_ENUMERIC if a component mass is not
+ * finite. */
 int tlb_observables(tlb_handle *h, tlb_obs *out);
 
 /* Fields at the current time into host arrays of ly*lx doubles (any may be
@@ -224,7 +228,8 @@ int tlb_set_bottom_temperature(tlb_handle *h, const double *t_bottom);
  * tlb_step calls do not touch it. Checkpoint memory is
  * ceil(nsteps / ckpt_every) copies of the state. Synchronises the stream.
  * Errors: TLB_EINVAL (solid cells, moving walls, 16-bit storage, bad counts,
- * state buffer of 4 GiB or more, ly > 65535), TLB_ENOMEM, TLB_EDEVICE. */
+ * state buffer of 4 GiB or more, lx < 3, ly > 65535), TLB_ENOMEM,
+ * TLB_EDEVICE. */
 int tlb_forward_taped(tlb_handle *h, int64_t nsteps, int32_t ckpt_every, double *loss);
 
 /* Reverse sweep of the taped run: grad_t_bottom (host, lx doubles) receives
@@ -245,7 +250,7 @@ int64_t tlb_time(const tlb_handle *h);
  * lattice onto GPU threads; here a block of `bx` threads marches over a
  * chunk of `rows` rows of a `bx`-column strip). fused_rows > 0 means that
  * tlb_step advances pairs of steps with the fused two-step kernel (tau =
- * tau_g = 1, FP32 / FP64, walls at rest; strips of fused_strip stored
+ * tau_g = 1, flat walls at rest or moving; strips of fused_strip stored
  * columns, chunks of fused_rows rows); every tlb_step call still ends with a
  * single step. Host struct, written by the call. Returns TLB_EINVAL on a
  * NULL argument. */

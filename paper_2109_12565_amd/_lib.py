@@ -65,6 +65,12 @@ class Droplet(ctypes.Structure):
                 ("x", ctypes.c_double), ("y", ctypes.c_double), ("nu", ctypes.c_double)]
 
 
+# the same record as a numpy structured type (filled by the library in place)
+DROPLET_DTYPE = np.dtype([(k, np.int64 if k in ("root", "size") else np.float64)
+                          for k, _ in Droplet._fields_], align=True)
+assert DROPLET_DTYPE.itemsize == ctypes.sizeof(Droplet)
+
+
 _lib = None
 
 
@@ -92,7 +98,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tlb_get_populations.argtypes = [vp, dp]
     lib.tlb_get_stress.argtypes = [vp, dp, dp]
     lib.tlb_row_averages.argtypes = [vp, dp, dp]
-    lib.tlb_droplets.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Droplet), ctypes.c_int64,
+    lib.tlb_droplets.argtypes = [vp, ctypes.c_double, vp, ctypes.c_int64,
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
     lib.tlb_set_bottom_temperature.argtypes = [vp, dp]
     lib.tlb_forward_taped.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, dp]
@@ -188,6 +194,8 @@ class Simulation:
         p.u_wall[0], p.u_wall[1] = params.get("u_wall", (0.0, 0.0))
         self.params = p
         self.precision = precision
+        self._drop_cap = 4096      # droplet records asked for by droplets()
+        self._tape_generation = 0  # bumped by every forward_taped
         s = _current_stream() if stream == "torch" else stream
         rc = self._lib.tlb_init(ctypes.byref(self._h), ctypes.byref(p), _dp(rho_a), _dp(rho_b),
                                 _dp(temp), _dp(ux0), _dp(uy0),
@@ -251,18 +259,17 @@ class Simulation:
         count = ctypes.c_int64()
         lab = np.empty((ly, lx), np.int32) if labels else None
         lab_p = lab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if labels else None
-        cap = min(ly * lx, 1 << 18)
-        arr = (Droplet * cap)()
-        self._check(self._lib.tlb_droplets(self._h, float(threshold), arr, cap, ctypes.byref(count),
-                                           lab_p))
+        fn = self._lib.tlb_droplets
+        arr = np.empty(self._drop_cap, DROPLET_DTYPE)
+        self._check(fn(self._h, float(threshold), arr.ctypes.data, len(arr), ctypes.byref(count),
+                       lab_p))
         n = count.value
-        if n > cap:  # more droplets than the first guess: ask again with room for all
-            arr = (Droplet * n)()
-            self._check(self._lib.tlb_droplets(self._h, float(threshold), arr, n,
-                                               ctypes.byref(count), None))
-        out = {k: np.array([getattr(arr[i], k) for i in range(n)],
-                           dtype=np.int64 if k in ("root", "size") else np.float64)
-               for k, _ in Droplet._fields_}
+        if n > len(arr):  # more droplets than room: ask again with room for all
+            self._drop_cap = n
+            arr = np.empty(n, DROPLET_DTYPE)
+            self._check(fn(self._h, float(threshold), arr.ctypes.data, n, ctypes.byref(count),
+                           None))
+        out = {k: np.ascontiguousarray(arr[k][:n]) for k in DROPLET_DTYPE.names}
         if labels:
             out["label"] = lab
         return out
@@ -282,9 +289,16 @@ class Simulation:
         """Advance ``nsteps`` steps keeping checkpoints every ``ckpt_every``;
         returns the time-averaged top-wall Nusselt number over them."""
         loss = ctypes.c_double()
+        self._tape_generation += 1
         self._check(self._lib.tlb_forward_taped(self._h, int(nsteps), int(ckpt_every),
                                                 ctypes.byref(loss)))
         return loss.value
+
+    @property
+    def tape_generation(self) -> int:
+        """Number of taped runs started on this handle (identifies the tape
+        that a later ``adjoint`` call sweeps)."""
+        return self._tape_generation
 
     def adjoint(self, nsteps: int, seed: float = 1.0) -> np.ndarray:
         """``seed`` times the gradient of the taped loss with respect to the
@@ -326,11 +340,18 @@ def _autograd_function():
             sim.set_bottom_temperature(t_bottom.detach().to("cpu", torch.float64).numpy())
             loss = sim.forward_taped(nsteps, ckpt_every)
             ctx.sim, ctx.nsteps = sim, nsteps
+            ctx.generation = sim.tape_generation
             ctx.dtype, ctx.device = t_bottom.dtype, t_bottom.device
             return torch.tensor(loss, dtype=t_bottom.dtype, device=t_bottom.device)
 
         @staticmethod
         def backward(ctx, grad_out):
+            if ctx.sim.tape_generation != ctx.generation:
+                # the handle holds one tape: a later taped run replaced it
+                raise RuntimeError(
+                    "top_nusselt_loss: the simulation was taped again after this loss was "
+                    "formed; its tape is gone (differentiate each loss before the next taped "
+                    "run on the same Simulation)")
             g = ctx.sim.adjoint(ctx.nsteps, float(grad_out))
             return torch.as_tensor(g, dtype=ctx.dtype).to(ctx.device), None, None, None
 

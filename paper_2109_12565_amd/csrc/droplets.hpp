@@ -12,8 +12,10 @@
 //
 // Per-droplet sums (node count, sum rho_A, sum rho_A X, sum rho_A Y) are
 // exact: each term is rounded once to a multiple of 2^-40 and split into a
-// high and a low 32-bit part that are added with 64-bit integer atomics, so
-// the result does not depend on the order of the additions.
+// high and a low 32-bit part; the parts are summed as 64-bit integers, first
+// over the lanes of a wavefront that belong to the same droplet and then
+// across wavefronts with integer atomics, so the result does not depend on
+// the order of the additions.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,8 +23,14 @@
 
 namespace tlbk {
 
+// One droplet as the C ABI returns it (struct tlb_droplet).
+struct DropRecord {
+  int64_t root, size;
+  double mass, x, y, nu;
+};
+
 struct DropArgs {
-  const double* fields;     // [7][ly][lx]: rho_A, rho_B, u^H_x, u^H_y, T, ...
+  const double* fields;     // [5][ly][lx]: rho_A, rho_B, u^H_x, u^H_y, T
   const uint8_t* solid;     // [ly*lx]
   const double* t_bottom;   // [lx] (FP64 copy)
   int32_t* parent;          // [ly*lx] union-find parents, -1 outside droplets
@@ -30,7 +38,7 @@ struct DropArgs {
   int32_t* block_count;     // [nblocks] roots per block, then exclusive offsets
   int64_t* acc;             // [count][7] size, mass hi/lo, mx hi/lo, my hi/lo
   int64_t* roots;           // [count] root node of each droplet
-  double* out;              // [count][6] root, size, mass, x, y, nu
+  DropRecord* out;          // [count]
   int32_t* label;           // [ly*lx] droplet number, -1 outside
   int* error;               // set when a bounded loop runs out
   double threshold, t_top, kappa, dt_nominal;
@@ -88,6 +96,7 @@ __device__ inline bool is_bulk(const DropArgs& a, int q) {
 __global__ __launch_bounds__(256) void drop_init(DropArgs a) {
   const int q = blockIdx.x * 256 + threadIdx.x;
   if (q >= a.n) return;
+  if (q == 0) *a.error = 0;  // raised only by the later passes
   a.parent[q] = is_bulk(a, q) ? q : -1;
 }
 
@@ -183,40 +192,84 @@ __global__ __launch_bounds__(256) void drop_number_roots(DropArgs a) {
 
 // Fixed-point term: v rounded to a multiple of 2^-40, split into a high
 // part (multiples of 2^-8) and a low part in [0, 2^32) units of 2^-40.
-__device__ inline void add_fixed(int64_t* hi, int64_t* lo, double v) {
+__device__ inline void split_fixed(double v, int64_t& hi, int64_t& lo) {
   const int64_t f = __double2ll_rn(v * 1099511627776.0);  // 2^40
-  const int64_t h = f >> 32;
-  const int64_t l = f - (h << 32);
-  atomicAdd(reinterpret_cast<unsigned long long*>(hi), (unsigned long long)h);
-  atomicAdd(reinterpret_cast<unsigned long long*>(lo), (unsigned long long)l);
+  hi = f >> 32;
+  lo = f - (hi << 32);
 }
 
 __device__ inline double fixed_value(int64_t hi, int64_t lo) {
   return ((double)hi * 4294967296.0 + (double)lo) * (1.0 / 1099511627776.0);
 }
 
+__device__ inline int64_t wave_sum(int64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // Per node: its droplet number, and its terms of the droplet's sums (x
-// taken within half a period of the root's x).
+// taken within half a period of the root's x). The lanes of a wavefront
+// that belong to one droplet add their terms first (one group per distinct
+// droplet, taken in lane order), so each group issues one set of atomics.
 __global__ __launch_bounds__(256) void drop_accumulate(DropArgs a) {
   const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= a.n) return;
-  const int32_t root = a.parent[q];
-  if (root < 0) {
-    a.label[q] = -1;
-    return;
+  const int lane = threadIdx.x & 63;
+  int d = -1;
+  int64_t t[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (q < a.n) {
+    const int32_t root = a.parent[q];
+    if (root >= 0) {
+      d = a.rid[root];
+      const int x = q % a.lx, y = q / a.lx, xr = root % a.lx, yr = root / a.lx;
+      double dx = (double)(x - xr);
+      if (dx > 0.5 * a.lx) dx -= a.lx;
+      if (dx < -0.5 * a.lx) dx += a.lx;
+      const double r = a.fields[q];
+      t[0] = 1;
+      split_fixed(r, t[1], t[2]);
+      split_fixed(r * ((double)xr + dx), t[3], t[4]);
+      split_fixed(r * (double)(yr + (y - yr)), t[5], t[6]);
+    }
+    a.label[q] = d;
   }
-  const int d = a.rid[root];
-  a.label[q] = d;
-  const int x = q % a.lx, y = q / a.lx, xr = root % a.lx, yr = root / a.lx;
-  double dx = (double)(x - xr);
-  if (dx > 0.5 * a.lx) dx -= a.lx;
-  if (dx < -0.5 * a.lx) dx += a.lx;
-  const double r = a.fields[q];
-  int64_t* c = a.acc + (size_t)d * 7;
-  atomicAdd(reinterpret_cast<unsigned long long*>(c), 1ull);
-  add_fixed(c + 1, c + 2, r);
-  add_fixed(c + 3, c + 4, r * ((double)xr + dx));
-  add_fixed(c + 5, c + 6, r * (double)(yr + (y - yr)));
+  uint64_t pending = __ballot(d >= 0);
+  while (pending != 0) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int dl = __shfl(d, leader, 64);
+    const bool mine = d == dl;
+    const uint64_t group = __ballot(mine);
+    int64_t sum[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) sum[j] = wave_sum(mine ? t[j] : 0);
+    if (lane == leader) {
+      unsigned long long* c = reinterpret_cast<unsigned long long*>(a.acc + (size_t)dl * 7);
+#pragma unroll
+      for (int j = 0; j < 7; ++j) atomicAdd(c + j, (unsigned long long)sum[j]);
+    }
+    pending &= ~group;
+  }
+}
+
+// FP64 copy of the bottom wall temperature (the handle keeps the compute
+// type of its storage).
+__global__ __launch_bounds__(256) void drop_bottom_temperature(const void* src, int src_is_f32,
+                                                               double* dst, int lx) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= lx) return;
+  dst[x] = src_is_f32 ? (double)static_cast<const float*>(src)[x]
+                      : static_cast<const double*>(src)[x];
+}
+
+// Zero the first `*count` droplet accumulators (the count is read on the
+// device; the grid covers `max_count`).
+__global__ __launch_bounds__(256) void drop_clear(int64_t* acc, const int32_t* count,
+                                                  int max_count) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int c = *count;
+  if (i >= max_count || i >= c) return;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) acc[(size_t)i * 7 + j] = 0;
 }
 
 // Temperature gradient dT/dy at node (x, y) by central differences with
@@ -264,13 +317,14 @@ __global__ __launch_bounds__(256) void drop_finalize(DropArgs a) {
   const double t = w00 * T[q00] + w01 * T[q01] + w10 * T[q10] + w11 * T[q11];
   const double g = w00 * node_dtdy(a, x0, y0) + w01 * node_dtdy(a, x1, y0) +
                    w10 * node_dtdy(a, x0, y1) + w11 * node_dtdy(a, x1, y1);
-  double* o = a.out + (size_t)d * 6;
-  o[0] = (double)a.roots[d];
-  o[1] = (double)c[0];
-  o[2] = m;
-  o[3] = X;
-  o[4] = Y;
-  o[5] = (u * t - a.kappa * g) / (a.kappa * a.dt_nominal / a.ly);
+  DropRecord o;
+  o.root = a.roots[d];
+  o.size = c[0];
+  o.mass = m;
+  o.x = X;
+  o.y = Y;
+  o.nu = (u * t - a.kappa * g) / (a.kappa * a.dt_nominal / a.ly);
+  a.out[d] = o;
 }
 
 }  // namespace tlbk

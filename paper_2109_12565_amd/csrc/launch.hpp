@@ -15,7 +15,7 @@ struct Geometry {
   int rows = 1;      // rows per block chunk
   bool wide = false; // 64-bit byte offsets (population buffer >= 4 GiB)
   dim3 grid;
-  // fused two-step kernel (tau = tau_g = 1, FP32 / FP64, walls at rest);
+  // fused two-step kernel (tau = tau_g = 1; flat walls at rest or moving);
   // rows2 == 0: not used
   int rows2 = 0;     // rows per block chunk
   int strip2 = 0;    // stored columns per strip (kStep2Lanes - kStep2Halo at most)
@@ -47,7 +47,8 @@ struct Device {
 // Kernel passes of the step kernel.
 enum class Pass {
   kStep,         // f*(t) -> f*(t+1)
-  kInitStep,     // f(0) in place -> f*(0)
+  kStepObserve,  // same, and the observable sums of time t+1 into partials
+  kInitStep,     // f(0) in place -> f*(0), and the observable sums of t = 0
   kObserve,      // observable sums of time t from f*(t-1), no store
   kObserveInit,  // same at t = 0 from f(0)
   kFields,       // fields of time t from f*(t-1), no store

@@ -173,7 +173,10 @@ void Launcher<St>::step(const Device& d, Pass pass, const void* src, void* dst) 
   using namespace tlbk;
   switch (pass) {
     case Pass::kStep: detail::launch_mode<St, kModeStore>(d, src, dst); break;
-    case Pass::kInitStep: detail::launch_mode<St, kModeStore | kModeInit>(d, src, dst); break;
+    case Pass::kStepObserve: detail::launch_mode<St, kModeStore | kModeObserve>(d, src, dst); break;
+    case Pass::kInitStep:
+      detail::launch_mode<St, kModeStore | kModeInit | kModeObserve>(d, src, dst);
+      break;
     case Pass::kObserve: detail::launch_mode<St, kModeObserve>(d, src, dst); break;
     case Pass::kObserveInit: detail::launch_mode<St, kModeObserve | kModeInit>(d, src, dst); break;
     case Pass::kFields: detail::launch_mode<St, kModeFields>(d, src, dst); break;

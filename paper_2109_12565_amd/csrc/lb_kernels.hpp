@@ -162,6 +162,10 @@ struct StoreFix16Dev {
 };
 
 // ---------------------------------------------------------------- arguments
+// Observable sums per block (FP64, fluid nodes): rho_A, rho_B, T, u^H_y T,
+// |u^H|^2, and T - t_top over the top row.
+constexpr int kObsSums = 6;
+
 template <typename C>
 struct StepArgs {
   const void* src;          // post-collision populations f*(t) (or f(0))
@@ -169,7 +173,7 @@ struct StepArgs {
   const uint16_t* link;     // [ly*lx] link masks (solid cells present only)
   const uint8_t* solid;     // [ly*lx] 0 fluid, 1 bottom-held, 2 top-held
   const C* t_bottom;        // [lx]
-  double* partials;         // [gridDim.x*gridDim.y][8] observable sums
+  double* partials;         // [gridDim.x*gridDim.y][kObsSums] observable sums
   double* fields;           // [5][ly][lx] rho_a, rho_b, ux, uy, T
   int lx, ly, pitch, rows_per_block;
   long long pop_stride;     // ly * pitch
@@ -553,23 +557,6 @@ __device__ inline C solid_temperature(const StepArgs<C>& a, int x, int y) {
   return a.solid[(uint32_t)y * (uint32_t)a.lx + (uint32_t)x] == 1 ? tb : a.t_top;
 }
 
-// Temperature of the neighbour (x, r) of a fluid node whose temperature is
-// t_here, for the central difference of dT/dy: T itself if fluid, else the
-// mirror value 2 T_w - t_here (wall plane half-way).
-template <class St, unsigned kMode, typename C>
-__device__ inline C neighbour_temperature(const StepArgs<C>& a, const PopMem<St, kMode>& m,
-                                          const LaneOff<kMode>& L, int x, int r, C t_here) {
-  if (r < 0) return C(2) * a.t_bottom[x] - t_here;
-  if (r >= a.ly) return C(2) * a.t_top - t_here;
-  const uint32_t lm = link_mask<kMode>(a, x, r);
-  if (lm & kSelfSolid) return C(2) * solid_temperature(a, x, r) - t_here;
-  C g[9];
-  pull_thermal<St, kMode>(a, m, L, x, r, lm, g);
-  C t = sum9(g);
-  if constexpr (St::kDev) t += a.ref_t;
-  return t;
-}
-
 // ---------------------------------------------------------------- kernel
 template <class St, int BX, unsigned kMode>
 __global__ __launch_bounds__(BX)
@@ -639,7 +626,7 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
   const C psi_w0 = psi_of<St>(a.rho_wall0, a.rho0, a.inv_rho0);
   const C psi_w1 = psi_of<St>(a.rho_wall1, a.rho0, a.inv_rho0);
 
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  double acc[kObsSums] = {0, 0, 0, 0, 0, 0};
 
   // Densities of node (x, r) into ring slot `slot` / column `col`; the pulled
   // populations land in f and the node's link mask in lm. Returns whether
@@ -968,15 +955,15 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
       }
     }
     if constexpr ((kMode & kModeObserve) != 0) {
-      const C tn = neighbour_temperature<St, kMode>(a, msrc, Lo, xw, y + 1, temp);
-      const C ts = neighbour_temperature<St, kMode>(a, msrc, Lo, xw, y - 1, temp);
+      // local sums only: the fluid-node sum of the central differences of T
+      // (Nu's conductive term) telescopes along each column to the wall
+      // temperatures and is formed on the host
       acc[0] += dra;
       acc[1] += drb;
       acc[2] += dtt;
       acc[3] += (double)hy * dtt;
-      acc[4] += 0.5 * ((double)tn - (double)ts);
-      acc[5] += (double)hx * (double)hx + (double)hy * (double)hy;
-      if (y == ly - 1) acc[6] += dtt - (double)a.t_top;
+      acc[4] += (double)hx * (double)hx + (double)hy * (double)hy;
+      if (y == ly - 1) acc[5] += dtt - (double)a.t_top;
     }
   };
 
@@ -993,20 +980,20 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
   }
 
   if constexpr ((kMode & kModeObserve) != 0) {
-    // block reduction of the 7 sums in a fixed order (deterministic)
-    __shared__ double s_acc[BX / 64][8];
+    // block reduction of the sums in a fixed order (deterministic)
+    __shared__ double s_acc[BX / 64][kObsSums];
 #pragma unroll
-    for (int j = 0; j < 7; ++j) {
+    for (int j = 0; j < kObsSums; ++j) {
       double v = acc[j];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
       if ((tid & 63) == 0) s_acc[tid >> 6][j] = v;
     }
     __syncthreads();
-    if (tid < 7) {
+    if (tid < kObsSums) {
       double v = 0;
       for (int w = 0; w < BX / 64; ++w) v += s_acc[w][tid];
-      a.partials[(size_t)lin * 8 + tid] = v;
+      a.partials[(size_t)lin * kObsSums + tid] = v;
     }
   }
 }

@@ -4,29 +4,37 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lb_kernels.hpp"
+
 namespace tlbk {
 
 // Final observable reduction: one block sums the per-block partials in a
-// fixed order and forms the observables of the header's definitions.
+// fixed order and forms the observables of the header's definitions. The
+// fluid-node sum of the central differences of T, with the mirror value
+// 2 T_w - T at a solid neighbour, telescopes along every column to the
+// wall temperatures above and below each run of fluid nodes; that sum
+// (`dtdy_sum`) is formed on the host from the solid map and the wall
+// temperatures.
 struct ObsArgs {
-  const double* partials;
+  const double* partials;   // [nblocks][kObsSums]
   int nblocks;
   double n_fluid, n_top;
   double kappa, dt_nominal, ly;
+  double dtdy_sum;
   double* out;   // [6] mass_a, mass_b, sum_t, nu, nu_top, ke
 };
 
 __global__ __launch_bounds__(256) void lb_reduce_observables(ObsArgs a) {
-  __shared__ double s[7][256];
+  __shared__ double s[kObsSums][256];
   const int tid = threadIdx.x;
-  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  double v[kObsSums] = {0, 0, 0, 0, 0, 0};
   for (int b = tid; b < a.nblocks; b += 256)
-    for (int j = 0; j < 7; ++j) v[j] += a.partials[(size_t)b * 8 + j];
-  for (int j = 0; j < 7; ++j) s[j][tid] = v[j];
+    for (int j = 0; j < kObsSums; ++j) v[j] += a.partials[(size_t)b * kObsSums + j];
+  for (int j = 0; j < kObsSums; ++j) s[j][tid] = v[j];
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if (tid < h)
-      for (int j = 0; j < 7; ++j) s[j][tid] += s[j][tid + h];
+      for (int j = 0; j < kObsSums; ++j) s[j][tid] += s[j][tid + h];
     __syncthreads();
   }
   if (tid == 0) {
@@ -34,9 +42,9 @@ __global__ __launch_bounds__(256) void lb_reduce_observables(ObsArgs a) {
     a.out[0] = s[0][0];
     a.out[1] = s[1][0];
     a.out[2] = s[2][0];
-    a.out[3] = (s[3][0] * inv - a.kappa * s[4][0] * inv) / (a.kappa * a.dt_nominal / a.ly);
-    a.out[4] = a.n_top > 0 ? 2.0 * a.ly / a.dt_nominal * (s[6][0] / a.n_top) : 0.0;
-    a.out[5] = s[5][0] * inv;
+    a.out[3] = (s[3][0] * inv - a.kappa * a.dtdy_sum * inv) / (a.kappa * a.dt_nominal / a.ly);
+    a.out[4] = a.n_top > 0 ? 2.0 * a.ly / a.dt_nominal * (s[5][0] / a.n_top) : 0.0;
+    a.out[5] = s[4][0] * inv;
   }
 }
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -46,10 +47,14 @@ struct tlb_handle {
   int32_t* drop_tiles = nullptr;   // [tiles + 1] roots per tile, offsets
   int* drop_error = nullptr;
   double* drop_tb = nullptr;       // [lx] FP64 bottom temperature
-  void* drop_acc = nullptr;        // per droplet: sums, roots, results
-  size_t drop_acc_cap = 0;
+  void* drop_acc = nullptr;        // per droplet: sums, root, output record
+  size_t drop_acc_cap = 0;         // droplets drop_acc has room for
   double* export_buf = nullptr;    // [27][ly][lx], allocated on first use
   double n_fluid = 0, n_top = 0;
+  std::vector<uint8_t> host_solid;  // [ly*lx] solid flags (host copy)
+  std::vector<double> host_tb;      // [lx] bottom wall temperature (host copy)
+  double dtdy_sum = 0;             // fluid-node sum of the central dT/dy
+  int64_t obs_t = -1;              // time of the observable sums in partials
   tlbh::Geometry launch{};
   bool tau_one = false;            // tau = tau_g = 1: equilibria path
   // adjoint tape (flat walls, FP64 / FP32 storage)
@@ -187,7 +192,7 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
   return l;
 }
 
-tlbh::Device device_view(const tlb_handle* h) {
+tlbh::Device device_view(const tlb_handle* h, double* fields = nullptr) {
   tlbh::Device d;
   d.p = &h->p;
   d.stream = h->stream;
@@ -201,12 +206,13 @@ tlbh::Device device_view(const tlb_handle* h) {
   d.solid = h->solid;
   d.t_bottom = h->t_bottom;
   d.partials = h->partials;
-  d.fields = h->fields;
+  d.fields = fields ? fields : h->fields;
   return d;
 }
 
-void launch_pass(const tlb_handle* h, tlbh::Pass pass, const void* src, void* dst) {
-  const tlbh::Device d = device_view(h);
+void launch_pass(const tlb_handle* h, tlbh::Pass pass, const void* src, void* dst,
+                 double* fields = nullptr) {
+  const tlbh::Device d = device_view(h, fields);
   with_storage(h->p.precision,
                [&](auto st) { tlbh::Launcher<decltype(st)>::step(d, pass, src, dst); });
 }
@@ -215,19 +221,46 @@ void launch_pass(const tlb_handle* h, tlbh::Pass pass, const void* src, void* ds
 // moments, forces and u^H of time t (observables or fields).
 enum class Level { kObserve, kFields, kStress };
 
-int evaluate_time_level(tlb_handle* h, Level what) {
+int evaluate_time_level(tlb_handle* h, Level what, double* fields = nullptr) {
   const void* src = h->buf[1 - h->cur];
   using tlbh::Pass;
   const bool init = h->t == 0;
   Pass pass = init ? Pass::kObserveInit : Pass::kObserve;
   if (what == Level::kFields) pass = init ? Pass::kFieldsInit : Pass::kFields;
   if (what == Level::kStress) pass = init ? Pass::kStressInit : Pass::kStress;
-  launch_pass(h, pass, src, nullptr);
+  launch_pass(h, pass, src, nullptr, fields);
   TLB_HIP(h, hipGetLastError());
   return TLB_OK;
 }
 
 bool finite_positive(double v) { return std::isfinite(v) && v > 0; }
+
+// Fluid-node sum of the central differences (T(y+1) - T(y-1)) / 2 with the
+// mirror value 2 T_w - T(y) at a solid neighbour (Nu, Eq. (24)): along a
+// column each run of fluid nodes from row a to row b telescopes to
+// T_w(above b) - T_w(below a), whatever the fluid temperatures are.
+double dtdy_sum(const tlb_handle* h) {
+  const int lx = h->p.lx, ly = h->p.ly;
+  auto wall_t = [&](int x, int y) {
+    if (y < 0) return h->host_tb[x];
+    if (y >= ly) return h->p.t_top;
+    return h->host_solid[(size_t)y * lx + x] == 1 ? h->host_tb[x] : h->p.t_top;
+  };
+  double sum = 0;
+  for (int x = 0; x < lx; ++x) {
+    int y = 0;
+    while (y < ly) {
+      if (h->host_solid[(size_t)y * lx + x] != 0) {
+        ++y;
+        continue;
+      }
+      const int a = y;
+      while (y < ly && h->host_solid[(size_t)y * lx + x] == 0) ++y;
+      sum += wall_t(x, y) - wall_t(x, a - 1);
+    }
+  }
+  return sum;
+}
 
 size_t state_bytes(const tlb_handle* h) { return (size_t)27 * h->pop_stride * h->elem; }
 
@@ -280,6 +313,105 @@ template <class F>
 void with_adjoint_storage(const tlb_handle* h, F&& f) {
   if (is_fp64(h)) f(tlbk::Store<double>{});
   else f(tlbk::Store<float>{});
+}
+
+// Device buffers of one droplet detection: the fields of the time level
+// ([5][ly][lx]), per node parent / root number / label ([3][ly*lx]), the
+// per-tile root counts and their offsets, the error flag, the FP64 bottom
+// temperature ([lx]) and per droplet 7 int64 sums, the root and the output
+// record (`acc`, room for `acc_count` droplets).
+struct DropBuffers {
+  double* fields = nullptr;
+  int32_t* nodes = nullptr;
+  int32_t* tiles = nullptr;
+  int* error = nullptr;
+  double* tb = nullptr;
+  void* acc = nullptr;
+  int64_t acc_count = 0;
+};
+
+constexpr size_t kDropBytesPerDroplet =
+    7 * sizeof(int64_t) + sizeof(int64_t) + sizeof(tlbk::DropRecord);
+static_assert(sizeof(tlbk::DropRecord) == sizeof(tlb_droplet), "droplet record layout");
+static_assert(offsetof(tlb_droplet, nu) == offsetof(tlbk::DropRecord, nu), "droplet record layout");
+
+// Droplet detection into `b`. `grow` reallocates the per-droplet buffer of
+// the handle when the count exceeds it; without it more droplets than
+// b.acc_count is an error.
+int run_droplets(tlb_handle* h, const char* who, DropBuffers& b, bool grow, double threshold,
+                 tlb_droplet* out, int64_t cap, int64_t* count, int32_t* labels) {
+  const int lx = h->p.lx, ly = h->p.ly;
+  const int n = lx * ly;  // below 2^30 (checked at init)
+  const int tiles = (n + tlbk::kDropTile - 1) / tlbk::kDropTile;
+  int rc = evaluate_time_level(h, Level::kFields, b.fields);
+  if (rc != TLB_OK) return rc;
+  hipLaunchKernelGGL(tlbk::drop_bottom_temperature, dim3((lx + 255) / 256), dim3(256), 0,
+                     h->stream, h->t_bottom, is_fp64(h) ? 0 : 1, b.tb, lx);
+  tlbk::DropArgs a{};
+  a.fields = b.fields;
+  a.solid = h->solid;
+  a.t_bottom = b.tb;
+  a.parent = b.nodes;
+  a.rid = b.nodes + n;
+  a.label = b.nodes + 2 * (size_t)n;
+  a.block_count = b.tiles;
+  a.error = b.error;
+  a.threshold = threshold;
+  a.t_top = h->p.t_top;
+  a.kappa = (h->p.tau_g - 0.5) / 3.0;
+  a.dt_nominal = h->p.dt_nominal;
+  a.lx = lx;
+  a.ly = ly;
+  a.n = n;
+  const dim3 nodes((n + 255) / 256), block(256);
+  hipLaunchKernelGGL(tlbk::drop_init, nodes, block, 0, h->stream, a);
+  hipLaunchKernelGGL(tlbk::drop_union, nodes, block, 0, h->stream, a);
+  hipLaunchKernelGGL(tlbk::drop_compress, nodes, block, 0, h->stream, a);
+  hipLaunchKernelGGL(tlbk::drop_count_roots, dim3(tiles), block, 0, h->stream, a);
+  hipLaunchKernelGGL(tlbk::drop_scan_tiles, dim3(1), block, 0, h->stream, b.tiles, tiles);
+  TLB_HIP(h, hipGetLastError());
+  int32_t total = 0;
+  int err = 0;
+  TLB_HIP(h, hipMemcpyAsync(&total, b.tiles + tiles, sizeof(int32_t), hipMemcpyDeviceToHost,
+                            h->stream));
+  TLB_HIP(h, hipMemcpyAsync(&err, b.error, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  TLB_HIP(h, hipStreamSynchronize(h->stream));
+  if (err) return fail(h, TLB_EDEVICE, "%s: cluster walk exceeded its bound", who);
+  *count = total;
+  if (total > b.acc_count) {
+    if (!grow)
+      return fail(h, TLB_EINVAL, "%s: %d droplets, more than the workspace holds (%lld)", who,
+                  (int)total, (long long)b.acc_count);
+    if (h->drop_acc) TLB_HIP(h, hipFree(h->drop_acc));
+    h->drop_acc = nullptr;
+    h->drop_acc_cap = 0;
+    TLB_HIP(h, hipMalloc(&h->drop_acc, (size_t)total * kDropBytesPerDroplet));
+    h->drop_acc_cap = (size_t)total;
+    b.acc = h->drop_acc;
+    b.acc_count = total;
+  }
+  a.acc = static_cast<int64_t*>(b.acc);
+  a.roots = a.acc + 7 * (size_t)b.acc_count;
+  a.out = reinterpret_cast<tlbk::DropRecord*>(a.roots + b.acc_count);
+  a.count = total;
+  if (total > 0) {
+    hipLaunchKernelGGL(tlbk::drop_clear, dim3((total + 255) / 256), block, 0, h->stream, a.acc,
+                       b.tiles + tiles, total);
+  }
+  hipLaunchKernelGGL(tlbk::drop_number_roots, dim3(tiles), block, 0, h->stream, a);
+  hipLaunchKernelGGL(tlbk::drop_accumulate, nodes, block, 0, h->stream, a);
+  if (total > 0)
+    hipLaunchKernelGGL(tlbk::drop_finalize, dim3((total + 255) / 256), block, 0, h->stream, a);
+  TLB_HIP(h, hipGetLastError());
+  const int64_t m = std::min<int64_t>(cap, total);
+  if (m > 0)
+    TLB_HIP(h, hipMemcpyAsync(out, a.out, (size_t)m * sizeof(tlb_droplet), hipMemcpyDeviceToHost,
+                              h->stream));
+  if (labels)
+    TLB_HIP(h, hipMemcpyAsync(labels, a.label, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost,
+                              h->stream));
+  TLB_HIP(h, hipStreamSynchronize(h->stream));
+  return TLB_OK;
 }
 
 }  // namespace
@@ -341,6 +473,7 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
       }
   }
   for (size_t q = 0; q < n; ++q) h->n_fluid += sol[q] == 0;
+  h->host_solid = sol;
   for (int x = 0; x < lx; ++x) h->n_top += sol[(size_t)(ly - 1) * lx + x] == 0;
 
   h->pitch = (lx + 63) / 64 * 64;
@@ -385,7 +518,7 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
   INIT_HIP(hipMemsetAsync(h->buf[0], 0, buf_bytes, h->stream));
   INIT_HIP(hipMemsetAsync(h->buf[1], 0, buf_bytes, h->stream));
   const size_t nblocks = (size_t)h->launch.grid.x * h->launch.grid.y;
-  INIT_HIP(hipMalloc(&h->partials, nblocks * 8 * sizeof(double)));
+  INIT_HIP(hipMalloc(&h->partials, nblocks * tlbk::kObsSums * sizeof(double)));
   INIT_HIP(hipMalloc(&h->obs, 8 * sizeof(double)));
   INIT_HIP(hipMalloc(&h->t_bottom, lx * (is_fp64(h) ? sizeof(double) : sizeof(float))));
   INIT_HIP(hipMalloc(&h->solid, n));
@@ -421,6 +554,7 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
   INIT_HIP(hipGetLastError());
   launch_pass(h, tlbh::Pass::kInitStep, h->buf[1], h->buf[0]);
   INIT_HIP(hipGetLastError());
+  h->obs_t = 0;
   INIT_HIP(hipStreamSynchronize(h->stream));
   INIT_HIP(hipFree(d_fields));
 #undef INIT_HIP
@@ -434,8 +568,9 @@ int tlb_step(tlb_handle* h, int64_t nsteps) {
   if (!h) return fail(nullptr, TLB_EINVAL, "tlb_step: NULL handle");
   if (nsteps < 0) return fail(h, TLB_EINVAL, "tlb_step: nsteps < 0");
   // Fused two-step launches first; the call always ends with a single step,
-  // so the other buffer holds f*(t-1), from which observables and fields of
-  // time t are pulled.
+  // so the other buffer holds f*(t-1), from which fields and stress of
+  // time t are pulled. That last step also leaves the observable sums of
+  // the new time in the partials.
   int64_t s = 0;
   if (h->launch.rows2 > 0) {
     for (; s + 2 < nsteps; s += 2) {
@@ -445,9 +580,12 @@ int tlb_step(tlb_handle* h, int64_t nsteps) {
     }
   }
   for (; s < nsteps; ++s) {
-    launch_pass(h, tlbh::Pass::kStep, h->buf[h->cur], h->buf[1 - h->cur]);
+    const bool last = s + 1 == nsteps;
+    launch_pass(h, last ? tlbh::Pass::kStepObserve : tlbh::Pass::kStep, h->buf[h->cur],
+                h->buf[1 - h->cur]);
     h->cur = 1 - h->cur;
     h->t += 1;
+    if (last) h->obs_t = h->t;
   }
   TLB_HIP(h, hipGetLastError());
   return TLB_OK;
@@ -469,8 +607,13 @@ int tlb_launch_info(const tlb_handle* h, tlb_launch* out) {
 
 int tlb_observables(tlb_handle* h, tlb_obs* out) {
   if (!h || !out) return fail(h, TLB_EINVAL, "tlb_observables: NULL argument");
-  int rc = evaluate_time_level(h, Level::kObserve);
-  if (rc != TLB_OK) return rc;
+  // the last step of tlb_step left the sums of the current time; otherwise
+  // (a taped run, a new bottom temperature) re-evaluate the time level
+  if (h->obs_t != h->t) {
+    int rc = evaluate_time_level(h, Level::kObserve);
+    if (rc != TLB_OK) return rc;
+    h->obs_t = h->t;
+  }
   tlbk::ObsArgs oa{};
   oa.partials = h->partials;
   oa.nblocks = (int)(h->launch.grid.x * h->launch.grid.y);
@@ -479,6 +622,7 @@ int tlb_observables(tlb_handle* h, tlb_obs* out) {
   oa.kappa = (h->p.tau_g - 0.5) / 3.0;
   oa.dt_nominal = h->p.dt_nominal;
   oa.ly = h->p.ly;
+  oa.dtdy_sum = h->dtdy_sum;
   oa.out = h->obs;
   hipLaunchKernelGGL(tlbk::lb_reduce_observables, dim3(1), dim3(256), 0, h->stream, oa);
   TLB_HIP(h, hipGetLastError());
@@ -555,103 +699,22 @@ int tlb_droplets(tlb_handle* h, double threshold, tlb_droplet* out, int64_t cap,
     return fail(h, TLB_EINVAL, "tlb_droplets: need cap >= 0 and an output array when cap > 0");
   if (!std::isfinite(threshold)) return fail(h, TLB_EINVAL, "tlb_droplets: threshold not finite");
   const int lx = h->p.lx, ly = h->p.ly;
-  const int n = lx * ly;  // below 2^30 (checked at init)
+  const int n = lx * ly;
   const int tiles = (n + tlbk::kDropTile - 1) / tlbk::kDropTile;
   if (!h->fields) TLB_HIP(h, hipMalloc(&h->fields, 7 * (size_t)n * sizeof(double)));
   if (!h->drop_nodes) TLB_HIP(h, hipMalloc(&h->drop_nodes, 3 * (size_t)n * sizeof(int32_t)));
   if (!h->drop_tiles) TLB_HIP(h, hipMalloc(&h->drop_tiles, (size_t)(tiles + 1) * sizeof(int32_t)));
   if (!h->drop_error) TLB_HIP(h, hipMalloc(&h->drop_error, sizeof(int)));
   if (!h->drop_tb) TLB_HIP(h, hipMalloc(&h->drop_tb, (size_t)lx * sizeof(double)));
-  int rc = evaluate_time_level(h, Level::kFields);
-  if (rc != TLB_OK) return rc;
-  // FP64 copy of the bottom temperature (the handle keeps the compute type)
-  {
-    std::vector<double> tb(lx);
-    if (is_fp64(h)) {
-      TLB_HIP(h, hipMemcpyAsync(h->drop_tb, h->t_bottom, lx * sizeof(double),
-                                hipMemcpyDeviceToDevice, h->stream));
-    } else {
-      std::vector<float> tf(lx);
-      TLB_HIP(h, hipMemcpyAsync(tf.data(), h->t_bottom, lx * sizeof(float), hipMemcpyDeviceToHost,
-                                h->stream));
-      TLB_HIP(h, hipStreamSynchronize(h->stream));
-      for (int x = 0; x < lx; ++x) tb[x] = tf[x];
-      TLB_HIP(h, hipMemcpyAsync(h->drop_tb, tb.data(), lx * sizeof(double), hipMemcpyHostToDevice,
-                                h->stream));
-    }
-  }
-  tlbk::DropArgs a{};
-  a.fields = h->fields;
-  a.solid = h->solid;
-  a.t_bottom = h->drop_tb;
-  a.parent = h->drop_nodes;
-  a.rid = h->drop_nodes + n;
-  a.label = h->drop_nodes + 2 * (size_t)n;
-  a.block_count = h->drop_tiles;
-  a.error = h->drop_error;
-  a.threshold = threshold;
-  a.t_top = h->p.t_top;
-  a.kappa = (h->p.tau_g - 0.5) / 3.0;
-  a.dt_nominal = h->p.dt_nominal;
-  a.lx = lx;
-  a.ly = ly;
-  a.n = n;
-  const dim3 nodes((n + 255) / 256), block(256);
-  TLB_HIP(h, hipMemsetAsync(h->drop_error, 0, sizeof(int), h->stream));
-  hipLaunchKernelGGL(tlbk::drop_init, nodes, block, 0, h->stream, a);
-  hipLaunchKernelGGL(tlbk::drop_union, nodes, block, 0, h->stream, a);
-  hipLaunchKernelGGL(tlbk::drop_compress, nodes, block, 0, h->stream, a);
-  hipLaunchKernelGGL(tlbk::drop_count_roots, dim3(tiles), block, 0, h->stream, a);
-  hipLaunchKernelGGL(tlbk::drop_scan_tiles, dim3(1), block, 0, h->stream, h->drop_tiles, tiles);
-  TLB_HIP(h, hipGetLastError());
-  int32_t total = 0;
-  int err = 0;
-  TLB_HIP(h, hipMemcpyAsync(&total, h->drop_tiles + tiles, sizeof(int32_t), hipMemcpyDeviceToHost,
-                            h->stream));
-  TLB_HIP(h, hipMemcpyAsync(&err, h->drop_error, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-  TLB_HIP(h, hipStreamSynchronize(h->stream));
-  if (err) return fail(h, TLB_EDEVICE, "tlb_droplets: cluster walk exceeded its bound");
-  *count = total;
-  // per droplet: 7 int64 sums, the root, 6 doubles of results
-  const size_t per = 7 * sizeof(int64_t) + sizeof(int64_t) + 6 * sizeof(double);
-  const size_t need = (size_t)(total > 0 ? total : 1) * per;
-  if (h->drop_acc_cap < need) {
-    if (h->drop_acc) TLB_HIP(h, hipFree(h->drop_acc));
-    h->drop_acc = nullptr;
-    h->drop_acc_cap = 0;
-    TLB_HIP(h, hipMalloc(&h->drop_acc, need));
-    h->drop_acc_cap = need;
-  }
-  a.acc = static_cast<int64_t*>(h->drop_acc);
-  a.roots = a.acc + 7 * (size_t)total;
-  a.out = reinterpret_cast<double*>(a.roots + total);
-  a.count = total;
-  if (total > 0)
-    TLB_HIP(h, hipMemsetAsync(a.acc, 0, 7 * (size_t)total * sizeof(int64_t), h->stream));
-  hipLaunchKernelGGL(tlbk::drop_number_roots, dim3(tiles), block, 0, h->stream, a);
-  hipLaunchKernelGGL(tlbk::drop_accumulate, nodes, block, 0, h->stream, a);
-  if (total > 0)
-    hipLaunchKernelGGL(tlbk::drop_finalize, dim3((total + 255) / 256), block, 0, h->stream, a);
-  TLB_HIP(h, hipGetLastError());
-  const int64_t m = std::min<int64_t>(cap, total);
-  std::vector<double> res((size_t)m * 6);
-  if (m > 0)
-    TLB_HIP(h, hipMemcpyAsync(res.data(), a.out, res.size() * sizeof(double), hipMemcpyDeviceToHost,
-                              h->stream));
-  if (labels)
-    TLB_HIP(h, hipMemcpyAsync(labels, a.label, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost,
-                              h->stream));
-  TLB_HIP(h, hipStreamSynchronize(h->stream));
-  for (int64_t i = 0; i < m; ++i) {
-    const double* r = res.data() + 6 * i;
-    out[i].root = (int64_t)r[0];
-    out[i].size = (int64_t)r[1];
-    out[i].mass = r[2];
-    out[i].x = r[3];
-    out[i].y = r[4];
-    out[i].nu = r[5];
-  }
-  return TLB_OK;
+  DropBuffers b;
+  b.fields = h->fields;
+  b.nodes = h->drop_nodes;
+  b.tiles = h->drop_tiles;
+  b.error = h->drop_error;
+  b.tb = h->drop_tb;
+  b.acc = h->drop_acc;
+  b.acc_count = (int64_t)h->drop_acc_cap;
+  return run_droplets(h, "tlb_droplets", b, true, threshold, out, cap, count, labels);
 }
 
 int tlb_get_populations(tlb_handle* h, double* out) {
@@ -676,6 +739,9 @@ int tlb_set_bottom_temperature(tlb_handle* h, const double* t_bottom) {
   if (!h || !t_bottom) return fail(h, TLB_EINVAL, "tlb_set_bottom_temperature: NULL argument");
   const int lx = h->p.lx;
   h->tape_valid = false;
+  h->obs_t = -1;
+  h->host_tb.assign(t_bottom, t_bottom + lx);
+  h->dtdy_sum = dtdy_sum(h);
   if (is_fp64(h)) {
     TLB_HIP(h, hipMemcpyAsync(h->t_bottom, t_bottom, lx * sizeof(double), hipMemcpyHostToDevice,
                               h->stream));
@@ -703,6 +769,8 @@ int tlb_forward_taped(tlb_handle* h, int64_t nsteps, int32_t ckpt_every, double*
     return fail(h, TLB_EINVAL, "tlb_forward_taped: the adjoint needs walls at rest");
   if (h->p.ly > 65535)
     return fail(h, TLB_EINVAL, "tlb_forward_taped: ly > 65535 rows");
+  // the adjoint kernels fold x offsets of up to 2 columns by one period
+  if (h->p.lx < 3) return fail(h, TLB_EINVAL, "tlb_forward_taped: lx < 3 columns");
   h->tape_valid = false;
   const size_t sb = state_bytes(h);
   const int64_t nck = (nsteps + ckpt_every - 1) / ckpt_every;

@@ -204,3 +204,33 @@ def test_adjoint_error_paths():
         with pytest.raises(TlbError) as e:
             sim.forward_taped(5, 2)
         assert e.value.code == -1
+
+
+def test_second_taped_window_invalidates_the_first_loss():
+    """A handle holds one tape: differentiating a loss formed before a later
+    taped run on the same Simulation raises instead of returning the later
+    window's gradient; the latest loss still differentiates."""
+    w = workloads.small()
+    with make_sim(w, "fp64") as sim:
+        tb = torch.tensor(w["t_bottom"], dtype=torch.float64, requires_grad=True)
+        l1 = top_nusselt_loss(sim, tb, 6, 3)
+        l2 = top_nusselt_loss(sim, tb, 6, 3)
+        with pytest.raises(RuntimeError, match="taped again"):
+            (l1 + l2).backward()
+        tb.grad = None
+        l3 = top_nusselt_loss(sim, tb, 6, 3)
+        l3.backward()
+        assert torch.isfinite(tb.grad).all()
+
+
+def test_taped_run_rejects_fewer_than_three_columns():
+    """The adjoint folds x offsets of two columns by one period, so a taped
+    run needs lx >= 3 (checked before any adjoint kernel runs)."""
+    rng = np.random.default_rng(4)
+    ly, lx = 8, 2
+    sim = Simulation(dict(workloads.BASE_PARAMS), rng.uniform(0.2, 1.2, (ly, lx)),
+                     rng.uniform(0.2, 1.2, (ly, lx)), rng.uniform(0, 1, (ly, lx)), precision="fp64")
+    with pytest.raises(TlbError) as e:
+        sim.forward_taped(4, 2)
+    assert e.value.code == -1 and "lx < 3" in str(e.value)
+    sim.close()

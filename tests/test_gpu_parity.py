@@ -174,6 +174,71 @@ def test_fp32_posts_300_steps():
     assert max(errs["ux"], errs["uy"]) <= 3e-5, errs
 
 
+@pytest.fixture(scope="module")
+def mid_oracle():
+    """The FP64 oracle on the 1024 x 512 emulsion (seed 2): fields and
+    post-collision populations after 1000 and 2000 steps."""
+    w = workloads.mid()
+    ora = Oracle(ModelParams(**w["params"]), w["rho_a"], w["rho_b"], w["temp"],
+                 solid=w["solid"], t_bottom=w["t_bottom"])
+    out = {}
+    for t in (1000, 2000):
+        ora.step(t - ora.t)
+        out[t] = (ora.fields(), ora.post_collision(), ora.observables())
+    return w, out
+
+
+def l2_rel(a, b):
+    return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+
+
+@pytest.mark.parametrize("fused", ["0", "1"])
+def test_fp32_mid_1000_and_2000_steps(monkeypatch, mid_oracle, fused):
+    """The FP32 benchmark emulsion 1024 x 512 (seed 2, buoyant, noisy) against
+    the FP64 oracle element by element after 1000 and 2000 steps, with single
+    steps and with the fused two-step kernel. Densities, temperature and
+    populations <= 1e-5 of their largest value at both times; u^H is
+    reported as max error over max|u| and as an L2 relative error (see the
+    velocity bar below)."""
+    w, ref = mid_oracle
+    monkeypatch.setenv("TLB_STEP2", fused)
+    sim = Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+                     t_bottom=w["t_bottom"], precision="fp32")
+    assert (sim.launch_info()["fused_rows"] > 0) == (fused == "1")
+    for t in (1000, 2000):
+        sim.step(t - sim.t)
+        f_ref, p_ref, o_ref = ref[t]
+        got = sim.fields()
+        errs = field_errors(got, f_ref)
+        errs["u_l2"] = max(l2_rel(got["ux"], f_ref["ux"]), l2_rel(got["uy"], f_ref["uy"]))
+        perr = pop_errors(sim.populations(), p_ref)
+        o = sim.observables()
+        errs["nu"] = abs(o["nu"] - o_ref["nu"]) / abs(o_ref["nu"])
+        print(f"fp32 mid fused={fused} t={t}", errs, perr, flush=True)
+        assert max(errs[k] for k in FIELDS) <= 1e-5, (t, errs)
+        assert max(perr.values()) <= 1e-5, (t, perr)
+        assert max(errs["ux"], errs["uy"]) <= 3e-5, (t, errs)
+        for k in ("mass_a", "mass_b", "sum_t"):
+            assert o[k] == pytest.approx(o_ref[k], rel=1e-6), (t, k)
+
+
+def test_observables_from_the_last_step_equal_a_reevaluated_time_level(monkeypatch):
+    """tlb_step's last launch forms the observable sums; after a new bottom
+    temperature the time level is evaluated again by a separate pass. Both
+    give the oracle's observables (FP64, posts, per-column T_b, fused
+    launches before the last step)."""
+    monkeypatch.setenv("TLB_STEP2", "1")
+    c = posts_case()
+    sim, ora = run_pair(c, 41, "fp64")
+    a = sim.observables()
+    sim.set_bottom_temperature(c["t_bottom"])
+    b = sim.observables()
+    oo = ora.observables()
+    for k in ("mass_a", "mass_b", "sum_t", "ke", "nu", "nu_top"):
+        assert a[k] == pytest.approx(b[k], rel=1e-13, abs=1e-15), (k, a[k], b[k])
+        assert a[k] == pytest.approx(oo[k], rel=1e-11, abs=1e-14), (k, a[k], oo[k])
+
+
 @pytest.mark.parametrize("name", ["mid", "large"])
 def test_fp32_full_size_one_step_from_gpu_state(name):
     """Benchmark lattices in the benchmark's launch configuration: after 20
