@@ -628,16 +628,23 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
 
   double acc[kObsSums] = {0, 0, 0, 0, 0, 0};
 
-  // Densities of node (x, r) into ring slot `slot` / column `col`; the pulled
-  // populations land in f and the node's link mask in lm. Returns whether
-  // the node was pulled (fluid, inside the lattice).
-  auto density = [&](int x, const LaneOff<kMode>& L, int r, int slot, int col, C (&f)[18],
-                     uint32_t& lm) {
+  // Link mask of node (x, r), solid outside the lattice. With solid cells it
+  // is a global load, issued one row iteration before the row is pulled so
+  // that its latency does not delay the population loads that depend on it.
+  auto mask_at = [&](int x, int r) -> uint32_t {
+    return (r >= 0 && r < ly) ? link_mask<kMode>(a, x, r) : kSelfSolid;
+  };
+
+  // Densities of node (x, r) with link mask lm_in into ring slot `slot` /
+  // column `col`; the pulled populations land in f and the mask in lm.
+  // Returns whether the node was pulled (fluid, inside the lattice).
+  auto density = [&](const LaneOff<kMode>& L, int r, uint32_t lm_in, int slot, int col,
+                     C (&f)[18], uint32_t& lm) {
     C ra = a.rho_wall0, rb = a.rho_wall1, pa = psi_w0, pb = psi_w1;
     bool pulled = false;
     lm = kSelfSolid;
     if (r >= 0 && r < ly) {
-      lm = link_mask<kMode>(a, x, r);
+      lm = lm_in;
       if (!((kMode & kModeSolid) != 0 && (lm & kSelfSolid))) {
         pull_fluid<St, kMode>(a, msrc, L, r, lm, f);
         ra = sum9(f);
@@ -663,9 +670,17 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
   // row y are pulled together with the f values of row r, so each
   // iteration waits on memory once. With tau = tau_g = 1 the collision
   // returns the equilibria, so a kept row is only its moments.
+  const int dir = down ? -1 : 1;
+  const int r_first = down ? y1 + 1 : y0 - 2;
+  // prefetched masks of the next pulled row: own column, and the halo
+  // column of lanes 0..3 (each wavefront keeps its own, used in its turn)
+  uint32_t pm_own = mask_at(xw, r_first), pm_halo = lane < 4 ? mask_at(hx, r_first) : kSelfSolid;
   auto iterate = [&](int k, C (&kw)[kKept], uint32_t& lw, const C (&ku)[kKept], uint32_t lu) {
-    const int r = down ? y1 + 1 - k : y0 - 2 + k;
+    const int r = r_first + dir * k;
     const int y = down ? r + 2 : r - 2;
+    const uint32_t m_own = pm_own, m_halo = pm_halo;
+    pm_own = mask_at(xw, r + dir);
+    if (lane < 4) pm_halo = mask_at(hx, r + dir);
     const int slot = k % R;
     const bool out = k >= 4 && y >= y0 && y < y1 && own_valid;
     const bool out_fluid = out && !((kMode & kModeSolid) != 0 && (lu & kSelfSolid));
@@ -674,7 +689,7 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
     if (out_fluid) pull_thermal<St, kMode>(a, msrc, Lo, xw, y, lu, g);
     {
       C f[18];
-      const bool pulled = density(xw, Lo, r, slot, tid + 2, f, lw);
+      const bool pulled = density(Lo, r, m_own, slot, tid + 2, f, lw);
       if constexpr (kTauOne) {
         if (pulled) {
           kw[0] = sum9(f);
@@ -690,7 +705,7 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
     if (wave == k % kWaves && lane < 4) {
       C hf[18];
       uint32_t hl;
-      density(hx, Lh, r, slot, hslot, hf, hl);
+      density(Lh, r, m_halo, slot, hslot, hf, hl);
     }
     __syncthreads();
 

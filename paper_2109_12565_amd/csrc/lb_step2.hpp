@@ -248,12 +248,16 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   // the level-2 work of the phase hides the load latency), then densities
   // and psi into ring 1 and the kept rho_A, rho_B, j (tau = 1: the moments
   // are all the collision needs).
-  auto level1_pull = [&](int r, C (&f)[18], uint32_t& lw) {
-    lw = kSelfSolid;
-    if (r >= 0 && r < ly) {
-      lw = link_mask<kMode>(a, xw, r);
-      if (!(kSolid && (lw & kSelfSolid))) pull_fluid<St, kMode>(a, msrc, Lo, r, lw, f);
-    }
+  // Link mask of row r at the lane's column (solid for rows outside the
+  // lattice). With solid cells it is a global load, issued one row
+  // iteration before the row is pulled so that its latency does not delay
+  // the loads (level 1) or LDS reads (level 2) that depend on it.
+  auto mask_of = [&](int r) -> uint32_t {
+    return (r >= 0 && r < ly) ? link_mask<kMode>(a, xw, r) : kSelfSolid;
+  };
+  auto level1_pull = [&](int r, uint32_t lm, C (&f)[18], uint32_t& lw) {
+    lw = lm;
+    if (r >= 0 && r < ly && !(kSolid && (lw & kSelfSolid))) pull_fluid<St, kMode>(a, msrc, Lo, r, lw, f);
   };
   auto level1_density = [&](int r, const C (&f)[18], uint32_t lw, C (&kw)[4]) {
     C ra = a.rho_wall0, rb = a.rho_wall1, pa = psi_w0, pb = psi_w1;
@@ -306,11 +310,10 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
 
   // Level 2, phase 1: pull row r from the moment ring; densities and psi
   // into ring 2; keep rho_A, rho_B, j, T.
-  auto level2_density = [&](int r, C (&kw)[5], uint32_t& lw) {
+  auto level2_density = [&](int r, uint32_t lm, C (&kw)[5], uint32_t& lw) {
     C ra = a.rho_wall0, rb = a.rho_wall1, pa = psi_w0, pb = psi_w1;
-    lw = kSelfSolid;
+    lw = lm;
     if (r >= 0 && r < ly) {
-      lw = link_mask<kMode>(a, xw, r);
       if (!(kSolid && (lw & kSelfSolid))) {
         const int so = ring_slot<RM>(r);
         C fa[9], fb[9], g[9];
@@ -438,6 +441,7 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   // One row iteration (see the header): ra = first + dir k.
   const int dir = down ? -1 : 1;
   const int first = down ? y1 - 1 + 5 : y0 - 5;
+  uint32_t pm1 = mask_of(first), pm2 = mask_of(first - 4 * dir);
   auto in_rows = [&](int r, int lo, int hi) { return r >= lo && r < hi && r >= 0 && r < ly; };
   auto iterate = [&](int k, C (&k1w)[4], uint32_t& l1w, const C (&k1u)[4], uint32_t l1u,
                      C (&k2w)[5], uint32_t& l2w, const C (&k2u)[5], uint32_t l2u) {
@@ -447,11 +451,16 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
     const bool do_b = in_rows(rb, y0 - 3, y1 + 3) && !(kSolid && (l1u & kSelfSolid));
     const bool do_c = rc >= y0 - 2 && rc < y1 + 2;
     const bool do_d = out_lane && rd >= y0 && rd < y1;
+    // masks of rows ra and rc (loaded during the previous iteration), then
+    // the loads of the next iteration's
+    const uint32_t ma = pm1, mc = pm2;
+    pm1 = mask_of(ra + dir);
+    pm2 = mask_of(rc + dir);
     // phase 1: HBM loads first, then the LDS work of level 2
     C f[18], g[9];
-    if (do_a) level1_pull(ra, f, l1w);
+    if (do_a) level1_pull(ra, ma, f, l1w);
     if (do_b) pull_thermal<St, kMode>(a, msrc, Lo, xw, rb, l1u, g);
-    if (do_c) level2_density(rc, k2w, l2w);
+    if (do_c) level2_density(rc, mc, k2w, l2w);
     if (do_a) level1_density(ra, f, l1w, k1w);
     __syncthreads();
     // phase 2
