@@ -205,6 +205,21 @@ int tlb_row_averages(tlb_handle *h, double *u_av, double *pxy_av);
 int tlb_droplets(tlb_handle *h, double threshold, tlb_droplet *out, int64_t cap,
                  int64_t *count, int32_t *labels);
 
+/* tlb_droplets for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same results, computed in a static workspace that the library holds
+ * on each device from its first tlb_init there until the process ends
+ * (about 28 MiB), with no allocation or free of any kind. Limits: at most
+ * 2^19 lattice nodes, 8192 columns and 16384 droplets; a larger lattice is
+ * rejected with TLB_EINVAL before any work, more droplets with TLB_EINVAL
+ * after the count (which is still returned). All handles on one device
+ * share the workspace and each call overwrites it: calls that overlap in
+ * time on one device (other threads or streams) race and must be
+ * serialised by the caller. Synchronises the stream. Errors: TLB_EINVAL,
+ * TLB_EDEVICE. */
+int tlb_droplets_noalloc(tlb_handle *h, double threshold, tlb_droplet *out, int64_t cap,
+                         int64_t *count, int32_t *labels);
+
 /* Post-collision populations f*(t) of the current time (the state the next
  * step streams) as host doubles [27][ly][lx]; zero at solid nodes.
  * Synchronises the stream. */

@@ -22,8 +22,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "fp16dev": 2, "bf16dev": 3, "fix16dev": 4}
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = (
     "tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_stress",
-    "tlb_row_averages", "tlb_droplets", "tlb_get_populations", "tlb_set_bottom_temperature",
-    "tlb_forward_taped", "tlb_adjoint_step", "tlb_time", "tlb_launch_info", "tlb_destroy",
+    "tlb_row_averages", "tlb_droplets", "tlb_droplets_noalloc", "tlb_get_populations",
+    "tlb_set_bottom_temperature", "tlb_forward_taped", "tlb_adjoint_step", "tlb_time", "tlb_launch_info", "tlb_destroy",
     "tlb_last_error",
 )
 
@@ -98,8 +98,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tlb_get_populations.argtypes = [vp, dp]
     lib.tlb_get_stress.argtypes = [vp, dp, dp]
     lib.tlb_row_averages.argtypes = [vp, dp, dp]
-    lib.tlb_droplets.argtypes = [vp, ctypes.c_double, vp, ctypes.c_int64,
-                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+    for name in ("tlb_droplets", "tlb_droplets_noalloc"):
+        getattr(lib, name).argtypes = [vp, ctypes.c_double, vp, ctypes.c_int64,
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
     lib.tlb_set_bottom_temperature.argtypes = [vp, dp]
     lib.tlb_forward_taped.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, dp]
     lib.tlb_adjoint_step.argtypes = [vp, ctypes.c_int64, ctypes.c_double, dp]
@@ -110,8 +111,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tlb_last_error.argtypes = [vp]
     lib.tlb_last_error.restype = ctypes.c_char_p
     for name in ("tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_stress",
-                 "tlb_row_averages", "tlb_droplets", "tlb_get_populations",
-                 "tlb_set_bottom_temperature",
+                 "tlb_row_averages", "tlb_droplets", "tlb_droplets_noalloc",
+                 "tlb_get_populations", "tlb_set_bottom_temperature",
                  "tlb_forward_taped", "tlb_adjoint_step", "tlb_launch_info", "tlb_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -251,15 +252,16 @@ class Simulation:
         self._check(self._lib.tlb_row_averages(self._h, _dp(out["u_av"]), _dp(out["pxy_av"])))
         return out
 
-    def droplets(self, threshold: float = 0.8, labels: bool = False) -> dict:
+    def droplets(self, threshold: float = 0.8, labels: bool = False, noalloc: bool = False) -> dict:
         """Droplets of the current time: arrays root, size, mass, x, y, nu
         (numbered by smallest node index) and, if asked, the node labels
-        (ly, lx) with -1 outside droplets."""
+        (ly, lx) with -1 outside droplets. ``noalloc`` calls
+        ``tlb_droplets_noalloc`` (static device workspace, no allocation)."""
         ly, lx = self.shape
         count = ctypes.c_int64()
         lab = np.empty((ly, lx), np.int32) if labels else None
         lab_p = lab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if labels else None
-        fn = self._lib.tlb_droplets
+        fn = self._lib.tlb_droplets_noalloc if noalloc else self._lib.tlb_droplets
         arr = np.empty(self._drop_cap, DROPLET_DTYPE)
         self._check(fn(self._h, float(threshold), arr.ctypes.data, len(arr), ctypes.byref(count),
                        lab_p))

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -26,6 +27,7 @@ thread_local char g_init_error[512];
 
 struct tlb_handle {
   tlb_params p{};
+  int device = 0;                  // HIP device current at tlb_init
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int pitch = 0;
@@ -335,6 +337,53 @@ constexpr size_t kDropBytesPerDroplet =
 static_assert(sizeof(tlbk::DropRecord) == sizeof(tlb_droplet), "droplet record layout");
 static_assert(offsetof(tlb_droplet, nu) == offsetof(tlbk::DropRecord, nu), "droplet record layout");
 
+// Static workspace of tlb_droplets_noalloc: one array per device, sized for
+// lattices of up to kNoAllocNodes nodes and kNoAllocCols columns with up to
+// kNoAllocDroplets droplets. Layout (each part 256-byte aligned): fields
+// [5][n] doubles, nodes [3][n] int32, tile counts, error flag, FP64 bottom
+// temperature [lx], per-droplet accumulators.
+constexpr int64_t kNoAllocNodes = int64_t(1) << 19;
+constexpr int64_t kNoAllocCols = 8192;
+constexpr int64_t kNoAllocDroplets = int64_t(1) << 14;
+constexpr size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+constexpr size_t kNoAllocTiles = (kNoAllocNodes + tlbk::kDropTile - 1) / tlbk::kDropTile + 1;
+constexpr size_t kNoAllocOffNodes = align256(5 * kNoAllocNodes * sizeof(double));
+constexpr size_t kNoAllocOffTiles = kNoAllocOffNodes + align256(3 * kNoAllocNodes * sizeof(int32_t));
+constexpr size_t kNoAllocOffError = kNoAllocOffTiles + align256(kNoAllocTiles * sizeof(int32_t));
+constexpr size_t kNoAllocOffTb = kNoAllocOffError + 256;
+constexpr size_t kNoAllocOffAcc = kNoAllocOffTb + align256(kNoAllocCols * sizeof(double));
+constexpr size_t kNoAllocBytes = kNoAllocOffAcc + align256(kNoAllocDroplets * kDropBytesPerDroplet);
+
+}  // namespace
+
+// In host code `scratch` names a host-side stand-in; the device address of
+// each GPU's copy comes from hipGetSymbolAddress (scratch_address).
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// once per device; nullptr with the HIP error in *err on failure.
+void* scratch_address(int device, hipError_t* err) {
+  *err = hipSuccess;
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
 // Droplet detection into `b`. `grow` reallocates the per-droplet buffer of
 // the handle when the count exceeds it; without it more droplets than
 // b.acc_count is an error.
@@ -500,6 +549,16 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
       return TLB_EDEVICE;
     }
     h->own_stream = true;
+  }
+  {
+    // the device's copy of the no-allocation workspace (tlb_droplets_noalloc)
+    hipError_t e = hipGetDevice(&h->device);
+    if (e == hipSuccess) (void)scratch_address(h->device, &e);
+    if (e != hipSuccess) {
+      fail(nullptr, TLB_EDEVICE, "tlb_init: device workspace lookup: %s", hipGetErrorString(e));
+      tlb_destroy(h);
+      return TLB_EDEVICE;
+    }
   }
 
 #define INIT_HIP(expr)                                                                  \
@@ -715,6 +774,35 @@ int tlb_droplets(tlb_handle* h, double threshold, tlb_droplet* out, int64_t cap,
   b.acc = h->drop_acc;
   b.acc_count = (int64_t)h->drop_acc_cap;
   return run_droplets(h, "tlb_droplets", b, true, threshold, out, cap, count, labels);
+}
+
+int tlb_droplets_noalloc(tlb_handle* h, double threshold, tlb_droplet* out, int64_t cap,
+                         int64_t* count, int32_t* labels) {
+  if (!h || !count) return fail(h, TLB_EINVAL, "tlb_droplets_noalloc: NULL handle or count");
+  if (cap < 0 || (cap > 0 && !out))
+    return fail(h, TLB_EINVAL, "tlb_droplets_noalloc: need cap >= 0 and an output array when cap > 0");
+  if (!std::isfinite(threshold))
+    return fail(h, TLB_EINVAL, "tlb_droplets_noalloc: threshold not finite");
+  const int lx = h->p.lx, ly = h->p.ly;
+  const int64_t n = (int64_t)lx * ly;
+  if (n > kNoAllocNodes || lx > kNoAllocCols)
+    return fail(h, TLB_EINVAL,
+                "tlb_droplets_noalloc: lattice %d x %d exceeds the static workspace (at most "
+                "%lld nodes and %lld columns)",
+                lx, ly, (long long)kNoAllocNodes, (long long)kNoAllocCols);
+  hipError_t e = hipSuccess;
+  char* base = static_cast<char*>(scratch_address(h->device, &e));
+  if (!base)
+    return fail(h, TLB_EDEVICE, "tlb_droplets_noalloc: workspace address: %s", hipGetErrorString(e));
+  DropBuffers b;
+  b.fields = reinterpret_cast<double*>(base);
+  b.nodes = reinterpret_cast<int32_t*>(base + kNoAllocOffNodes);
+  b.tiles = reinterpret_cast<int32_t*>(base + kNoAllocOffTiles);
+  b.error = reinterpret_cast<int*>(base + kNoAllocOffError);
+  b.tb = reinterpret_cast<double*>(base + kNoAllocOffTb);
+  b.acc = base + kNoAllocOffAcc;
+  b.acc_count = kNoAllocDroplets;
+  return run_droplets(h, "tlb_droplets_noalloc", b, false, threshold, out, cap, count, labels);
 }
 
 int tlb_get_populations(tlb_handle* h, double* out) {
