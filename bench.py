@@ -29,8 +29,10 @@ import workloads  # noqa: E402
 METRIC = "MLUPS and % HBM roofline (FP32 vs FP16-storage); adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per node update: the 27 populations read once and
-# written once, plus one byte of solid flag when the lattice has solid cells.
-BYTES_PER_POP = {"fp64": 8, "fp32": 4, "fp16dev": 2, "bf16dev": 2, "fix16dev": 2}
+# written once (FP16 / BF16 deviations: 24 16-bit moving populations and 3
+# FP32 rest populations), plus one byte of solid flag when the lattice has
+# solid cells.
+BYTES_PER_UPDATE = {"fp64": 432, "fp32": 216, "fp16dev": 120, "bf16dev": 120, "fix16dev": 108}
 KERNEL_SOURCES = ("paper_2109_12565_amd/csrc/lb_kernels.hpp",
                   "paper_2109_12565_amd/csrc/lb_step2.hpp",
                   "paper_2109_12565_amd/csrc/launch_impl.hpp",
@@ -216,7 +218,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--config", default="large", choices=sorted(workloads.CONFIGS))
-    ap.add_argument("--precision", default="fp32", choices=sorted(BYTES_PER_POP))
+    ap.add_argument("--precision", default="fp32", choices=sorted(BYTES_PER_UPDATE))
     ap.add_argument("--cpu-steps", type=int, default=25,
                     help="oracle steps for the CPU baseline on all host threads (0 to skip)")
     ap.add_argument("--cpu-steps-1t", type=int, default=2,
@@ -330,7 +332,7 @@ def main() -> int:
     n_single = args.steps - 2 * n_fused
     nodes = w["lx"] * w["ly"]
     mlups = nodes * args.steps / (total_ms * 1e-3) / 1e6
-    bpn = 54 * BYTES_PER_POP[args.precision] + (1 if w["solid"] is not None else 0)
+    bpn = BYTES_PER_UPDATE[args.precision] + (1 if w["solid"] is not None else 0)
     kernel, updates = ("lb_step2_kernel", 2) if n_fused > 0 else ("lb_step_kernel", 1)
     if fused and n_fused == 0:  # fused kernel chosen, but too few steps to use it
         per_launch_s = single_s
@@ -353,7 +355,7 @@ def main() -> int:
             # what the counters show limits the kernel: the fused kernel does two
             # steps' arithmetic per pass over HBM and is bound by vector
             # instruction issue; the 4- and 8-byte single step by HBM
-            "limiter": "valu-issue" if n_fused > 0 or BYTES_PER_POP[args.precision] == 2
+            "limiter": "valu-issue" if n_fused > 0 or BYTES_PER_UPDATE[args.precision] <= 120
                        else "hbm"}
     traffic = measured_traffic(w["name"], args.precision, kernel)
     if traffic is not None:

@@ -115,9 +115,15 @@ void launch_step2_kernel(const Device& d, const tlbk::StepArgs<typename St::C>& 
                      dim3(kStep2Lanes), 0, d.stream, a, d.geo.strip2);
 }
 
+// Storages with a two-step kernel: FP64, FP32 and the 16-bit floating
+// deviations (FP32 rest planes); not the fixed-point one, whose exact
+// mass needs every intermediate value on its grid.
+template <class St>
+constexpr bool kHasStep2 = !St::kFix && (!St::kDev || St::kRest32);
+
 template <class St>
 void launch_step2(const Device& d, const void* src, void* dst) {
-  if constexpr (!St::kDev && !St::kFix) {
+  if constexpr (kHasStep2<St>) {
     auto a = make_args<typename St::C>(d, src, dst);
     a.rows_per_block = d.geo.rows2;
     constexpr unsigned M = tlbk::kModeStore | tlbk::kModeTauOne;
@@ -146,7 +152,7 @@ int step2_occupancy() {
 
 template <class St>
 int Launcher<St>::step2_blocks_per_cu(bool solid) {
-  if constexpr (!St::kDev && !St::kFix) {
+  if constexpr (detail::kHasStep2<St>) {
     constexpr unsigned M = tlbk::kModeStore | tlbk::kModeTauOne;
     return solid ? detail::step2_occupancy<St, M | tlbk::kModeSolid>()
                  : detail::step2_occupancy<St, M>();

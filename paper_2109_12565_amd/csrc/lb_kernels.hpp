@@ -93,19 +93,30 @@ constexpr uint32_t kFromAbove = (1u << 4) | (1u << 7) | (1u << 8);
 // works on values in stored form: the population itself (kDev = false) or
 // its deviation from the reference w_i * ref (kDev = true). grid() maps a
 // stored-form value onto the representable grid when the format is fixed
-// point (kFix), where sums of stored values are exact. Stores are
-// non-temporal: the next step reads the populations from HBM anyway.
+// point (kFix), where sums of stored values are exact; stored() is the value
+// a store keeps (grid() for fixed point, the decoded 16-bit value for the
+// floating formats). Stores are non-temporal: the next step reads the
+// populations from HBM anyway.
+//
+// kRest32: the rest populations (planes 0, 9, 18) are kept in FP32, in
+// three planes after the 27 16-bit ones, as the exact remainder of the
+// node's zeroth moment minus its eight rounded moving populations. Sums of
+// the stored values are then exact in FP32 (every 16-bit value and every
+// remainder is a multiple of 2^-24 below 1 in magnitude), so the rounding
+// of the moving populations moves no mass between nodes or components.
 template <typename T_> struct Store {
   using T = T_;
   using C = T_;
   static constexpr bool kDev = false;
   static constexpr bool kFix = false;
+  static constexpr bool kRest32 = false;
   static constexpr bool kFast = false;  // library expm1, IEEE division
   __device__ static C decode(T v) { return v; }
   __device__ static T encode(C v) { return v; }
   __device__ static C load(const T* p) { return decode(*p); }
   __device__ static void store(T* p, C v) { __builtin_nontemporal_store(encode(v), p); }
   __device__ static C grid(C v) { return v; }
+  __device__ static C stored(C v) { return v; }
 };
 
 // 16-bit floating-point deviations, converted with round-to-nearest-even.
@@ -114,10 +125,12 @@ struct StoreF16Dev {
   using C = float;
   static constexpr bool kDev = true;
   static constexpr bool kFix = false;
+  static constexpr bool kRest32 = true;
   static constexpr bool kFast = true;   // cheaper psi and reciprocals
   __device__ static C grid(C v) { return v; }
   __device__ static C decode(T v) { return (float)__builtin_bit_cast(_Float16, v); }
   __device__ static T encode(C v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+  __device__ static C stored(C v) { return decode(encode(v)); }
   __device__ static C load(const T* p) { return decode(*p); }
   __device__ static void store(T* p, C v) { __builtin_nontemporal_store(encode(v), p); }
 };
@@ -127,9 +140,11 @@ struct StoreBF16Dev {
   using C = float;
   static constexpr bool kDev = true;
   static constexpr bool kFix = false;
+  static constexpr bool kRest32 = true;
   static constexpr bool kFast = true;   // cheaper psi and reciprocals
   __device__ static C grid(C v) { return v; }
   __device__ static C decode(T v) { return __uint_as_float((uint32_t)v << 16); }
+  __device__ static C stored(C v) { return decode(encode(v)); }
   __device__ static T encode(C v) {
     uint32_t u = __float_as_uint(v);
     const bool nan = (u & 0x7fffffffu) > 0x7f800000u;
@@ -149,6 +164,7 @@ struct StoreFix16Dev {
   using C = float;
   static constexpr bool kDev = true;
   static constexpr bool kFix = true;
+  static constexpr bool kRest32 = false;
   static constexpr bool kFast = true;   // cheaper psi and reciprocals
   static constexpr float kScale = 32768.0f;
   __device__ static C decode(T v) { return (float)v * (1.0f / kScale); }
@@ -158,6 +174,7 @@ struct StoreFix16Dev {
     const float q = fminf(fmaxf(rintf(v * kScale), -32768.0f), 32767.0f);
     return q * (1.0f / kScale);
   }
+  __device__ static C stored(C v) { return grid(v); }
   __device__ static void store(T* p, C v) { __builtin_nontemporal_store(encode(v), p); }
 };
 
@@ -264,6 +281,20 @@ struct PopMem {
     if constexpr (kBuf)
       rsrc = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)(uint32_t)bytes, kBufferWord3);
   }
+  // FP32 rest planes of the kRest32 storages (byte offsets as for ld/st).
+  __device__ float ldr(O soff, O voff) const {
+    if constexpr (kBuf)
+      return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, soff, 0));
+    else
+      return *reinterpret_cast<const float*>(base + soff + voff);
+  }
+  __device__ void str(O soff, O voff, float v) const {
+    if constexpr (kBuf)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), rsrc, voff, soff,
+                                            kNonTemporal);
+    else
+      __builtin_nontemporal_store(v, reinterpret_cast<float*>(base + soff + voff));
+  }
   __device__ C ld(O soff, O voff) const {
     if constexpr (kBuf) {
       if constexpr (sizeof(T) == 8)
@@ -293,11 +324,17 @@ struct PopMem {
   }
 };
 
+// Bytes of a population buffer in units of one stored plane: 27 planes, and
+// for kRest32 three FP32 rest planes of twice the size after them.
+template <class St>
+constexpr int kPlaneUnits = St::kRest32 ? 27 + 3 * (4 / (int)sizeof(typename St::T)) : 27;
+
 // Per-lane byte offsets of one column x within a row (x itself and its
-// periodic neighbours x - 1 and x + 1) and the uniform plane and row sizes.
+// periodic neighbours x - 1 and x + 1) and the uniform plane and row sizes;
+// v0r is the column's offset in an FP32 rest plane (kRest32).
 template <unsigned kMode>
 struct LaneOff {
-  Off<kMode> v0, vm, vp;
+  Off<kMode> v0, vm, vp, v0r;
   Off<kMode> plane_b, row_b;
 };
 
@@ -309,9 +346,20 @@ __device__ inline LaneOff<kMode> lane_off(int x, int lx, Off<kMode> plane_b, Off
   L.v0 = (O)x * E;
   L.vm = (O)(x == 0 ? lx - 1 : x - 1) * E;
   L.vp = (O)(x == lx - 1 ? 0 : x + 1) * E;
+  L.v0r = (O)x * 4;
   L.plane_b = plane_b;
   L.row_b = row_b;
   return L;
+}
+
+// Uniform byte offset of row r of the FP32 rest plane of set k (0 f_A,
+// 1 f_B, 2 g) for the kRest32 storages: after the 27 16-bit planes, each
+// rest plane and row twice the size of a 16-bit one.
+template <class St, unsigned kMode>
+__device__ inline Off<kMode> rest_off(const LaneOff<kMode>& L, int k, int r) {
+  using O = Off<kMode>;
+  constexpr O kRatio = 4 / sizeof(typename St::T);
+  return (O)27 * L.plane_b + (O)k * kRatio * L.plane_b + (O)r * kRatio * L.row_b;
 }
 
 // Offsets of the value pulled for direction I into row r, in the block of
@@ -418,8 +466,13 @@ __device__ inline void moving_wall_fluid(const StepArgs<C>& a, const PopMem<St, 
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
     const O s = (O)j * L.plane_b + (O)r * L.row_b;
-    ra += m.ld(s, L.v0);
-    rb += m.ld(s + p9, L.v0);
+    if (St::kRest32 && j == 0) {
+      ra += m.ldr(rest_off<St>(L, 0, r), L.v0r);
+      rb += m.ldr(rest_off<St>(L, 1, r), L.v0r);
+    } else {
+      ra += m.ld(s, L.v0);
+      rb += m.ld(s + p9, L.v0);
+    }
   }
   if constexpr (St::kDev) {
     ra += a.ref_a;
@@ -470,8 +523,13 @@ __device__ inline void pull_fluid(const StepArgs<C>& a, const PopMem<St, kMode>&
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const O s = (O)i * L.plane_b + (O)r * L.row_b;
-      f[i] = m.ld(s, L.v0);
-      f[i + 9] = m.ld(s + p9, L.v0);
+      if (St::kRest32 && i == 0) {
+        f[0] = m.ldr(rest_off<St>(L, 0, r), L.v0r);
+        f[9] = m.ldr(rest_off<St>(L, 1, r), L.v0r);
+      } else {
+        f[i] = m.ld(s, L.v0);
+        f[i + 9] = m.ld(s + p9, L.v0);
+      }
     }
     return;
   }
@@ -481,15 +539,22 @@ __device__ inline void pull_fluid(const StepArgs<C>& a, const PopMem<St, kMode>&
     f[I] = m.ld(o.s, o.v);                                                     \
     f[I + 9] = m.ld(o.s + p9, o.v);                                            \
   }
+  // the rest populations never move or bounce
+  if constexpr (St::kRest32) {
+    f[0] = m.ldr(rest_off<St>(L, 0, r), L.v0r);
+    f[9] = m.ldr(rest_off<St>(L, 1, r), L.v0r);
+  } else {
+    TLB_PULL_F(0, false)
+  }
   if (any_link<kMode>(lm)) {
-    TLB_PULL_F(0, true) TLB_PULL_F(1, true) TLB_PULL_F(2, true) TLB_PULL_F(3, true)
+    TLB_PULL_F(1, true) TLB_PULL_F(2, true) TLB_PULL_F(3, true)
     TLB_PULL_F(4, true) TLB_PULL_F(5, true) TLB_PULL_F(6, true) TLB_PULL_F(7, true)
     TLB_PULL_F(8, true)
     if constexpr ((kMode & kModeMoving) != 0) {
       if (r == 0 || r == a.ly - 1) moving_wall_fluid(a, m, L, r, f);
     }
   } else {
-    TLB_PULL_F(0, false) TLB_PULL_F(1, false) TLB_PULL_F(2, false) TLB_PULL_F(3, false)
+    TLB_PULL_F(1, false) TLB_PULL_F(2, false) TLB_PULL_F(3, false)
     TLB_PULL_F(4, false) TLB_PULL_F(5, false) TLB_PULL_F(6, false) TLB_PULL_F(7, false)
     TLB_PULL_F(8, false)
   }
@@ -507,7 +572,9 @@ __device__ inline void pull_thermal(const StepArgs<C>& a, const PopMem<St, kMode
   const O p18 = L.plane_b * 18;
   if constexpr ((kMode & kModeInit) != 0) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) g[i] = m.ld(p18 + (O)i * L.plane_b + (O)r * L.row_b, L.v0);
+    for (int i = 0; i < 9; ++i)
+      g[i] = (St::kRest32 && i == 0) ? m.ldr(rest_off<St>(L, 2, r), L.v0r)
+                                     : m.ld(p18 + (O)i * L.plane_b + (O)r * L.row_b, L.v0);
     return;
   }
 #define TLB_PULL_G(I, B)                                                          \
@@ -524,12 +591,17 @@ __device__ inline void pull_thermal(const StepArgs<C>& a, const PopMem<St, kMode
     }                                                                             \
     g[I] = v;                                                                     \
   }
+  if constexpr (St::kRest32) {
+    g[0] = m.ldr(rest_off<St>(L, 2, r), L.v0r);
+  } else {
+    TLB_PULL_G(0, false)
+  }
   if (any_link<kMode>(lm)) {
-    TLB_PULL_G(0, true) TLB_PULL_G(1, true) TLB_PULL_G(2, true) TLB_PULL_G(3, true)
+    TLB_PULL_G(1, true) TLB_PULL_G(2, true) TLB_PULL_G(3, true)
     TLB_PULL_G(4, true) TLB_PULL_G(5, true) TLB_PULL_G(6, true) TLB_PULL_G(7, true)
     TLB_PULL_G(8, true)
   } else {
-    TLB_PULL_G(0, false) TLB_PULL_G(1, false) TLB_PULL_G(2, false) TLB_PULL_G(3, false)
+    TLB_PULL_G(1, false) TLB_PULL_G(2, false) TLB_PULL_G(3, false)
     TLB_PULL_G(4, false) TLB_PULL_G(5, false) TLB_PULL_G(6, false) TLB_PULL_G(7, false)
     TLB_PULL_G(8, false)
   }
@@ -603,8 +675,8 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
 #endif
   const O row_b = (O)a.pitch * sizeof(T);
   const O plane_b = (O)a.pop_stride * sizeof(T);
-  const PopMem<St, kMode> msrc(a.src, (uint64_t)plane_b * 27);
-  const PopMem<St, kMode> mdst(a.dst, (uint64_t)plane_b * 27);
+  const PopMem<St, kMode> msrc(a.src, (uint64_t)plane_b * kPlaneUnits<St>);
+  const PopMem<St, kMode> mdst(a.dst, (uint64_t)plane_b * kPlaneUnits<St>);
 
   // own column (idle threads of a ragged strip still fill their ring slot,
   // with a wrapped column, so the halo of the last valid column is right)
@@ -713,7 +785,10 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
     if (!out_fluid) {
       if constexpr ((kMode & kModeStore) != 0) {
 #pragma unroll
-        for (int p = 0; p < 27; ++p) mdst.st((O)p * plane_b + yrow, Lo.v0, C(0));
+        for (int p = 0; p < 27; ++p) {
+          if (St::kRest32 && p % 9 == 0) mdst.str(rest_off<St>(Lo, p / 9, y < 0 ? 0 : y), Lo.v0r, 0.0f);
+          else mdst.st((O)p * plane_b + yrow, Lo.v0, C(0));
+        }
       }
       if constexpr ((kMode & kModeFields) != 0) {
         const size_t nn = (size_t)lx * ly, q = (size_t)y * lx + xo;
@@ -873,13 +948,13 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
       qgI += kg * (g[I] - egI);                                                        \
       qgJ += kg * (g[J] - egJ);                                                        \
     }                                                                                  \
-    qaI = St::grid(qaI);                                                               \
-    qaJ = St::grid(qaJ);                                                               \
-    qbI = St::grid(qbI);                                                               \
-    qbJ = St::grid(qbJ);                                                               \
-    qgI = St::grid(qgI);                                                               \
-    qgJ = St::grid(qgJ);                                                               \
-    if constexpr (St::kFix) {                                                          \
+    qaI = St::stored(qaI);                                                             \
+    qaJ = St::stored(qaJ);                                                             \
+    qbI = St::stored(qbI);                                                             \
+    qbJ = St::stored(qbJ);                                                             \
+    qgI = St::stored(qgI);                                                             \
+    qgJ = St::stored(qgJ);                                                             \
+    if constexpr (St::kFix || St::kRest32) {                                           \
       sa += qaI + qaJ;                                                                 \
       sb += qbI + qbJ;                                                                 \
       sg += qgI + qgJ;                                                                 \
@@ -903,6 +978,12 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
         mdst.st(yrow, Lo.v0, St::grid(Da - sa));
         mdst.st(yrow + p9, Lo.v0, St::grid(Db - sb));
         mdst.st(yrow + p18, Lo.v0, St::grid(Dt - sg));
+      } else if constexpr (St::kRest32) {
+        // FP32 remainders of the rounded moving populations (any tau: the
+        // BGK rest value is the zeroth moment minus the other eight)
+        mdst.str(rest_off<St>(Lo, 0, y), Lo.v0r, Da - sa);
+        mdst.str(rest_off<St>(Lo, 1, y), Lo.v0r, Db - sb);
+        mdst.str(rest_off<St>(Lo, 2, y), Lo.v0r, Dt - sg);
       } else if constexpr (kTauOne) {
         mdst.st(yrow, Lo.v0, Da - sa);
         mdst.st(yrow + p9, Lo.v0, Db - sb);
@@ -1041,17 +1122,22 @@ __global__ __launch_bounds__(256) void lb_init_equilibrium(
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
       const C v = dens[s] * shape;
-      const C d = St::grid(v - w_dir<C>(i) * ref[s]);   // stored form
-      sum[s] += St::kFix ? d : v;
+      const C d = St::stored(v - w_dir<C>(i) * ref[s]);   // stored form
+      sum[s] += (St::kFix || St::kRest32) ? d : v;
       St::store(buf + (long long)(i + 9 * s) * pop_stride + off, is_solid ? C(0) : d);
     }
   }
   // rest population: zeroth moment minus the other eight (exact mass)
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
-    const C d = St::kFix ? St::grid(St::grid(dens[s] - ref[s]) - sum[s])
-                         : (dens[s] - sum[s]) - w_dir<C>(0) * ref[s];
-    St::store(buf + (long long)(9 * s) * pop_stride + off, is_solid ? C(0) : d);
+    if constexpr (St::kRest32) {
+      float* rest = reinterpret_cast<float*>(buf + 27 * pop_stride) + (long long)s * pop_stride;
+      __builtin_nontemporal_store(is_solid ? 0.0f : (dens[s] - ref[s]) - sum[s], rest + off);
+    } else {
+      const C d = St::kFix ? St::grid(St::grid(dens[s] - ref[s]) - sum[s])
+                           : (dens[s] - sum[s]) - w_dir<C>(0) * ref[s];
+      St::store(buf + (long long)(9 * s) * pop_stride + off, is_solid ? C(0) : d);
+    }
   }
 }
 
@@ -1066,7 +1152,12 @@ __global__ __launch_bounds__(256) void lb_export_populations(
   const int y = blockIdx.y;
   const int p = blockIdx.z;
   if (x >= lx) return;
-  double v = (double)St::load(buf + p * pop_stride + (long long)y * pitch + x);
+  const long long off = (long long)y * pitch + x;
+  double v;
+  if (St::kRest32 && p % 9 == 0)
+    v = (double)(reinterpret_cast<const float*>(buf + 27 * pop_stride) + (long long)(p / 9) * pop_stride)[off];
+  else
+    v = (double)St::load(buf + p * pop_stride + off);
   if constexpr (St::kDev)
     v += w_dir<double>(p % 9) * (double)(p < 9 ? ref_a : (p < 18 ? ref_b : ref_t));
   if (solid[(size_t)y * lx + x] != 0) v = 0.0;

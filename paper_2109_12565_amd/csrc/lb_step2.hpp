@@ -1,5 +1,7 @@
 // Fused two-step update f*(t) -> f*(t+2) for tau = tau_g = 1 (arXiv:2109.12565,
-// Sec. 2), FP32 and FP64 storage, flat walls at rest or moving along x.
+// Sec. 2): FP64, FP32 and the 16-bit floating deviation storages (their
+// intermediate level stays in FP32, so a fused launch rounds to 16 bits once
+// per two steps), solid cells allowed, flat walls at rest or moving along x.
 //
 // At tau = tau_g = 1 the BGK collision (Eqs. (2), (16)) returns the
 // equilibria (Eqs. (3), (18)), so the post-collision populations of a node
@@ -196,7 +198,8 @@ template <class St, int BT, unsigned kMode>
 __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a, int strip_w) {
   using C = typename St::C;
   using O = Off<kMode>;
-  static_assert(!St::kDev && !St::kFix, "two-step kernel: FP32 / FP64 storage only");
+  static_assert(!St::kFix && (!St::kDev || St::kRest32),
+                "two-step kernel: FP64, FP32, or 16-bit floating deviations with FP32 rest planes");
   static_assert((kMode & kModeTauOne) != 0 && (kMode & kModeStore) != 0, "tau = 1 store pass");
   static_assert((kMode & (kModeWide | kModeInit | kModeObserve | kModeFields)) == 0,
                 "32-bit offsets, no observables");
@@ -226,10 +229,11 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   const int y1 = min(y0 + a.rows_per_block, ly);
   const bool down = (chunk & 1) != 0;
 
-  const O row_b = (O)a.pitch * sizeof(C);
-  const O plane_b = (O)a.pop_stride * sizeof(C);
-  const PopMem<St, kMode> msrc(a.src, (uint64_t)plane_b * 27);
-  const PopMem<St, kMode> mdst(a.dst, (uint64_t)plane_b * 27);
+  using T = typename St::T;
+  const O row_b = (O)a.pitch * sizeof(T);
+  const O plane_b = (O)a.pop_stride * sizeof(T);
+  const PopMem<St, kMode> msrc(a.src, (uint64_t)plane_b * kPlaneUnits<St>);
+  const PopMem<St, kMode> mdst(a.dst, (uint64_t)plane_b * kPlaneUnits<St>);
 
   // lane column (periodic); lanes kH .. kH + strip_w - 1 inside the lattice
   // store, the others compute halo columns only
@@ -262,8 +266,14 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   auto level1_density = [&](int r, const C (&f)[18], uint32_t lw, C (&kw)[4]) {
     C ra = a.rho_wall0, rb = a.rho_wall1, pa = psi_w0, pb = psi_w1;
     if (r >= 0 && r < ly && !(kSolid && (lw & kSelfSolid))) {
+      // densities in full (the deviation storages add their references; the
+      // references carry no momentum)
       kw[0] = sum9(f);
       kw[1] = sum9(f + 9);
+      if constexpr (St::kDev) {
+        kw[0] += a.ref_a;
+        kw[1] += a.ref_b;
+      }
       kw[2] = momentum_x(f, f + 9);
       kw[3] = momentum_y(f, f + 9);
       ra = kw[0];
@@ -283,7 +293,8 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   auto level1_moments = [&](int r, const C (&ku)[4], const C (&g)[9]) {
     const C Da = ku[0], Db = ku[1], jx = ku[2], jy = ku[3];
     const C ra = Da, rb = Db;
-    const C Dt = sum9(g);
+    C Dt = sum9(g);
+    if constexpr (St::kDev) Dt += a.ref_t;
     const C temp = Dt;
     int rs[5];
 #pragma unroll
@@ -386,7 +397,10 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
     const O yrow = (O)r * row_b;
     if (kSolid && (lu & kSelfSolid)) {
 #pragma unroll
-      for (int p = 0; p < 27; ++p) mdst.st((O)p * plane_b + yrow, Lo.v0, C(0));
+      for (int p = 0; p < 27; ++p) {
+        if (St::kRest32 && p % 9 == 0) mdst.str(rest_off<St>(Lo, p / 9, r), Lo.v0r, 0.0f);
+        else mdst.st((O)p * plane_b + yrow, Lo.v0, C(0));
+      }
       return;
     }
     const C Da = ku[0], Db = ku[1], jx = ku[2], jy = ku[3], Dt = ku[4];
@@ -417,9 +431,15 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
     eq_even_odd<I>(ra, uax, uay, ua2, Sa, Dla);             \
     eq_even_odd<I>(rb, ubx, uby, ub2, Sb, Dlb);             \
     eq_even_odd<I>(temp, hx, hy, uh2, Sg, Dlg);             \
-    const C eaI = Sa + Dla, eaJ = Sa - Dla;                 \
-    const C ebI = Sb + Dlb, ebJ = Sb - Dlb;                 \
-    const C egI = Sg + Dlg, egJ = Sg - Dlg;                 \
+    if constexpr (St::kDev) {                               \
+      constexpr C w = w_dir<C>(I);                          \
+      Sa -= w * a.ref_a;                                    \
+      Sb -= w * a.ref_b;                                    \
+      Sg -= w * a.ref_t;                                    \
+    }                                                       \
+    const C eaI = St::stored(Sa + Dla), eaJ = St::stored(Sa - Dla); \
+    const C ebI = St::stored(Sb + Dlb), ebJ = St::stored(Sb - Dlb); \
+    const C egI = St::stored(Sg + Dlg), egJ = St::stored(Sg - Dlg); \
     sa += eaI + eaJ;                                        \
     sb += ebI + ebJ;                                        \
     sg += egI + egJ;                                        \
@@ -433,9 +453,16 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   }
     TLB_PAIR2(1) TLB_PAIR2(2) TLB_PAIR2(5) TLB_PAIR2(6)
 #undef TLB_PAIR2
-    mdst.st(yrow, Lo.v0, Da - sa);
-    mdst.st(yrow + p9, Lo.v0, Db - sb);
-    mdst.st(yrow + p18, Lo.v0, Dt - sg);
+    if constexpr (St::kRest32) {
+      // FP32 remainders of the rounded moving deviations
+      mdst.str(rest_off<St>(Lo, 0, r), Lo.v0r, (Da - a.ref_a) - sa);
+      mdst.str(rest_off<St>(Lo, 1, r), Lo.v0r, (Db - a.ref_b) - sb);
+      mdst.str(rest_off<St>(Lo, 2, r), Lo.v0r, (Dt - a.ref_t) - sg);
+    } else {
+      mdst.st(yrow, Lo.v0, Da - sa);
+      mdst.st(yrow + p9, Lo.v0, Db - sb);
+      mdst.st(yrow + p18, Lo.v0, Dt - sg);
+    }
   };
 
   // One row iteration (see the header): ra = first + dir k.

@@ -97,6 +97,12 @@ size_t storage_bytes(int precision) {
   return precision == TLB_FP64 ? sizeof(double) : (precision == TLB_FP32 ? sizeof(float) : 2);
 }
 
+// Size of a population buffer in stored planes: 27, plus for the 16-bit
+// floating deviations three FP32 rest planes (two 16-bit planes each).
+size_t buffer_planes(int precision) {
+  return precision == TLB_FP16_DEV || precision == TLB_BF16_DEV ? 27 + 3 * 2 : 27;
+}
+
 // Call f with a value of the storage policy type of the handle's precision.
 template <class F>
 void with_storage(int precision, F&& f) {
@@ -150,14 +156,13 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
   l.rows = (int)(rows < ly ? rows : ly);
   l.grid = dim3((unsigned)strips, (unsigned)((ly + l.rows - 1) / l.rows), 1);
 
-  // Fused two-step kernel: tau = tau_g = 1, FP32 or FP64 storage, 32-bit
+  // Fused two-step kernel: tau = tau_g = 1, any storage but fixed point, 32-bit
   // offsets. Its strips overlap by kStep2Halo columns and its
   // chunks recompute 5 rows of the first step on each side, so it pays
   // where the chunks can be tall and the grid still fills every CU once:
   // chunks of at least 24 rows, one block per resident slot. TLB_STEP2=1
   // selects it wherever it applies (FP64 included), TLB_STEP2=0 never.
-  const bool eligible = tau_one && !l.wide &&
-                        (p.precision == TLB_FP32 || p.precision == TLB_FP64);
+  const bool eligible = tau_one && !l.wide && p.precision != TLB_FIX16_DEV;
   const char* step2_env = std::getenv("TLB_STEP2");
   const int step2_mode = step2_env ? std::atoi(step2_env) : -1;
   if (eligible && step2_mode != 0) {
@@ -264,7 +269,9 @@ double dtdy_sum(const tlb_handle* h) {
   return sum;
 }
 
-size_t state_bytes(const tlb_handle* h) { return (size_t)27 * h->pop_stride * h->elem; }
+size_t state_bytes(const tlb_handle* h) {
+  return buffer_planes(h->p.precision) * h->pop_stride * h->elem;
+}
 
 // Device buffer of at least `bytes`, reallocated when too small.
 int ensure_buffer(tlb_handle* h, void** ptr, size_t* cap, size_t bytes, const char* what) {
@@ -532,7 +539,8 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
   // the pulled rows (TLB_GENERAL_PATH=1 forces the general path, for tests)
   const char* general = std::getenv("TLB_GENERAL_PATH");
   h->tau_one = p->tau == 1.0 && p->tau_g == 1.0 && !(general && std::atoi(general) == 1);
-  h->launch = choose_launch(*p, (size_t)27 * h->pop_stride * h->elem, h->has_solid, h->tau_one);
+  h->launch = choose_launch(*p, buffer_planes(p->precision) * h->pop_stride * h->elem,
+                            h->has_solid, h->tau_one);
 
   int rc = TLB_OK;
   auto cleanup_fail = [&](int code) {
@@ -571,7 +579,7 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
     }                                                                                   \
   } while (0)
 
-  const size_t buf_bytes = (size_t)27 * h->pop_stride * h->elem;
+  const size_t buf_bytes = state_bytes(h);
   INIT_HIP(hipMalloc(&h->buf[0], buf_bytes));
   INIT_HIP(hipMalloc(&h->buf[1], buf_bytes));
   INIT_HIP(hipMemsetAsync(h->buf[0], 0, buf_bytes, h->stream));

@@ -1,5 +1,6 @@
-"""The fused two-step kernel (tau = tau_g = 1, FP32 / FP64, flat walls at
-rest or moving) against runs made of single steps and against the oracle.
+"""The fused two-step kernel (tau = tau_g = 1; FP64, FP32 and the FP16 / BF16
+deviation storages; posts; flat walls at rest or moving) against runs made of
+single steps and against the oracle.
 
 The fused kernel keeps the intermediate time level as moments per node
 (density, velocity and u^2 of each field) and rebuilds its populations with the same expressions the single step
@@ -98,11 +99,56 @@ def test_fused_matches_single_steps(monkeypatch, precision, name, rows):
 
 def test_fused_kernel_is_not_used_where_it_does_not_apply(monkeypatch):
     w = workloads.small()
-    for precision in ("fp16dev", "bf16dev", "fix16dev"):
-        _, info = make(w, precision, monkeypatch, True)
-        assert info["fused_rows"] == 0, precision
-    _, info = make(w, "fp32", monkeypatch, True, tau=0.8)
+    _, info = make(w, "fix16dev", monkeypatch, True)
     assert info["fused_rows"] == 0
+    for precision in ("fp32", "fp16dev"):
+        _, info = make(w, precision, monkeypatch, True, tau=0.8)
+        assert info["fused_rows"] == 0, precision
+
+
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+HALF_ULP_BITS = {"fp16dev": (10, -14), "bf16dev": (7, -126)}
+
+
+@pytest.mark.parametrize("precision", sorted(HALF_ULP_BITS))
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("rows", [None, 7])
+def test_dev16_fused_launch_from_gpu_state(monkeypatch, precision, name, rows):
+    """16-bit deviation storage, fused kernel forced on: from the GPU's own
+    state after 4 steps (decoded exactly), tlb_step(3) runs one fused launch
+    and one single step; the oracle takes 3 FP64 steps from the same state.
+    The densities and temperature of t + 3 are moments of populations that
+    were rounded to 16 bits once, at the end of the fused launch (its
+    intermediate level stays in FP32): each node's zeroth moment at t + 3
+    sums 8 rounded moving values pulled from its neighbours and loses the 8
+    roundings of its own (through the exact rest remainder), so the error
+    is at most 16 half ulps of the largest moving deviation, plus FP32
+    arithmetic."""
+    case = CASES[name]()
+    sim, info = make(case, precision, monkeypatch, True, rows)
+    assert info["fused_rows"] > 0
+    sim.step(4)
+    state = sim.populations()
+    sim.step(3)
+    ora = Oracle(ModelParams(**case["params"]), case["rho_a"], case["rho_b"], case["temp"],
+                 solid=case.get("solid"), t_bottom=case.get("t_bottom"))
+    ora.load_post_collision(state, 5).step(2)   # streams f*(4): the state of time 5
+    got, ref = sim.fields(), ora.fields()
+    pr = sim.params
+    solid = case.get("solid")
+    fluid = np.ones(state.shape[1:], bool) if solid is None else solid == 0
+    mant, emin = HALF_ULP_BITS[precision]
+    post = ora.post_collision()
+    for k0, key, refv in ((0, "rho_a", pr.rho_ref[0]), (9, "rho_b", pr.rho_ref[1]),
+                          (18, "temp", pr.t_ref)):
+        # largest moving deviation before and after the launch
+        refs = (W9[1:] * refv)[:, None, None]
+        big = max(np.abs(p[k0 + 1:k0 + 9] - refs)[:, fluid].max() for p in (state, post))
+        hu = 0.5 * 2.0 ** (np.floor(np.log2(max(big, 2.0 ** emin))) - mant)
+        err = np.abs(got[key] - ref[key])[fluid].max()
+        bound = 16 * hu + 1e-5 * np.abs(ref[key]).max()
+        print(precision, name, rows, key, "err", err, "bound", bound, flush=True)
+        assert err <= bound, (key, err, bound)
 
 
 def test_fp64_fused_matches_oracle(monkeypatch):
