@@ -70,11 +70,26 @@ enum tlb_precision {
   TLB_FIX16_DEV = 4   /* 16-bit fixed-point deviations */
 };
 
-/* Model constants (Sec. 2; values of Appendix A in parentheses). */
+/* Kernel selection bits of tlb_params.launch_flags (0 for normal use; for
+ * tests that compare the kernel variants and for tuning). */
+enum tlb_launch_flags {
+  TLB_LAUNCH_GENERAL_PATH = 1,  /* no tau = tau_g = 1 specialisation */
+  TLB_LAUNCH_WIDE_OFFSETS = 2   /* 64-bit offsets even below 4 GiB */
+};
+
+/* tlb_params.fused: use of the fused two-step kernel (see tlb_step). */
+enum tlb_fused_mode {
+  TLB_FUSED_AUTO = 0,    /* where it pays (chunks of >= 6 rows, 2 blocks per CU) */
+  TLB_FUSED_NEVER = 1,
+  TLB_FUSED_ALWAYS = 2   /* wherever it applies */
+};
+
+/* Model constants (Sec. 2; values of Appendix A in parentheses) and launch
+ * choices (zero: chosen by the library). */
 typedef struct tlb_params {
   int32_t lx, ly;        /* lattice size: lx >= 1, ly >= 1 */
   int32_t precision;     /* enum tlb_precision */
-  int32_t reserved;      /* set to 0 */
+  int32_t launch_flags;  /* enum tlb_launch_flags bits, normally 0 */
   double tau;            /* fluid relaxation time, > 1/2 (1.0) */
   double tau_g;          /* thermal relaxation time, > 1/2 (1.0) */
   double rho0;           /* pseudopotential reference density, > 0 (0.83) */
@@ -95,6 +110,12 @@ typedef struct tlb_params {
                             boundary node's own density) and g against
                             2 w_i T_w (1 + 4.5 (c_i.u_w)^2 - 1.5 u_w^2);
                             solid cells inside the lattice do not move */
+  int32_t fused;         /* enum tlb_fused_mode */
+  int32_t fused_rows;    /* rows per chunk of the fused kernel (1..4096), 0: chosen */
+  int32_t fused_strip;   /* at most this many stored columns per fused strip
+                            (1..245), 0: chosen */
+  int32_t rows;          /* rows per chunk of the single-step kernel (1..4096),
+                            0: chosen */
 } tlb_params;
 
 /* Observables at time `step` (Sec. 3.1, Sec. 3.3.2 Eq. (24)); sums and means

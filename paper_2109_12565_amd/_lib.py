@@ -37,7 +37,7 @@ class TlbError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [
         ("lx", ctypes.c_int32), ("ly", ctypes.c_int32),
-        ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("launch_flags", ctypes.c_int32),
         ("tau", ctypes.c_double), ("tau_g", ctypes.c_double),
         ("rho0", ctypes.c_double), ("g12", ctypes.c_double),
         ("g_a", ctypes.c_double * 2), ("g_r", ctypes.c_double * 2),
@@ -45,7 +45,14 @@ class Params(ctypes.Structure):
         ("rho_wall", ctypes.c_double * 2), ("dt_nominal", ctypes.c_double),
         ("rho_ref", ctypes.c_double * 2), ("t_ref", ctypes.c_double),
         ("u_wall", ctypes.c_double * 2),
+        ("fused", ctypes.c_int32), ("fused_rows", ctypes.c_int32),
+        ("fused_strip", ctypes.c_int32), ("rows", ctypes.c_int32),
     ]
+
+
+TLB_LAUNCH_GENERAL_PATH, TLB_LAUNCH_WIDE_OFFSETS = 1, 2
+FUSED_MODES = {"auto": 0, "never": 1, "always": 2}
+LAUNCH_KEYS = ("fused", "fused_rows", "fused_strip", "rows", "general_path", "wide_offsets")
 
 
 class Obs(ctypes.Structure):
@@ -153,10 +160,15 @@ class Simulation:
     x-velocities of the bottom and top walls, by default at rest).
     Field arrays are (ly, lx) with x fastest. By default the work runs on
     torch's current stream.
+
+    ``launch`` (optional) sets the launch choices of ``tlb_params``: ``fused``
+    ("auto", "never", "always"), ``fused_rows``, ``fused_strip``, ``rows``
+    (0 or absent: chosen by the library), and the kernel-selection flags
+    ``general_path`` and ``wide_offsets``.
     """
 
     def __init__(self, params: dict, rho_a, rho_b, temp, *, solid=None, t_bottom=None,
-                 ux0=None, uy0=None, precision: str = "fp32", stream="torch"):
+                 ux0=None, uy0=None, precision: str = "fp32", stream="torch", launch=None):
         self._lib = load_library()
         self._h = ctypes.c_void_p()
         rho_a = np.ascontiguousarray(np.asarray(rho_a, dtype=np.float64))
@@ -180,8 +192,18 @@ class Simulation:
         t_bottom = np.ascontiguousarray(np.broadcast_to(np.asarray(t_bottom, np.float64), (lx,)))
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        launch = dict(launch or {})
+        unknown = set(launch) - set(LAUNCH_KEYS)
+        if unknown:
+            raise ValueError(f"unknown launch options {sorted(unknown)}")
         p = Params()
-        p.lx, p.ly, p.precision, p.reserved = lx, ly, PRECISIONS[precision], 0
+        p.lx, p.ly, p.precision = lx, ly, PRECISIONS[precision]
+        p.launch_flags = ((TLB_LAUNCH_GENERAL_PATH if launch.get("general_path") else 0) |
+                          (TLB_LAUNCH_WIDE_OFFSETS if launch.get("wide_offsets") else 0))
+        p.fused = FUSED_MODES[launch.get("fused", "auto")]
+        p.fused_rows = int(launch.get("fused_rows", 0))
+        p.fused_strip = int(launch.get("fused_strip", 0))
+        p.rows = int(launch.get("rows", 0))
         p.tau, p.tau_g = params["tau"], params["tau_g"]
         p.rho0, p.g12 = params["rho0"], params["g12"]
         p.g_a[0], p.g_a[1] = params["g_a"]

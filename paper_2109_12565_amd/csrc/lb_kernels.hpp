@@ -631,11 +631,7 @@ __device__ inline C solid_temperature(const StepArgs<C>& a, int x, int y) {
 
 // ---------------------------------------------------------------- kernel
 template <class St, int BX, unsigned kMode>
-__global__ __launch_bounds__(BX)
-#if defined(TLB_WAVES_PER_EU)
-__attribute__((amdgpu_waves_per_eu(TLB_WAVES_PER_EU)))
-#endif
-void lb_step_kernel(StepArgs<typename St::C> a) {
+__global__ __launch_bounds__(BX) void lb_step_kernel(StepArgs<typename St::C> a) {
   using C = typename St::C;
   using T = typename St::T;
   using O = Off<kMode>;
@@ -657,22 +653,14 @@ void lb_step_kernel(StepArgs<typename St::C> a) {
   const int nbx = gridDim.x;
   const int ntiles = gridDim.x * gridDim.y;
   const int lin = blockIdx.y * nbx + blockIdx.x;
-#if defined(TLB_NO_XCD_REMAP)
-  const int tile = lin;
-#else
   constexpr int kXcds = 8;
   const int xcd = lin % kXcds;
   const int tile = xcd * (ntiles / kXcds) + min(xcd, ntiles % kXcds) + lin / kXcds;
-#endif
   const int chunk = tile / nbx;
   const int x0 = (tile - chunk * nbx) * BX;
   const int y0 = chunk * a.rows_per_block;
   const int y1 = min(y0 + a.rows_per_block, ly);
-#if defined(TLB_NO_ZIGZAG)
-  const bool down = false;
-#else
   const bool down = (chunk & 1) != 0;
-#endif
   const O row_b = (O)a.pitch * sizeof(T);
   const O plane_b = (O)a.pop_stride * sizeof(T);
   const PopMem<St, kMode> msrc(a.src, (uint64_t)plane_b * kPlaneUnits<St>);

@@ -122,15 +122,15 @@ void with_storage(int precision, F&& f) {
 // uneven count leaves some CUs with one block more than others. Storages of
 // 4 bytes and more are bandwidth bound and prefer fewer, taller chunks (less
 // halo re-read): 16 wavefronts per CU (4 blocks of 256); the 16-bit
-// storages are latency bound and prefer 20. Rows are kept in [11, 65] with rows + 4 a multiple of 3 (the row loop
-// is unrolled three times). TLB_ROWS_PER_BLOCK overrides the row count.
+// storages are latency bound and prefer 20. Rows are kept in [5, 65] with
+// rows + 4 a multiple of 3 (the row loop is unrolled three times);
+// p.rows > 0 sets the row count.
 tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool solid, bool tau_one) {
   tlbh::Geometry l;
   const int lx = p.lx, ly = p.ly;
   // 32-bit byte offsets address the whole population buffer below 4 GiB;
-  // TLB_FORCE_WIDE=1 selects the 64-bit variant at any size (for testing).
-  const char* force = std::getenv("TLB_FORCE_WIDE");
-  l.wide = buffer_bytes > 0xFFFFFFFFull || (force && std::atoi(force) == 1);
+  // TLB_LAUNCH_WIDE_OFFSETS selects the 64-bit variant at any size.
+  l.wide = buffer_bytes > 0xFFFFFFFFull || (p.launch_flags & TLB_LAUNCH_WIDE_OFFSETS) != 0;
   l.bx = (lx >= 2048 || l.wide) ? 256 : 64;
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
@@ -149,32 +149,25 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
   // 39.0 at 2, 41.0 at 8, 48.0 at 11).
   rows = rows < 5 ? 5 : (rows > 65 ? 65 : rows);
   while ((rows + 4) % 3) ++rows;
-  if (const char* env = std::getenv("TLB_ROWS_PER_BLOCK")) {
-    int v = std::atoi(env);
-    if (v >= 1 && v <= 4096) rows = v;
-  }
+  if (p.rows > 0) rows = p.rows;
   l.rows = (int)(rows < ly ? rows : ly);
   l.grid = dim3((unsigned)strips, (unsigned)((ly + l.rows - 1) / l.rows), 1);
 
   // Fused two-step kernel: tau = tau_g = 1, any storage but fixed point, 32-bit
   // offsets. Its strips overlap by kStep2Halo columns and its
   // chunks recompute 5 rows of the first step on each side, so it pays
-  // where the chunks can be tall and the grid still fills every CU once:
-  // chunks of at least 24 rows, one block per resident slot. TLB_STEP2=1
-  // selects it wherever it applies (FP64 included), TLB_STEP2=0 never.
+  // where the chunks can be tall enough and the grid still fills every CU
+  // once: chunks of at least 6 rows, one block per resident slot.
+  // TLB_FUSED_ALWAYS selects it wherever it applies (FP64 included),
+  // TLB_FUSED_NEVER never.
   const bool eligible = tau_one && !l.wide && p.precision != TLB_FIX16_DEV;
-  const char* step2_env = std::getenv("TLB_STEP2");
-  const int step2_mode = step2_env ? std::atoi(step2_env) : -1;
-  if (eligible && step2_mode != 0) {
+  if (eligible && p.fused != TLB_FUSED_NEVER) {
     int per_cu2 = 0;
     with_storage(p.precision, [&](auto st) {
       per_cu2 = tlbh::Launcher<decltype(st)>::step2_blocks_per_cu(solid);
     });
     int max_strip = tlbh::kStep2Lanes - tlbh::kStep2Halo;
-    if (const char* env = std::getenv("TLB_STEP2_STRIP")) {
-      int v = std::atoi(env);
-      if (v >= 1 && v < max_strip) max_strip = v;
-    }
+    if (p.fused_strip > 0) max_strip = p.fused_strip;
     const long long strips2 = (lx + max_strip - 1) / max_strip;
     const int strip2 = (int)((lx + strips2 - 1) / strips2);
     // at most one block per resident slot: a second, partial wave of blocks
@@ -182,15 +175,16 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
     const long long slots = (long long)cus * std::max(per_cu2, 1);
     const long long max_chunks = std::max(1LL, slots / strips2);
     long long rows2 = (ly + max_chunks - 1) / max_chunks;
-    // it pays with tall chunks and at least two resident blocks per CU: FP64
-    // (139 KB of LDS, one block per CU) measured 1577 us per fused launch
-    // against 2 x 766 us of single steps at 4096 x 2048
-    const bool pays = rows2 >= 24 && per_cu2 >= 2;
-    if (per_cu2 > 0 && (pays || step2_mode == 1)) {
-      if (const char* env = std::getenv("TLB_STEP2_ROWS")) {
-        int v = std::atoi(env);
-        if (v >= 1 && v <= 4096) rows2 = v;
-      }
+    // it pays with chunks of at least 6 rows and at least two resident
+    // blocks per CU. Measured FP32 steps: 1024 x 512 (lattice resident in
+    // the MALL, halo rows cheap) 27.7 us fused with 6-row chunks against
+    // 36.3 us single (8 rows 32.1, 4 rows 39.3); 4096 x 2048 with 69-row
+    // chunks 263 us against 377 us. FP64 (139 KB of LDS, one block per CU)
+    // measured 1577 us per fused launch against 2 x 766 us of single steps
+    // at 4096 x 2048.
+    const bool pays = rows2 >= 6 && per_cu2 >= 2;
+    if (per_cu2 > 0 && (pays || p.fused == TLB_FUSED_ALWAYS)) {
+      if (p.fused_rows > 0) rows2 = p.fused_rows;
       l.rows2 = (int)(rows2 < ly ? rows2 : ly);
       l.strip2 = strip2;
       l.grid2 = dim3((unsigned)strips2, (unsigned)((ly + l.rows2 - 1) / l.rows2), 1);
@@ -490,6 +484,14 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
     return fail(nullptr, TLB_EINVAL, "tlb_init: rho_ref and t_ref must be finite");
   if (!std::isfinite(p->u_wall[0]) || !std::isfinite(p->u_wall[1]))
     return fail(nullptr, TLB_EINVAL, "tlb_init: u_wall must be finite");
+  if ((p->launch_flags & ~(TLB_LAUNCH_GENERAL_PATH | TLB_LAUNCH_WIDE_OFFSETS)) != 0 ||
+      p->fused < TLB_FUSED_AUTO || p->fused > TLB_FUSED_ALWAYS || p->fused_rows < 0 ||
+      p->fused_rows > 4096 || p->fused_strip < 0 ||
+      p->fused_strip >= tlbh::kStep2Lanes - tlbh::kStep2Halo || p->rows < 0 || p->rows > 4096)
+    return fail(nullptr, TLB_EINVAL,
+                "tlb_init: launch options out of range (flags %d, fused %d, fused_rows %d, "
+                "fused_strip %d, rows %d)",
+                p->launch_flags, p->fused, p->fused_rows, p->fused_strip, p->rows);
   if (!(p->tau > 0.5) || !(p->tau_g > 0.5) || !finite_positive(p->rho0) || !(p->dt_nominal != 0) ||
       !std::isfinite(p->dt_nominal))
     return fail(nullptr, TLB_EINVAL, "tlb_init: need tau > 1/2, tau_g > 1/2, rho0 > 0, dt_nominal != 0");
@@ -536,9 +538,8 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
   h->pop_stride = (long long)h->pitch * ly;
   h->elem = storage_bytes(p->precision);
   // tau = tau_g = 1 gives f* = f^eq exactly: the kernels keep only moments of
-  // the pulled rows (TLB_GENERAL_PATH=1 forces the general path, for tests)
-  const char* general = std::getenv("TLB_GENERAL_PATH");
-  h->tau_one = p->tau == 1.0 && p->tau_g == 1.0 && !(general && std::atoi(general) == 1);
+  // the pulled rows (TLB_LAUNCH_GENERAL_PATH forces the general path)
+  h->tau_one = p->tau == 1.0 && p->tau_g == 1.0 && !(p->launch_flags & TLB_LAUNCH_GENERAL_PATH);
   h->launch = choose_launch(*p, buffer_planes(p->precision) * h->pop_stride * h->elem,
                             h->has_solid, h->tau_one);
 

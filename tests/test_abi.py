@@ -67,6 +67,8 @@ def _params(**kw):
     p.alpha_g, p.t_top = 0.0, 0.0
     p.rho_wall[0], p.rho_wall[1] = 0.612, 0.612
     p.dt_nominal = kw.get("dt_nominal", 1.0)
+    for k in ("launch_flags", "fused", "fused_rows", "fused_strip", "rows"):
+        setattr(p, k, kw.get(k, 0))
     return p
 
 
@@ -94,6 +96,13 @@ def _init(p, solid=None, null_field=False):
     (dict(tau_g=0.2), "tau"),
     (dict(rho0=0.0), "rho0"),
     (dict(dt_nominal=0.0), "dt_nominal"),
+    (dict(launch_flags=4), "launch options"),
+    (dict(fused=3), "launch options"),
+    (dict(fused=-1), "launch options"),
+    (dict(fused_rows=-2), "launch options"),
+    (dict(fused_rows=5000), "launch options"),
+    (dict(fused_strip=246), "launch options"),
+    (dict(rows=4097), "launch options"),
 ])
 def test_init_rejects_bad_params_without_device(kw, msg):
     rc, h, err = _init(_params(**kw))
@@ -138,6 +147,10 @@ def test_binding_fails_loudly_without_library(tmp_path):
 
 def test_binding_validates_shapes_before_calling():
     w = workloads.small()
+    with pytest.raises(ValueError):
+        tlb.Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], launch={"fused_row": 4})
+    with pytest.raises(KeyError):
+        tlb.Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], launch={"fused": "yes"})
     with pytest.raises(ValueError):
         tlb.Simulation(w["params"], w["rho_a"], w["rho_b"][:, :5], w["temp"])
     with pytest.raises(ValueError):

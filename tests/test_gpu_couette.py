@@ -130,16 +130,15 @@ def test_adjoint_refuses_moving_walls():
 
 @pytest.mark.parametrize("precision,fused,tol", [("fp64", "0", 1e-13), ("fp64", "1", 1e-13),
                                                  ("fp32", "0", 2e-6), ("fp32", "1", 2e-6)])
-def test_uniform_translation_with_comoving_walls_is_stationary(monkeypatch, precision, fused, tol):
+def test_uniform_translation_with_comoving_walls_is_stationary(precision, fused, tol):
     """Both moving-wall rules on the GPU (Sec. 2.2): a uniform fluid moving
     with the walls at the walls' temperature, wetting densities equal to the
     fluid's, stays at its start equilibrium (single and fused launches)."""
-    monkeypatch.setenv("TLB_STEP2", fused)
     lx, ly, uw, tw = 64, 24, 0.05, 0.7
     p = dict(workloads.BASE_PARAMS, alpha_g=0.0, rho_wall=(0.6, 0.4), t_top=tw, u_wall=(uw, uw))
     sim = Simulation(p, np.full((ly, lx), 0.6), np.full((ly, lx), 0.4), np.full((ly, lx), tw),
                      t_bottom=np.full(lx, tw), ux0=np.full((ly, lx), uw), uy0=np.zeros((ly, lx)),
-                     precision=precision)
+                     precision=precision, launch={"fused": "always" if fused == "1" else "never"})
     start = sim.populations()
     sim.step(151)
     assert rel(sim.populations(), start) <= tol

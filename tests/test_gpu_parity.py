@@ -193,7 +193,7 @@ def l2_rel(a, b):
 
 
 @pytest.mark.parametrize("fused", ["0", "1"])
-def test_fp32_mid_1000_and_2000_steps(monkeypatch, mid_oracle, fused):
+def test_fp32_mid_1000_and_2000_steps(mid_oracle, fused):
     """The FP32 benchmark emulsion 1024 x 512 (seed 2, buoyant, noisy) against
     the FP64 oracle element by element after 1000 and 2000 steps, with single
     steps and with the fused two-step kernel: temperature <= 1e-5 of its
@@ -201,9 +201,9 @@ def test_fp32_mid_1000_and_2000_steps(monkeypatch, mid_oracle, fused):
     below, set from a plain FP32 implementation of the same scheme; u^H is
     also reported as an L2 relative error."""
     w, ref = mid_oracle
-    monkeypatch.setenv("TLB_STEP2", fused)
     sim = Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
-                     t_bottom=w["t_bottom"], precision="fp32")
+                     t_bottom=w["t_bottom"], precision="fp32",
+                     launch={"fused": "always" if fused == "1" else "never"})
     assert (sim.launch_info()["fused_rows"] > 0) == (fused == "1")
     results = {}
     for t in (1000, 2000):
@@ -235,12 +235,11 @@ def test_fp32_mid_1000_and_2000_steps(monkeypatch, mid_oracle, fused):
             assert o[k] == pytest.approx(o_ref[k], rel=1e-6), (t, k)
 
 
-def test_observables_from_the_last_step_equal_a_reevaluated_time_level(monkeypatch):
+def test_observables_from_the_last_step_equal_a_reevaluated_time_level():
     """tlb_step's last launch forms the observable sums; after a new bottom
     temperature the time level is evaluated again by a separate pass. Both
     give the oracle's observables (FP64, posts, per-column T_b, fused
     launches before the last step)."""
-    monkeypatch.setenv("TLB_STEP2", "1")
     c = posts_case()
     sim, ora = run_pair(c, 41, "fp64")
     a = sim.observables()
@@ -302,15 +301,15 @@ def test_fp32_full_size_mass_and_translation_over_1000_steps(name):
         assert np.array_equal(sh(fa[k]), fb[k]), k
 
 
-def test_wide_offsets_match_narrow_bitwise(monkeypatch):
+def test_wide_offsets_match_narrow_bitwise():
     """The 64-bit offset variant (used for buffers >= 4 GiB) gives bitwise the
     same state as the 32-bit one; forced on a small lattice with posts."""
     c = posts_case(lx=96, ly=48, seed=3)
     runs = []
-    for force in ("0", "1"):
-        monkeypatch.setenv("TLB_FORCE_WIDE", force)
+    for wide in (False, True):
         sim = Simulation(c["params"], c["rho_a"], c["rho_b"], c["temp"], solid=c["solid"],
-                         t_bottom=c["t_bottom"], precision="fp32")
+                         t_bottom=c["t_bottom"], precision="fp32",
+                         launch={"wide_offsets": wide, "fused": "never"})
         sim.step(40)
         runs.append((sim.populations(), sim.fields()))
         sim.close()
@@ -385,7 +384,7 @@ def test_dev16_one_step_is_the_oracle_step_rounded_once(precision):
 
 @pytest.mark.parametrize("precision,fused", [("fp16dev", "0"), ("bf16dev", "0"),
                                              ("fp16dev", "1"), ("bf16dev", "1")])
-def test_dev16_float_conserves_each_component_mass(monkeypatch, precision, fused):
+def test_dev16_float_conserves_each_component_mass(precision, fused):
     """FP16 / BF16 deviations with FP32 rest populations: each component's
     mass (FP64 sum of the densities) after 1000 steps on the 512 x 256 crop
     with posts. Single steps move only stored values between nodes, and each
@@ -394,10 +393,10 @@ def test_dev16_float_conserves_each_component_mass(monkeypatch, precision, fused
     values much smaller than their node's sum): bar 1e-9. The fused kernel
     keeps its intermediate level in FP32 (rounded like FP32 storage, whose
     drift is ~1e-8 over 5000 steps): bar 1e-6."""
-    monkeypatch.setenv("TLB_STEP2", fused)
     w = workloads.crop(steps=0)
     sim = Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
-                     t_bottom=w["t_bottom"], precision=precision)
+                     t_bottom=w["t_bottom"], precision=precision,
+                     launch={"fused": "always" if fused == "1" else "never"})
     assert (sim.launch_info()["fused_rows"] > 0) == (fused == "1")
     m0 = sim.observables()
     sim.step(1000)
@@ -434,16 +433,17 @@ def test_fix16_conserves_each_component_mass_exactly():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fix16dev"])
-def test_tau_one_path_matches_general_path_bitwise(monkeypatch, precision):
+def test_tau_one_path_matches_general_path_bitwise(precision):
     """At tau = tau_g = 1 the collision returns the equilibria; the kernels
     then keep only the moments of the pulled rows. That path must give
-    bitwise the state of the general path (forced by TLB_GENERAL_PATH=1)."""
+    bitwise the state of the general path (forced by the general_path launch
+    flag)."""
     c = posts_case(lx=96, ly=48, seed=4)
     runs = []
-    for general in ("1", "0"):
-        monkeypatch.setenv("TLB_GENERAL_PATH", general)
+    for general in (True, False):
         sim = Simulation(c["params"], c["rho_a"], c["rho_b"], c["temp"], solid=c["solid"],
-                         t_bottom=c["t_bottom"], precision=precision)
+                         t_bottom=c["t_bottom"], precision=precision,
+                         launch={"general_path": general, "fused": "never"})
         sim.step(30)
         runs.append((sim.populations(), sim.fields(), sim.observables()))
         sim.close()

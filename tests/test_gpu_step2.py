@@ -13,10 +13,10 @@ differences of populations. Against the oracle the bars are those of the single-
 tests: FP64 <= 1e-12 relative, FP32 <= 1e-5 for densities, temperature and
 populations (3e-5 of max|u| for velocities).
 
-TLB_STEP2=1 forces the fused kernel wherever it applies (it is otherwise
-chosen only for lattices where it pays), TLB_STEP2=0 disables it, and
-TLB_STEP2_ROWS sets its chunk height, so short chunks exercise chunk edges
-in both marching directions.
+The launch option fused = "always" forces the fused kernel wherever it
+applies (it is otherwise chosen only for lattices where it pays), "never"
+disables it, and fused_rows sets its chunk height, so short chunks exercise
+chunk edges in both marching directions.
 """
 import numpy as np
 import pytest
@@ -30,15 +30,12 @@ from test_gpu_parity import FIELDS, field_errors, pop_errors, posts_case
 pytestmark = pytest.mark.gpu
 
 
-def make(case, precision, monkeypatch, fused, rows=None, **extra):
-    monkeypatch.setenv("TLB_STEP2", "1" if fused else "0")
-    if rows is None:
-        monkeypatch.delenv("TLB_STEP2_ROWS", raising=False)
-    else:
-        monkeypatch.setenv("TLB_STEP2_ROWS", str(rows))
+def make(case, precision, fused, rows=None, strip=None, **extra):
+    launch = {"fused": "always" if fused else "never", "fused_rows": rows or 0,
+              "fused_strip": strip or 0}
     p = dict(case["params"], **extra)
     sim = Simulation(p, case["rho_a"], case["rho_b"], case["temp"], solid=case.get("solid"),
-                     t_bottom=case.get("t_bottom"), precision=precision)
+                     t_bottom=case.get("t_bottom"), precision=precision, launch=launch)
     info = sim.launch_info()
     print("launch", info)
     return sim, info
@@ -81,11 +78,11 @@ CASES = {
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("rows", [None, 1, 7])
-def test_fused_matches_single_steps(monkeypatch, precision, name, rows):
+def test_fused_matches_single_steps(precision, name, rows):
     case = CASES[name]()
-    fused, info = make(case, precision, monkeypatch, True, rows)
+    fused, info = make(case, precision, True, rows)
     assert info["fused_rows"] > 0
-    single, info0 = make(case, precision, monkeypatch, False)
+    single, info0 = make(case, precision, False)
     assert info0["fused_rows"] == 0
     for n in (9, 1, 2, 6):   # odd and even calls; every call ends with a single step
         fused.step(n)
@@ -97,12 +94,12 @@ def test_fused_matches_single_steps(monkeypatch, precision, name, rows):
         assert_close_state(fused, single, 2e-6, 2e-5)
 
 
-def test_fused_kernel_is_not_used_where_it_does_not_apply(monkeypatch):
+def test_fused_kernel_is_not_used_where_it_does_not_apply():
     w = workloads.small()
-    _, info = make(w, "fix16dev", monkeypatch, True)
+    _, info = make(w, "fix16dev", True)
     assert info["fused_rows"] == 0
     for precision in ("fp32", "fp16dev"):
-        _, info = make(w, precision, monkeypatch, True, tau=0.8)
+        _, info = make(w, precision, True, tau=0.8)
         assert info["fused_rows"] == 0, precision
 
 
@@ -113,7 +110,7 @@ HALF_ULP_BITS = {"fp16dev": (10, -14), "bf16dev": (7, -126)}
 @pytest.mark.parametrize("precision", sorted(HALF_ULP_BITS))
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("rows", [None, 7])
-def test_dev16_fused_launch_from_gpu_state(monkeypatch, precision, name, rows):
+def test_dev16_fused_launch_from_gpu_state(precision, name, rows):
     """16-bit deviation storage, fused kernel forced on: from the GPU's own
     state after 4 steps (decoded exactly), tlb_step(3) runs one fused launch
     and one single step; the oracle takes 3 FP64 steps from the same state.
@@ -125,7 +122,7 @@ def test_dev16_fused_launch_from_gpu_state(monkeypatch, precision, name, rows):
     is at most 16 half ulps of the largest moving deviation, plus FP32
     arithmetic."""
     case = CASES[name]()
-    sim, info = make(case, precision, monkeypatch, True, rows)
+    sim, info = make(case, precision, True, rows)
     assert info["fused_rows"] > 0
     sim.step(4)
     state = sim.populations()
@@ -151,9 +148,9 @@ def test_dev16_fused_launch_from_gpu_state(monkeypatch, precision, name, rows):
         assert err <= bound, (key, err, bound)
 
 
-def test_fp64_fused_matches_oracle(monkeypatch):
+def test_fp64_fused_matches_oracle():
     case = posts_case()
-    sim, info = make(case, "fp64", monkeypatch, True, rows=5)
+    sim, info = make(case, "fp64", True, rows=5)
     assert info["fused_rows"] > 0
     ora = Oracle(ModelParams(**case["params"]), case["rho_a"], case["rho_b"], case["temp"],
                  solid=case["solid"], t_bottom=case["t_bottom"])
@@ -165,9 +162,9 @@ def test_fp64_fused_matches_oracle(monkeypatch):
     assert max(perr.values()) <= 1e-12, perr
 
 
-def test_fp32_fused_1000_steps_matches_oracle(monkeypatch):
+def test_fp32_fused_1000_steps_matches_oracle():
     case = workloads.small()
-    sim, info = make(case, "fp32", monkeypatch, True)
+    sim, info = make(case, "fp32", True)
     assert info["fused_rows"] > 0
     ora = Oracle(ModelParams(**case["params"]), case["rho_a"], case["rho_b"], case["temp"],
                  solid=case.get("solid"), t_bottom=case.get("t_bottom"))
@@ -179,14 +176,12 @@ def test_fp32_fused_1000_steps_matches_oracle(monkeypatch):
     assert max(errs["ux"], errs["uy"]) <= 3e-5, errs
 
 
-def test_full_size_fused_steps_from_gpu_state(monkeypatch):
+def test_full_size_fused_steps_from_gpu_state():
     """4096 x 2048 with posts in the benchmark's own launch configuration
     (fused kernel chosen by default): from the GPU's state after 20 steps,
     the GPU advances 3 steps (one fused launch and a single step) and the
     oracle 3 steps from the same state; every field and population is
     compared."""
-    monkeypatch.delenv("TLB_STEP2", raising=False)
-    monkeypatch.delenv("TLB_STEP2_ROWS", raising=False)
     w = workloads.large()
     p = w["params"]
     sim = Simulation(p, w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
@@ -211,30 +206,30 @@ def test_full_size_fused_steps_from_gpu_state(monkeypatch):
 
 
 @pytest.mark.parametrize("lx,ly", [(5, 3), (64, 1), (7, 2), (250, 9)])
-def test_fused_edge_shapes_fp64(monkeypatch, lx, ly):
+def test_fused_edge_shapes_fp64(lx, ly):
     """Lattices narrower than the kernel's halo (columns wrap several times
     across one block), a single row (both walls on it), and a strip just
     above one block's stored width. Velocities get 1e-11 of max|u|: on these
     lattices max|u| is small (about 1e-4 on the single row), while u carries
     the absolute rounding of its populations."""
     case = droplet_case(lx, ly, seed=lx + ly)
-    fused, info = make(case, "fp64", monkeypatch, True)
+    fused, info = make(case, "fp64", True)
     assert info["fused_rows"] > 0
-    single, _ = make(case, "fp64", monkeypatch, False)
+    single, _ = make(case, "fp64", False)
     for n in (7, 4):
         fused.step(n)
         single.step(n)
     assert_close_state(fused, single, 1e-13, 1e-11)
 
 
-def test_fused_launch_geometry(monkeypatch):
+def test_fused_launch_geometry():
     """At 4096 x 2048 the fused grid fits one block per resident slot, its
     strips cover the lattice with at most 246 stored columns each, and its
-    chunks are at least 24 rows tall; TLB_STEP2_ROWS and TLB_STEP2_STRIP
-    override the choice."""
+    chunks are at least 24 rows tall; the fused_rows and fused_strip launch
+    options override the choice."""
     w = workloads.large()
     lx, ly = w["lx"], w["ly"]
-    sim, info = make(w, "fp32", monkeypatch, True)
+    sim, info = make(w, "fp32", True)
     sim.close()
     assert 24 <= info["fused_rows"] <= ly and info["fused_strip"] <= 246
     assert info["fused_grid_x"] * info["fused_strip"] >= lx
@@ -243,8 +238,7 @@ def test_fused_launch_geometry(monkeypatch):
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     assert info["fused_grid_x"] * info["fused_grid_y"] <= 2 * cus
-    monkeypatch.setenv("TLB_STEP2_STRIP", "200")
-    sim, info2 = make(w, "fp32", monkeypatch, True, rows=40)
+    sim, info2 = make(w, "fp32", True, rows=40, strip=200)
     sim.close()
     assert info2["fused_rows"] == 40 and info2["fused_strip"] <= 200
 
@@ -254,15 +248,15 @@ U_WALL = (-0.01, 0.02)
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", ["small", "posts"])
-def test_fused_moving_walls_match_single_steps(monkeypatch, precision, name):
+def test_fused_moving_walls_match_single_steps(precision, name):
     """Couette walls (Sec. 2.2): the second level adds the wall momentum to
     the bounced diagonal links with the node's own intermediate zeroth
     moment as rho_w, which equals the sum of its stored populations in the
     single step up to rounding."""
     case = CASES[name]()
-    fused, info = make(case, precision, monkeypatch, True, rows=7, u_wall=U_WALL)
+    fused, info = make(case, precision, True, rows=7, u_wall=U_WALL)
     assert info["fused_rows"] > 0
-    single, _ = make(case, precision, monkeypatch, False, u_wall=U_WALL)
+    single, _ = make(case, precision, False, u_wall=U_WALL)
     for n in (9, 1, 2, 6):
         fused.step(n)
         single.step(n)
@@ -272,9 +266,9 @@ def test_fused_moving_walls_match_single_steps(monkeypatch, precision, name):
         assert_close_state(fused, single, 2e-6, 2e-5)
 
 
-def test_fp64_fused_moving_walls_match_oracle(monkeypatch):
+def test_fp64_fused_moving_walls_match_oracle():
     case = posts_case()
-    sim, info = make(case, "fp64", monkeypatch, True, rows=5, u_wall=U_WALL)
+    sim, info = make(case, "fp64", True, rows=5, u_wall=U_WALL)
     assert info["fused_rows"] > 0
     ora = Oracle(ModelParams(**dict(case["params"], u_wall=U_WALL)), case["rho_a"], case["rho_b"],
                  case["temp"], solid=case["solid"], t_bottom=case["t_bottom"])
@@ -286,11 +280,11 @@ def test_fp64_fused_moving_walls_match_oracle(monkeypatch):
     assert max(perr.values()) <= 1e-12, perr
 
 
-def test_fp32_fused_moving_walls_500_steps(monkeypatch):
+def test_fp32_fused_moving_walls_500_steps():
     """The single path's Couette bar (FP32 after 500 steps under shear:
     1e-5 for densities and temperature, 3e-5 of max|u| for velocities)."""
     case = workloads.small()
-    sim, info = make(case, "fp32", monkeypatch, True, u_wall=U_WALL)
+    sim, info = make(case, "fp32", True, u_wall=U_WALL)
     assert info["fused_rows"] > 0
     ora = Oracle(ModelParams(**dict(case["params"], u_wall=U_WALL)), case["rho_a"], case["rho_b"],
                  case["temp"], solid=case.get("solid"), t_bottom=case.get("t_bottom"))
