@@ -217,7 +217,10 @@ class Simulation:
         p.u_wall[0], p.u_wall[1] = params.get("u_wall", (0.0, 0.0))
         self.params = p
         self.precision = precision
-        self._drop_cap = 4096      # droplet records asked for by droplets()
+        # droplet records asked for by droplets(): room for one droplet per
+        # 64 nodes (emulsions of radius-10 discs hold one per ~600), raised
+        # to the count when a call finds more
+        self._drop_cap = max(4096, lx * ly // 64)
         self._tape_generation = 0  # bumped by every forward_taped
         s = _current_stream() if stream == "torch" else stream
         rc = self._lib.tlb_init(ctypes.byref(self._h), ctypes.byref(p), _dp(rho_a), _dp(rho_b),

@@ -10,6 +10,12 @@
 // cluster is therefore its smallest node index, and droplets are numbered in
 // the order of their roots (canonical, independent of scheduling).
 //
+// The unions run in two passes: each block first unites the links inside its
+// 64 x 16 tile in LDS and writes, for every bulk node, the smallest index of
+// its cluster within the tile; a global pass then unites only the links that
+// cross a tile edge (or the periodic seam), so most unions never touch
+// global memory.
+//
 // Per-droplet sums (node count, sum rho_A, sum rho_A X, sum rho_A Y) are
 // exact: each term is rounded once to a multiple of 2^-40 and split into a
 // high and a low 32-bit part; the parts are summed as 64-bit integers, first
@@ -93,20 +99,95 @@ __device__ inline bool is_bulk(const DropArgs& a, int q) {
   return a.solid[q] == 0 && a.fields[q] > a.threshold;
 }
 
-__global__ __launch_bounds__(256) void drop_init(DropArgs a) {
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= a.n) return;
-  if (q == 0) *a.error = 0;  // raised only by the later passes
-  a.parent[q] = is_bulk(a, q) ? q : -1;
+// Tile of the LDS union pass: 64 columns x 16 rows, 4 nodes per thread.
+constexpr int kLocalW = 64, kLocalH = 16, kLocalN = kLocalW * kLocalH;
+
+__device__ inline int lds_parent(const int* p, int i) {
+  return __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__global__ __launch_bounds__(256) void drop_union(DropArgs a) {
+// find_root / unite on a tile's LDS parents (local indices, row-major in the
+// tile; bounded walks as in the global ones).
+__device__ inline int lds_find(int* par, int q, bool& fail) {
+  for (int it = 0; it <= kLocalN; ++it) {
+    const int p = lds_parent(par, q);
+    if (p == q) return q;
+    const int g = lds_parent(par, p);
+    if (g == p) return p;
+    atomicMin(par + q, g);
+    q = g;
+  }
+  fail = true;
+  return q;
+}
+
+__device__ inline void lds_unite(int* par, int a, int b, bool& fail) {
+  for (int it = 0; it <= kLocalN; ++it) {
+    a = lds_find(par, a, fail);
+    b = lds_find(par, b, fail);
+    if (a == b) return;
+    if (a < b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    const int old = atomicMin(par + a, b);
+    if (old == a) return;
+    a = old;
+  }
+  fail = true;
+}
+
+// Union pass inside each tile. Local row-major order is the global order
+// restricted to the tile, so a tile cluster's local root is its smallest
+// node index, which becomes the parent of every node of the cluster.
+__global__ __launch_bounds__(256) void drop_local(DropArgs a) {
+  __shared__ int par[kLocalN];
+  const int x0 = blockIdx.x * kLocalW, y0 = blockIdx.y * kLocalH;
+  for (int k = 0; k < kLocalN / 256; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    const int gx = x0 + (i % kLocalW), gy = y0 + i / kLocalW;
+    const bool bulk = gx < a.lx && gy < a.ly && is_bulk(a, gy * a.lx + gx);
+    par[i] = bulk ? i : -1;
+  }
+  __syncthreads();
+  bool fail = false;
+  for (int k = 0; k < kLocalN / 256; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (lds_parent(par, i) < 0) continue;
+    const int lxi = i % kLocalW, lyi = i / kLocalW;
+    if (lxi + 1 < kLocalW && x0 + lxi + 1 < a.lx && lds_parent(par, i + 1) >= 0)
+      lds_unite(par, i, i + 1, fail);
+    if (lyi + 1 < kLocalH && y0 + lyi + 1 < a.ly && lds_parent(par, i + kLocalW) >= 0)
+      lds_unite(par, i, i + kLocalW, fail);
+  }
+  __syncthreads();
+  for (int k = 0; k < kLocalN / 256; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    const int gx = x0 + (i % kLocalW), gy = y0 + i / kLocalW;
+    if (gx >= a.lx || gy >= a.ly) continue;
+    int out = -1;
+    if (lds_parent(par, i) >= 0) {
+      const int r = lds_find(par, i, fail);
+      out = (y0 + r / kLocalW) * a.lx + x0 + r % kLocalW;
+    }
+    a.parent[gy * a.lx + gx] = out;
+  }
+  if (fail) atomicOr(a.error, 1);
+}
+
+// Global union pass over the links the tiles did not cover: from a tile's
+// last column (or the lattice's, across the periodic seam) to the right, and
+// from a tile's top row upwards.
+__global__ __launch_bounds__(256) void drop_union_border(DropArgs a) {
   const int q = blockIdx.x * 256 + threadIdx.x;
   if (q >= a.n || a.parent[q] < 0) return;
   const int x = q % a.lx, y = q / a.lx;
-  const int right = y * a.lx + (x + 1 == a.lx ? 0 : x + 1);
-  if (right != q && a.parent[right] >= 0) unite(a.parent, q, right, a.n + 1, a.error);
-  if (y + 1 < a.ly) {
+  if (x % kLocalW == kLocalW - 1 || x == a.lx - 1) {
+    const int right = y * a.lx + (x + 1 == a.lx ? 0 : x + 1);
+    if (right != q && a.parent[right] >= 0) unite(a.parent, q, right, a.n + 1, a.error);
+  }
+  if (y % kLocalH == kLocalH - 1 && y + 1 < a.ly) {
     const int up = q + a.lx;
     if (a.parent[up] >= 0) unite(a.parent, q, up, a.n + 1, a.error);
   }
@@ -252,10 +333,12 @@ __global__ __launch_bounds__(256) void drop_accumulate(DropArgs a) {
 }
 
 // FP64 copy of the bottom wall temperature (the handle keeps the compute
-// type of its storage).
+// type of its storage); also clears the error flag of the union passes,
+// which run after it.
 __global__ __launch_bounds__(256) void drop_bottom_temperature(const void* src, int src_is_f32,
-                                                               double* dst, int lx) {
+                                                               double* dst, int lx, int* error) {
   const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x == 0) *error = 0;
   if (x >= lx) return;
   dst[x] = src_is_f32 ? (double)static_cast<const float*>(src)[x]
                       : static_cast<const double*>(src)[x];

@@ -396,7 +396,7 @@ int run_droplets(tlb_handle* h, const char* who, DropBuffers& b, bool grow, doub
   int rc = evaluate_time_level(h, Level::kFields, b.fields);
   if (rc != TLB_OK) return rc;
   hipLaunchKernelGGL(tlbk::drop_bottom_temperature, dim3((lx + 255) / 256), dim3(256), 0,
-                     h->stream, h->t_bottom, is_fp64(h) ? 0 : 1, b.tb, lx);
+                     h->stream, h->t_bottom, is_fp64(h) ? 0 : 1, b.tb, lx, b.error);
   tlbk::DropArgs a{};
   a.fields = b.fields;
   a.solid = h->solid;
@@ -414,8 +414,10 @@ int run_droplets(tlb_handle* h, const char* who, DropBuffers& b, bool grow, doub
   a.ly = ly;
   a.n = n;
   const dim3 nodes((n + 255) / 256), block(256);
-  hipLaunchKernelGGL(tlbk::drop_init, nodes, block, 0, h->stream, a);
-  hipLaunchKernelGGL(tlbk::drop_union, nodes, block, 0, h->stream, a);
+  const dim3 local_tiles((lx + tlbk::kLocalW - 1) / tlbk::kLocalW,
+                         (ly + tlbk::kLocalH - 1) / tlbk::kLocalH);
+  hipLaunchKernelGGL(tlbk::drop_local, local_tiles, block, 0, h->stream, a);
+  hipLaunchKernelGGL(tlbk::drop_union_border, nodes, block, 0, h->stream, a);
   hipLaunchKernelGGL(tlbk::drop_compress, nodes, block, 0, h->stream, a);
   hipLaunchKernelGGL(tlbk::drop_count_roots, dim3(tiles), block, 0, h->stream, a);
   hipLaunchKernelGGL(tlbk::drop_scan_tiles, dim3(1), block, 0, h->stream, b.tiles, tiles);
