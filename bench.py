@@ -97,15 +97,17 @@ def cpu_baseline(w: dict, sample_steps: int, single_steps: int) -> dict:
     return out
 
 
-def adjoint_ratio(steps: int, ckpt: int, precision: str) -> dict:
+def adjoint_ratio(steps: int, ckpt: int, precision: str, config: str = "mid") -> dict:
     """Time of the taped forward plus the reverse sweep (checkpoint segment
     recompute included) over the time of the plain forward, for the same
-    `steps` steps of the 1024x512 emulsion with a noisy bottom temperature."""
+    `steps` steps of an emulsion with a noisy bottom temperature: the
+    1024x512 lattice (its gradient is zero: in 500 steps no signal crosses
+    512 rows) or the 1024x64 strip (a live gradient)."""
     import torch
 
     from paper_2109_12565_amd import Simulation
 
-    w = workloads.mid()
+    w = workloads.CONFIGS[config]()
     tb = workloads.bottom_temperature_noise(w["lx"], 5)
 
     def make():
@@ -399,6 +401,7 @@ def main() -> int:
         out["companions"] = companion_runs(args.config, args.precision)
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint_ratio(args.adjoint_steps, 25, "fp32")
+        out["adjoint_strip"] = adjoint_ratio(args.adjoint_steps, 25, "fp32", "strip")
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.cpu_steps_1t)
     print(json.dumps(out), flush=True)

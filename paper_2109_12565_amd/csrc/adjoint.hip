@@ -43,9 +43,15 @@ void Adjoint<St>::reverse_step(const Device& d, const AdjointWork& w, const void
   const int lx = d.p->lx, ly = d.p->ly;
   const dim3 grid((lx + 255) / 256, ly), block(256);
   if (!density_ready) hipLaunchKernelGGL((tlbk::adj_density<St>), grid, block, 0, d.stream, a);
-  hipLaunchKernelGGL((tlbk::adj_local<St>), grid, block, 0, d.stream, a);
-  hipLaunchKernelGGL((tlbk::adj_scatter<St>), grid, block, 0, d.stream, a);
-  hipLaunchKernelGGL((tlbk::adj_pull<St>), grid, block, 0, d.stream, a);
+  if (d.tau_one) {
+    hipLaunchKernelGGL((tlbk::adj_local<St, true>), grid, block, 0, d.stream, a);
+    hipLaunchKernelGGL((tlbk::adj_scatter<St, true>), grid, block, 0, d.stream, a);
+    hipLaunchKernelGGL((tlbk::adj_pull<St, true>), grid, block, 0, d.stream, a);
+  } else {
+    hipLaunchKernelGGL((tlbk::adj_local<St, false>), grid, block, 0, d.stream, a);
+    hipLaunchKernelGGL((tlbk::adj_scatter<St, false>), grid, block, 0, d.stream, a);
+    hipLaunchKernelGGL((tlbk::adj_pull<St, false>), grid, block, 0, d.stream, a);
+  }
 }
 
 template struct Adjoint<tlbk::Store<double>>;

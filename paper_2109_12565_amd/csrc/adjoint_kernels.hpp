@@ -25,6 +25,13 @@
 // Densities and pseudopotentials of the step's pulled state are precomputed
 // by adj_density; the forward quantities of a node are recomputed from them
 // and from the node's pulled populations.
+//
+// tau = tau_g = 1 (kTauOne): the relaxation passes nothing of lambda(t+1)
+// straight through, so dL/d f_{l,i}(t) at a node is rbar_l + c_i.jbar and
+// dL/d g_i(t) is tbar, five numbers per node: adj_local writes those (planes
+// 0..4 of fbar: rbar_A, rbar_B, jbar_x, jbar_y, tbar) instead of 27 values,
+// adj_scatter adds the stencil transpose to rbar_l, and adj_pull gathers the
+// five numbers of each source node.
 #pragma once
 
 #include "lb_kernels.hpp"
@@ -166,7 +173,10 @@ __global__ __launch_bounds__(256) void adj_top_row_sum(AdjArgs<typename St::C> a
   if (threadIdx.x == 0) a.loss_terms[a.step_index] = part[0];
 }
 
-template <class St>
+// Compact planes of the tau = 1 form (in the fbar array).
+constexpr int kCompactRbar = 0, kCompactJx = 2, kCompactJy = 3, kCompactT = 4;
+
+template <class St, bool kTauOne>
 __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
   using C = typename St::C;
   const StepArgs<C>& s = a.s;
@@ -278,6 +288,16 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
   }
   // ---- moments (and the loss term of the top row: dL/dT = kappa_top)
   if (y == s.ly - 1) tbar += a.kappa_top;
+  if constexpr (kTauOne) {
+    a.fbar[plane_index(s, kCompactRbar, x, y)] = rbar[0];
+    a.fbar[plane_index(s, kCompactRbar + 1, x, y)] = rbar[1];
+    a.fbar[plane_index(s, kCompactJx, x, y)] = jbx;
+    a.fbar[plane_index(s, kCompactJy, x, y)] = jby;
+    a.fbar[plane_index(s, kCompactT, x, y)] = tbar;
+    for (int l = 0; l < 2; ++l)
+      for (int d = 0; d < 2; ++d) a.Fbar[plane_index(s, 2 * l + d, x, y)] = Fbar[l][d];
+    return;
+  }
   for (int i = 0; i < 9; ++i) {
     const C cx = C(dir_cx(i)), cy = C(dir_cy(i));
     fb[i] += rbar[0] + cx * jbx + cy * jby;
@@ -293,7 +313,7 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
 // Transpose of the force stencils: rho_l(x') enters the self forces of its
 // 24 neighbours through psi_l and the cross forces of the other component's
 // 8 neighbours through rho_l / rho0.
-template <class St>
+template <class St, bool kTauOne>
 __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
   using C = typename St::C;
   const StepArgs<C>& s = a.s;
@@ -322,27 +342,32 @@ __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
   }
   for (int l = 0; l < 2; ++l) {
     const C dps = C(1) - psi_node(a, l, x, y) * s.inv_rho0;
-    a.rbar[plane_index(s, l, x, y)] = rb[l] + psibar[l] * dps;
+    C v = rb[l] + psibar[l] * dps;
+    // tau = 1: the node's own dL/drho_l joins it (one plane to gather later)
+    if constexpr (kTauOne) v = a.fbar[plane_index(s, kCompactRbar + l, x, y)] + v;
+    a.rbar[plane_index(s, l, x, y)] = v;
   }
 }
 
 // dL/dT_b(c) += sum of 2 w_i gbar_i(x, 0) over the bottom links whose solid
 // source lies in column c: i = 2 at x = c, i = 5 at x = c + 1, i = 6 at
 // x = c - 1 (gbar = dL/d of the pulled g, complete once adj_local is done).
-template <class St>
+template <class St, bool kTauOne>
 __device__ inline void grad_tb_column(const AdjArgs<typename St::C>& a, int c) {
   using C = typename St::C;
   const StepArgs<C>& s = a.s;
-  const double v = 2.0 * ((double)w_dir<C>(2) * (double)a.fbar[plane_index(s, 18 + 2, c, 0)] +
-                          (double)w_dir<C>(5) * (double)a.fbar[plane_index(s, 18 + 5, wrapx(s, c + 1), 0)] +
-                          (double)w_dir<C>(6) * (double)a.fbar[plane_index(s, 18 + 6, wrapx(s, c - 1), 0)]);
+  // plane of gbar_i: its own, or the compact tbar (the same for every i)
+  auto gp = [](int i) { return kTauOne ? kCompactT : 18 + i; };
+  const double v = 2.0 * ((double)w_dir<C>(2) * (double)a.fbar[plane_index(s, gp(2), c, 0)] +
+                          (double)w_dir<C>(5) * (double)a.fbar[plane_index(s, gp(5), wrapx(s, c + 1), 0)] +
+                          (double)w_dir<C>(6) * (double)a.fbar[plane_index(s, gp(6), wrapx(s, c - 1), 0)]);
   a.grad[c] += v;
 }
 
 // Transpose of the pull: f*_i(y) was pulled by the node y + c_i, or, when
 // that node is a wall, by y itself as direction opp(i) (bounce-back; with a
 // minus sign for g, anti-bounce-back).
-template <class St>
+template <class St, bool kTauOne>
 __global__ __launch_bounds__(256) void adj_pull(AdjArgs<typename St::C> a) {
   using C = typename St::C;
   const StepArgs<C>& s = a.s;
@@ -353,15 +378,26 @@ __global__ __launch_bounds__(256) void adj_pull(AdjArgs<typename St::C> a) {
     const int tx = wrapx(s, x + dir_cx(i)), ty = y + dir_cy(i);
     const bool wall = ty < 0 || ty >= s.ly;
     const int sx = wall ? x : tx, sy = wall ? y : ty, si = wall ? opp[i] : i;
-    for (int l = 0; l < 2; ++l) {
-      const C v = a.fbar[plane_index(s, 9 * l + si, sx, sy)] + a.rbar[plane_index(s, l, sx, sy)];
-      a.lam[plane_index(s, 9 * l + i, x, y)] = v;
+    if constexpr (kTauOne) {
+      // dL/d f_{l,si} = rbar_l + c_si.jbar, dL/d g_si = tbar at the source node
+      const C jx = a.fbar[plane_index(s, kCompactJx, sx, sy)];
+      const C jy = a.fbar[plane_index(s, kCompactJy, sx, sy)];
+      const C cj = C(dir_cx(si)) * jx + C(dir_cy(si)) * jy;
+      for (int l = 0; l < 2; ++l)
+        a.lam[plane_index(s, 9 * l + i, x, y)] = a.rbar[plane_index(s, l, sx, sy)] + cj;
+      const C gv = a.fbar[plane_index(s, kCompactT, sx, sy)];
+      a.lam[plane_index(s, 18 + i, x, y)] = wall ? -gv : gv;
+    } else {
+      for (int l = 0; l < 2; ++l) {
+        const C v = a.fbar[plane_index(s, 9 * l + si, sx, sy)] + a.rbar[plane_index(s, l, sx, sy)];
+        a.lam[plane_index(s, 9 * l + i, x, y)] = v;
+      }
+      const C gv = a.fbar[plane_index(s, 18 + si, sx, sy)];
+      a.lam[plane_index(s, 18 + i, x, y)] = wall ? -gv : gv;
     }
-    const C gv = a.fbar[plane_index(s, 18 + si, sx, sy)];
-    a.lam[plane_index(s, 18 + i, x, y)] = wall ? -gv : gv;
   }
   // the bottom row's blocks also accumulate dL/dT_b of their columns
-  if (y == 0) grad_tb_column<St>(a, x);
+  if (y == 0) grad_tb_column<St, kTauOne>(a, x);
   // densities of the next reverse step's state: aux is free again once
   // adj_local and adj_scatter of this step are done
   if (a.next_state) density_node<St>(a, a.next_state, x, y);
