@@ -42,14 +42,16 @@ void Adjoint<St>::reverse_step(const Device& d, const AdjointWork& w, const void
   a.next_state = next_state;
   const int lx = d.p->lx, ly = d.p->ly;
   const dim3 grid((lx + 255) / 256, ly), block(256);
+  // the stencil kernels run on 64 x 4 tiles
+  const dim3 tiles((lx + tlbk::kAdjTX - 1) / tlbk::kAdjTX, (ly + tlbk::kAdjTY - 1) / tlbk::kAdjTY);
   if (!density_ready) hipLaunchKernelGGL((tlbk::adj_density<St>), grid, block, 0, d.stream, a);
   if (d.tau_one) {
-    hipLaunchKernelGGL((tlbk::adj_local<St, true>), grid, block, 0, d.stream, a);
-    hipLaunchKernelGGL((tlbk::adj_scatter<St, true>), grid, block, 0, d.stream, a);
+    hipLaunchKernelGGL((tlbk::adj_local<St, true>), tiles, block, 0, d.stream, a);
+    hipLaunchKernelGGL((tlbk::adj_scatter<St, true>), tiles, block, 0, d.stream, a);
     hipLaunchKernelGGL((tlbk::adj_pull<St, true>), grid, block, 0, d.stream, a);
   } else {
-    hipLaunchKernelGGL((tlbk::adj_local<St, false>), grid, block, 0, d.stream, a);
-    hipLaunchKernelGGL((tlbk::adj_scatter<St, false>), grid, block, 0, d.stream, a);
+    hipLaunchKernelGGL((tlbk::adj_local<St, false>), tiles, block, 0, d.stream, a);
+    hipLaunchKernelGGL((tlbk::adj_scatter<St, false>), tiles, block, 0, d.stream, a);
     hipLaunchKernelGGL((tlbk::adj_pull<St, false>), grid, block, 0, d.stream, a);
   }
 }

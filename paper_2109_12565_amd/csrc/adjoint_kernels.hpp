@@ -70,31 +70,30 @@ __device__ inline int wrapx(const StepArgs<C>& a, int x) {
   return x < 0 ? x + a.lx : (x >= a.lx ? x - a.lx : x);
 }
 
-// Density of component l at lattice node (x, y) (wall value outside).
-template <typename C>
-__device__ inline C rho_node(const AdjArgs<C>& a, int l, int x, int y) {
-  if (y < 0 || y >= a.s.ly) return l == 0 ? a.s.rho_wall0 : a.s.rho_wall1;
-  return a.aux[plane_index(a.s, l, wrapx(a.s, x), y)];
-}
+// LDS tile of the stencil kernels: a block of 256 threads owns 64 x 4
+// nodes and stages NF fields of the (64 + 4) x (4 + 4) cells within 2 of
+// them (x periodic; rows beyond the walls take `wall`), so the 5 x 5
+// stencils of adj_local and adj_scatter read LDS instead of global memory.
+constexpr int kAdjTX = 64, kAdjTY = 4, kAdjHalo = 2;
+constexpr int kAdjTW = kAdjTX + 2 * kAdjHalo, kAdjTH = kAdjTY + 2 * kAdjHalo;
 
-// psi_l = rho0 (1 - exp(-rho_l / rho0)) (Eq. (12)) at (x, y).
-template <typename C>
-__device__ inline C psi_node(const AdjArgs<C>& a, int l, int x, int y) {
-  if (y < 0 || y >= a.s.ly)
-    return psi_exp(l == 0 ? a.s.rho_wall0 : a.s.rho_wall1, a.s.rho0, a.s.inv_rho0);
-  return a.aux[plane_index(a.s, 2 + l, wrapx(a.s, x), y)];
-}
+template <typename C, int NF>
+struct AdjTile {
+  C v[NF][kAdjTH][kAdjTW];
+};
 
-// F-bar of component l at (x, y); zero outside the lattice.
-template <typename C>
-__device__ inline void fbar_node(const AdjArgs<C>& a, int l, int x, int y, C& fx, C& fy) {
-  if (y < 0 || y >= a.s.ly) {
-    fx = fy = C(0);
-    return;
+// Fill the tile of the block at (x0, y0): field f of cell (cx, cy) is
+// load(f, x, y) at the lattice node (x, y), or wall[f] outside the rows.
+template <typename C, int NF, class Load>
+__device__ inline void fill_tile(AdjTile<C, NF>& t, int x0, int y0, int lx, int ly,
+                                 const C (&wall)[NF], Load load) {
+  for (int c = threadIdx.x; c < kAdjTW * kAdjTH; c += 256) {
+    const int cx = c % kAdjTW, cy = c / kAdjTW;
+    const int x = ((x0 - kAdjHalo + cx) % lx + lx) % lx, y = y0 - kAdjHalo + cy;
+    const bool in = y >= 0 && y < ly;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) t.v[f][cy][cx] = in ? load(f, x, y) : wall[f];
   }
-  const uint32_t q = plane_index(a.s, 2 * l, wrapx(a.s, x), y);
-  fx = a.Fbar[q];
-  fy = a.Fbar[q + (uint32_t)a.s.pop_stride];
 }
 
 // Pulled populations of node (x, y) from the state (flat walls).
@@ -180,8 +179,21 @@ template <class St, bool kTauOne>
 __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
   using C = typename St::C;
   const StepArgs<C>& s = a.s;
-  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-  if (x >= s.lx) return;
+  // densities and pseudopotentials of the tile and its halo (fields rho_A,
+  // rho_B, psi_A, psi_B; the wall rows carry the wetting values)
+  __shared__ AdjTile<C, 4> tile;
+  const int x0 = blockIdx.x * kAdjTX, y0 = blockIdx.y * kAdjTY;
+  {
+    const C pw0 = psi_exp(s.rho_wall0, s.rho0, s.inv_rho0), pw1 = psi_exp(s.rho_wall1, s.rho0, s.inv_rho0);
+    const C wall[4] = {s.rho_wall0, s.rho_wall1, pw0, pw1};
+    fill_tile(tile, x0, y0, s.lx, s.ly, wall,
+              [&](int f, int xx, int yy) { return a.aux[plane_index(s, f, xx, yy)]; });
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % kAdjTX, ty = threadIdx.x / kAdjTX;
+  const int x = x0 + tx, y = y0 + ty;
+  if (x >= s.lx || y >= s.ly) return;
+  const int cx0 = tx + kAdjHalo, cy0 = ty + kAdjHalo;
   C f[18], g[9];
   adj_pull_node<St>(a, x, y, f, g);
 
@@ -192,7 +204,7 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
   const C ux = jx * inv_rho, uy = jy * inv_rho;
   C Sa[2][2], Sr[2][2], X[2][2], ps[2], dps[2], rl[2] = {ra, rb};
   for (int l = 0; l < 2; ++l) {
-    ps[l] = psi_node(a, l, x, y);
+    ps[l] = tile.v[2 + l][cy0][cx0];
     dps[l] = C(1) - ps[l] * s.inv_rho0;  // d psi / d rho = exp(-rho / rho0)
     Sa[l][0] = Sa[l][1] = Sr[l][0] = Sr[l][1] = X[l][0] = X[l][1] = C(0);
   }
@@ -202,13 +214,13 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
       const int c2 = dx * dx + dy * dy;
       const C pw = p_c2<C>(c2), ww = w_c2<C>(c2);
       for (int l = 0; l < 2; ++l) {
-        const C v = psi_node(a, l, x + dx, y + dy);
+        const C v = tile.v[2 + l][cy0 + dy][cx0 + dx];
         Sr[l][0] += pw * v * C(dx);
         Sr[l][1] += pw * v * C(dy);
         if (c2 <= 2) {
           Sa[l][0] += ww * v * C(dx);
           Sa[l][1] += ww * v * C(dy);
-          const C r = rho_node(a, 1 - l, x + dx, y + dy);  // other component
+          const C r = tile.v[1 - l][cy0 + dy][cx0 + dx];  // other component
           X[l][0] += ww * r * C(dx);
           X[l][1] += ww * r * C(dy);
         }
@@ -317,8 +329,22 @@ template <class St, bool kTauOne>
 __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
   using C = typename St::C;
   const StepArgs<C>& s = a.s;
-  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-  if (x >= s.lx) return;
+  // F-bar (A_x, A_y, B_x, B_y), rho_A, rho_B, psi_A, psi_B of the tile and
+  // its halo (no force beyond the walls)
+  __shared__ AdjTile<C, 8> tile;
+  const int x0 = blockIdx.x * kAdjTX, y0 = blockIdx.y * kAdjTY;
+  {
+    const C wall[8] = {C(0), C(0), C(0), C(0), s.rho_wall0, s.rho_wall1,
+                       psi_exp(s.rho_wall0, s.rho0, s.inv_rho0), psi_exp(s.rho_wall1, s.rho0, s.inv_rho0)};
+    fill_tile(tile, x0, y0, s.lx, s.ly, wall, [&](int f, int xx, int yy) {
+      return f < 4 ? a.Fbar[plane_index(s, f, xx, yy)] : a.aux[plane_index(s, f - 4, xx, yy)];
+    });
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % kAdjTX, ty = threadIdx.x / kAdjTX;
+  const int x = x0 + tx, y = y0 + ty;
+  if (x >= s.lx || y >= s.ly) return;
+  const int cx0 = tx + kAdjHalo, cy0 = ty + kAdjHalo;
   const C gcross = s.g12 * s.inv_rho0 * s.inv_rho0;
   const C ga[2] = {s.ga0, s.ga1}, gr[2] = {s.gr0, s.gr1};
   C psibar[2] = {0, 0}, rb[2] = {0, 0};
@@ -328,20 +354,19 @@ __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
     for (int dx = -2; dx <= 2; ++dx) {
       if (dx == 0 && dy == 0) continue;
       // neighbour x - c whose stencil reaches this node with offset c
-      const int nx = x - dx, ny = y - dy;
+      const int ncx = cx0 - dx, ncy = cy0 - dy;
       const int c2 = dx * dx + dy * dy;
       const C pw = p_c2<C>(c2), ww = w_c2<C>(c2);
       for (int l = 0; l < 2; ++l) {
-        C fx, fy;
-        fbar_node(a, l, nx, ny, fx, fy);
+        const C fx = tile.v[2 * l][ncy][ncx], fy = tile.v[2 * l + 1][ncy][ncx];
         const C dot = fx * C(dx) + fy * C(dy);
-        psibar[l] -= psi_node(a, l, nx, ny) * (ga[l] * ww + gr[l] * pw) * dot;
-        if (c2 <= 2) rb[1 - l] -= gcross * rho_node(a, l, nx, ny) * ww * dot;
+        psibar[l] -= tile.v[6 + l][ncy][ncx] * (ga[l] * ww + gr[l] * pw) * dot;
+        if (c2 <= 2) rb[1 - l] -= gcross * tile.v[4 + l][ncy][ncx] * ww * dot;
       }
     }
   }
   for (int l = 0; l < 2; ++l) {
-    const C dps = C(1) - psi_node(a, l, x, y) * s.inv_rho0;
+    const C dps = C(1) - tile.v[6 + l][cy0][cx0] * s.inv_rho0;
     C v = rb[l] + psibar[l] * dps;
     // tau = 1: the node's own dL/drho_l joins it (one plane to gather later)
     if constexpr (kTauOne) v = a.fbar[plane_index(s, kCompactRbar + l, x, y)] + v;
