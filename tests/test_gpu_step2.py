@@ -108,9 +108,10 @@ HALF_ULP_BITS = {"fp16dev": (10, -14), "bf16dev": (7, -126)}
 
 
 @pytest.mark.parametrize("precision", sorted(HALF_ULP_BITS))
-@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("name,u_wall", [(n, (0.0, 0.0)) for n in sorted(CASES)] +
+                         [("small", (-0.01, 0.02)), ("posts", (-0.01, 0.02))])
 @pytest.mark.parametrize("rows", [None, 7])
-def test_dev16_fused_launch_from_gpu_state(precision, name, rows):
+def test_dev16_fused_launch_from_gpu_state(precision, name, u_wall, rows):
     """16-bit deviation storage, fused kernel forced on: from the GPU's own
     state after 4 steps (decoded exactly), tlb_step(3) runs one fused launch
     and one single step; the oracle takes 3 FP64 steps from the same state.
@@ -120,8 +121,9 @@ def test_dev16_fused_launch_from_gpu_state(precision, name, rows):
     sums 8 rounded moving values pulled from its neighbours and loses the 8
     roundings of its own (through the exact rest remainder), so the error
     is at most 16 half ulps of the largest moving deviation, plus FP32
-    arithmetic."""
+    arithmetic. Walls at rest, and moving Couette walls on two lattices."""
     case = CASES[name]()
+    case["params"] = dict(case["params"], u_wall=u_wall)
     sim, info = make(case, precision, True, rows)
     assert info["fused_rows"] > 0
     sim.step(4)
