@@ -28,9 +28,11 @@ tlbk::AdjArgs<typename St::C> adjoint_args(const Device& d, const AdjointWork& w
 }  // namespace
 
 template <class St>
-void Adjoint<St>::top_row_term(const Device& d, const AdjointWork& w, const void* state, int k) {
+void Adjoint<St>::top_row_term(const Device& d, const AdjointWork& w, const void* state, int k,
+                               int stride) {
   auto a = adjoint_args<St>(d, w, state, 0);
   a.step_index = k;
+  a.loss_stride = stride;
   hipLaunchKernelGGL((tlbk::adj_top_row_sum<St>), dim3(1), dim3(256), 0, d.stream, a);
 }
 

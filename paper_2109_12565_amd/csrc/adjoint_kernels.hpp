@@ -54,6 +54,7 @@ struct AdjArgs {
                            // then also fills aux for it
   C kappa_top;           // dL/dT of each top-row node for this step
   int step_index;
+  int loss_stride;       // slots per step in loss_terms
 };
 
 // Element index of plane p at node (x, y) in a population-layout array. The
@@ -169,7 +170,11 @@ __global__ __launch_bounds__(256) void adj_top_row_sum(AdjArgs<typename St::C> a
     if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) a.loss_terms[a.step_index] = part[0];
+  // slot 0 of the step's row; the other slots (per-strip sums of the fused
+  // kernel's steps) are zero here
+  double* row = a.loss_terms + (size_t)a.step_index * a.loss_stride;
+  if (threadIdx.x == 0) row[0] = part[0];
+  for (int k = 1 + threadIdx.x; k < a.loss_stride; k += 256) row[k] = 0.0;
 }
 
 // Compact planes of the tau = 1 form (in the fbar array).

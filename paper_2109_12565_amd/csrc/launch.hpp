@@ -55,7 +55,9 @@ enum class Pass {
   kFieldsInit,   // same at t = 0 from f(0)
   kStress,       // fields and xy stress of time t (general path), no store
   kStressInit,   // same at t = 0 from f(0)
-  kStep2         // f*(t) -> f*(t+2), fused two-step kernel (Geometry::rows2 > 0)
+  kStep2,        // f*(t) -> f*(t+2), fused two-step kernel (Geometry::rows2 > 0)
+  kStep2TopRow   // same (flat walls at rest), and per strip the sums of T - t_top over
+                 // the top row of both steps into Device::partials [2][strips]
 };
 
 template <class St>
@@ -82,7 +84,8 @@ struct AdjointWork {
   void* aux = nullptr;                // rho_A, rho_B, psi_A, psi_B, 4 planes
   void* rbar = nullptr;               // dL/drho from the force stencils, 2 planes
   double* grad = nullptr;             // [lx] dL/dT_b
-  double* loss_terms = nullptr;       // [steps] top-row sums of T - t_top
+  double* loss_terms = nullptr;       // [steps][stride] top-row sums of T - t_top (per
+                                      // fused-kernel strip, or in slot 0)
 };
 
 // Number of compute-type planes of an AdjointWork.
@@ -93,7 +96,8 @@ template <class St>
 struct Adjoint {
   // w.loss_terms[k] = sum over the top row of T - t_top, T the temperature
   // pulled from `state` (the step's pre-collision temperature).
-  static void top_row_term(const Device& d, const AdjointWork& w, const void* state, int k);
+  static void top_row_term(const Device& d, const AdjointWork& w, const void* state, int k,
+                           int stride);
   // Reverse step of state -> next state: lambda[1 - in] from lambda[in]
   // (dL/d of the next state), adding the top-row loss term with weight
   // kappa_top and accumulating dL/dT_b into w.grad. density_ready: the

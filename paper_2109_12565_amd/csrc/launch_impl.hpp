@@ -122,12 +122,16 @@ template <class St>
 constexpr bool kHasStep2 = !St::kFix && (!St::kDev || St::kRest32);
 
 template <class St>
-void launch_step2(const Device& d, const void* src, void* dst) {
+void launch_step2(const Device& d, const void* src, void* dst, bool top_row) {
   if constexpr (kHasStep2<St>) {
     auto a = make_args<typename St::C>(d, src, dst);
     a.rows_per_block = d.geo.rows2;
     constexpr unsigned M = tlbk::kModeStore | tlbk::kModeTauOne;
     constexpr unsigned S = tlbk::kModeSolid, V = tlbk::kModeMoving;
+    if (top_row) {  // the taped run of the adjoint: flat walls at rest only
+      if (!d.moving && !d.has_solid) launch_step2_kernel<St, M | tlbk::kModeTopRow>(d, a);
+      return;
+    }
     if (d.moving) {
       if (d.has_solid) launch_step2_kernel<St, M | S | V>(d, a);
       else launch_step2_kernel<St, M | V>(d, a);
@@ -191,7 +195,8 @@ void Launcher<St>::step(const Device& d, Pass pass, const void* src, void* dst) 
     case Pass::kStressInit:
       detail::launch_mode<St, kModeFields | kModeStress | kModeInit>(d, src, dst);
       break;
-    case Pass::kStep2: detail::launch_step2<St>(d, src, dst); break;
+    case Pass::kStep2: detail::launch_step2<St>(d, src, dst, false); break;
+    case Pass::kStep2TopRow: detail::launch_step2<St>(d, src, dst, true); break;
   }
 }
 

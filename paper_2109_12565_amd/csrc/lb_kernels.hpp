@@ -211,7 +211,9 @@ enum : unsigned {
   kModeWide = 32u,    // 64-bit byte offsets (population buffer >= 4 GiB)
   kModeTauOne = 64u,  // tau = tau_g = 1: the collision returns the equilibria
   kModeStress = 128u, // with kModeFields: also write the xy stress fields
-  kModeMoving = 256u  // the flat walls move (momentum term in their bounce-back)
+  kModeMoving = 256u, // the flat walls move (momentum term in their bounce-back)
+  kModeTopRow = 512u  // fused kernel: per-strip sums of T - t_top over the top row
+                      // at both levels into partials (the taped run's loss terms)
 };
 
 // rho0 (1 - exp(-rho/rho0)) of Eq. (12), evaluated as -rho0 expm1(-rho/rho0)

@@ -203,6 +203,7 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   static_assert((kMode & kModeTauOne) != 0 && (kMode & kModeStore) != 0, "tau = 1 store pass");
   static_assert((kMode & (kModeWide | kModeInit | kModeObserve | kModeFields)) == 0,
                 "32-bit offsets, no observables");
+  constexpr bool kTop = (kMode & kModeTopRow) != 0;
   constexpr int kH = 5;          // left halo lanes
   constexpr int R1 = 5, RM = 3;  // density ring rows, moment ring rows
   constexpr int W = BT + 4;      // density ring row: lanes plus 2 padding columns each side
@@ -247,6 +248,10 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   const C psi_w0 = psi_of<St>(a.rho_wall0, a.rho0, a.inv_rho0);
   const C psi_w1 = psi_of<St>(a.rho_wall1, a.rho0, a.inv_rho0);
   constexpr bool kSolid = (kMode & kModeSolid) != 0;
+  // kTop: this lane's T - t_top on the top row at the two levels (the chunk
+  // that owns the top row, stored lanes only: each column counted once)
+  const bool top_chunk = kTop && y1 == ly;
+  double top_sum[2] = {0.0, 0.0};
 
   // Level 1, phase 1: pull row ra from HBM (issued first in the phase, so
   // the level-2 work of the phase hides the load latency), then densities
@@ -296,6 +301,9 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
     C Dt = sum9(g);
     if constexpr (St::kDev) Dt += a.ref_t;
     const C temp = Dt;
+    if constexpr (kTop) {
+      if (top_chunk && r == ly - 1 && out_lane) top_sum[0] += (double)temp - (double)a.t_top;
+    }
     int rs[5];
 #pragma unroll
     for (int d = 0; d < 5; ++d) rs[d] = ring_slot<R1>(r - 2 + d);
@@ -405,6 +413,9 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
     }
     const C Da = ku[0], Db = ku[1], jx = ku[2], jy = ku[3], Dt = ku[4];
     const C ra = Da, rb = Db, temp = Dt;
+    if constexpr (kTop) {
+      if (top_chunk && r == ly - 1) top_sum[1] += (double)temp - (double)a.t_top;
+    }
     int rs[5];
 #pragma unroll
     for (int d = 0; d < 5; ++d) rs[d] = ring_slot<R1>(r - 2 + d);
@@ -505,6 +516,26 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
     iterate(k, f0, l0, f1, l1, h0, m0, h1, m1);
     iterate(k + 1, f1, l1, f2, l2, h1, m1, h2, m2);
     iterate(k + 2, f2, l2, f0, l0, h2, m2, h0, m0);
+  }
+
+  if constexpr (kTop) {
+    // fixed-order block sums into partials[level * strips + strip]
+    if (top_chunk) {
+      __shared__ double s_top[2][BT / 64];
+#pragma unroll
+      for (int lev = 0; lev < 2; ++lev) {
+        double v = top_sum[lev];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if ((tid & 63) == 0) s_top[lev][tid >> 6] = v;
+      }
+      __syncthreads();
+      if (tid < 2) {
+        double v = 0;
+        for (int w = 0; w < BT / 64; ++w) v += s_top[tid][w];
+        a.partials[(size_t)tid * nbx + (tile - chunk * nbx)] = v;
+      }
+    }
   }
 }
 

@@ -193,7 +193,8 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
   return l;
 }
 
-tlbh::Device device_view(const tlb_handle* h, double* fields = nullptr) {
+tlbh::Device device_view(const tlb_handle* h, double* fields = nullptr,
+                         double* partials = nullptr) {
   tlbh::Device d;
   d.p = &h->p;
   d.stream = h->stream;
@@ -206,14 +207,14 @@ tlbh::Device device_view(const tlb_handle* h, double* fields = nullptr) {
   d.link = h->link;
   d.solid = h->solid;
   d.t_bottom = h->t_bottom;
-  d.partials = h->partials;
+  d.partials = partials ? partials : h->partials;
   d.fields = fields ? fields : h->fields;
   return d;
 }
 
 void launch_pass(const tlb_handle* h, tlbh::Pass pass, const void* src, void* dst,
-                 double* fields = nullptr) {
-  const tlbh::Device d = device_view(h, fields);
+                 double* fields = nullptr, double* partials = nullptr) {
+  const tlbh::Device d = device_view(h, fields, partials);
   with_storage(h->p.precision,
                [&](auto st) { tlbh::Launcher<decltype(st)>::step(d, pass, src, dst); });
 }
@@ -286,6 +287,12 @@ int ensure_buffer(tlb_handle* h, void** ptr, size_t* cap, size_t bytes, const ch
   return TLB_OK;
 }
 
+// Slots per step of the taped run's loss terms: one per strip of the fused
+// kernel (whose launches write per-strip top-row sums), else one.
+int loss_stride(const tlb_handle* h) {
+  return h->launch.rows2 > 0 ? (int)h->launch.grid2.x : 1;
+}
+
 // Adjoint work buffers (planes and FP64 scalars) for a run of `nsteps`.
 int ensure_adjoint_work(tlb_handle* h, int64_t nsteps, tlbh::AdjointWork* w) {
   const size_t csize = is_fp64(h) ? sizeof(double) : sizeof(float);
@@ -293,7 +300,7 @@ int ensure_adjoint_work(tlb_handle* h, int64_t nsteps, tlbh::AdjointWork* w) {
   size_t cap = h->adj ? (size_t)tlbh::kAdjointPlanes * plane : 0;
   int rc = ensure_buffer(h, &h->adj, &cap, (size_t)tlbh::kAdjointPlanes * plane, "adjoint work");
   if (rc != TLB_OK) return rc;
-  const size_t scalars = (size_t)h->p.lx + (size_t)nsteps;
+  const size_t scalars = (size_t)h->p.lx + (size_t)nsteps * (size_t)loss_stride(h);
   size_t scap = h->adj_scalars ? ((size_t)h->p.lx + h->loss_cap) * sizeof(double) : 0;
   rc = ensure_buffer(h, reinterpret_cast<void**>(&h->adj_scalars), &scap, scalars * sizeof(double),
                      "adjoint scalars");
@@ -879,23 +886,39 @@ int tlb_forward_taped(tlb_handle* h, int64_t nsteps, int32_t ckpt_every, double*
   rc = ensure_adjoint_work(h, nsteps, &w);
   if (rc != TLB_OK) return rc;
   const tlbh::Device d = device_view(h);
-  for (int64_t k = 0; k < nsteps; ++k) {
+  // Pairs of steps run as one fused launch (which also writes both steps'
+  // top-row sums, per strip) where the kernel applies and the state between
+  // them is not a checkpoint; the other steps, and always the last one (so
+  // that the other buffer holds the previous state, as after tlb_step), are
+  // single steps with the top-row sum of their pulled state.
+  const int stride = loss_stride(h);
+  const bool fused = h->launch.rows2 > 0;
+  for (int64_t k = 0; k < nsteps;) {
     if (k % ckpt_every == 0)
       TLB_HIP(h, hipMemcpyAsync(static_cast<char*>(h->ckpt) + (size_t)(k / ckpt_every) * sb,
                                 h->buf[h->cur], sb, hipMemcpyDeviceToDevice, h->stream));
+    if (fused && k + 2 < nsteps && (k + 1) % ckpt_every != 0) {
+      launch_pass(h, tlbh::Pass::kStep2TopRow, h->buf[h->cur], h->buf[1 - h->cur], nullptr,
+                  w.loss_terms + (size_t)k * stride);
+      h->cur = 1 - h->cur;
+      h->t += 2;
+      k += 2;
+      continue;
+    }
     with_adjoint_storage(h, [&](auto st) {
-      tlbh::Adjoint<decltype(st)>::top_row_term(d, w, h->buf[h->cur], (int)k);
+      tlbh::Adjoint<decltype(st)>::top_row_term(d, w, h->buf[h->cur], (int)k, stride);
     });
     launch_pass(h, tlbh::Pass::kStep, h->buf[h->cur], h->buf[1 - h->cur]);
     h->cur = 1 - h->cur;
     h->t += 1;
+    k += 1;
   }
   TLB_HIP(h, hipGetLastError());
-  std::vector<double> terms((size_t)nsteps);
+  std::vector<double> terms((size_t)nsteps * stride);
   TLB_HIP(h, hipMemcpyAsync(terms.data(), w.loss_terms, terms.size() * sizeof(double),
                             hipMemcpyDeviceToHost, h->stream));
   TLB_HIP(h, hipStreamSynchronize(h->stream));
-  double acc = 0;
+  double acc = 0;   // fixed order: step by step, strip by strip
   for (double v : terms) acc += v;
   if (loss)
     *loss = acc * 2.0 * h->p.ly / (h->p.dt_nominal * h->p.lx) / (double)nsteps;

@@ -33,11 +33,11 @@ def T(a):
     return torch.tensor(a, dtype=torch.float64)
 
 
-def make_sim(case, precision, t_bottom=None, **params):
+def make_sim(case, precision, t_bottom=None, launch=None, **params):
     p = dict(case["params"], **params)
     tb = case["t_bottom"] if t_bottom is None else t_bottom
     return Simulation(p, case["rho_a"], case["rho_b"], case["temp"], t_bottom=tb,
-                      precision=precision)
+                      precision=precision, launch=launch)
 
 
 def gpu_loss_and_grad(case, precision, tb, nsteps, ckpt, **params):
@@ -162,6 +162,30 @@ def test_taped_run_matches_plain_steps_and_observables():
         g2 = a.adjoint(n, seed=2.0)
         assert np.array_equal(2.0 * g1, g2)
         assert np.array_equal(a.populations(), b.populations())
+
+
+def test_fused_taped_run_matches_fused_steps_and_single_step_adjoint():
+    """With the fused two-step kernel forced on, the taped run takes the same
+    launches as tlb_step (fused pairs, the last steps single; checkpoints
+    every 8 fall between pairs), so it advances bitwise like tlb_step; its
+    loss, formed from the fused kernel's per-strip top-row sums, and the
+    gradient of the reverse sweep equal those of the single-step taped run
+    to rounding (FP64)."""
+    case = buoyant_case()
+    n = 30
+    fused = {"fused": "always"}
+    with make_sim(case, "fp64", launch=fused) as a, make_sim(case, "fp64", launch=fused) as b, \
+            make_sim(case, "fp64", launch={"fused": "never"}) as c:
+        assert a.launch_info()["fused_rows"] > 0
+        loss = a.forward_taped(n, 8)
+        b.step(n)
+        assert np.array_equal(a.populations(), b.populations())
+        ref_loss = c.forward_taped(n, 8)
+        assert loss == pytest.approx(ref_loss, rel=1e-13)
+        g, ref_g = a.adjoint(n), c.adjoint(n)
+        scale = np.abs(ref_g).max()
+        assert scale > 0
+        assert np.abs(g - ref_g).max() <= 1e-11 * scale
 
 
 def test_autograd_function_matches_adjoint():
