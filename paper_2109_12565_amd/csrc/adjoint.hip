@@ -38,20 +38,38 @@ void Adjoint<St>::top_row_term(const Device& d, const AdjointWork& w, const void
 
 template <class St>
 void Adjoint<St>::reverse_step(const Device& d, const AdjointWork& w, const void* state, int in,
-                               double kappa_top, const void* next_state, bool density_ready) {
+                               double kappa_top, const void* next_state, bool density_ready,
+                               bool first) {
+  using C = typename St::C;
   auto a = adjoint_args<St>(d, w, state, in);
-  a.kappa_top = static_cast<typename St::C>(kappa_top);
+  a.kappa_top = static_cast<C>(kappa_top);
   a.next_state = next_state;
   const int lx = d.p->lx, ly = d.p->ly;
   const dim3 grid((lx + 255) / 256, ly), block(256);
   // the stencil kernels run on 64 x 4 tiles
   const dim3 tiles((lx + tlbk::kAdjTX - 1) / tlbk::kAdjTX, (ly + tlbk::kAdjTY - 1) / tlbk::kAdjTY);
-  if (!density_ready) hipLaunchKernelGGL((tlbk::adj_density<St>), grid, block, 0, d.stream, a);
   if (d.tau_one) {
+    // Two kernels per reverse step: adj_local gathers lambda(t+1) from the
+    // previous step's compact planes, adj_scatter also does the T_b gradient
+    // and the next step's densities. Buffers alternate by `in` (planes of
+    // lambda[0], unused in this form): compact planes, dL/drho, densities.
+    C* lam0 = static_cast<C*>(w.lam[0]);
+    const size_t plane = (size_t)d.pop_stride;
+    C* cmp[2] = {lam0, lam0 + 5 * plane};
+    C* rb[2] = {lam0 + 10 * plane, lam0 + 12 * plane};
+    C* aux[2] = {static_cast<C*>(w.aux), lam0 + 14 * plane};
+    a.fbar = cmp[in];
+    a.rbar = rb[in];
+    a.aux = aux[in];
+    a.cmp_prev = cmp[1 - in];
+    a.rbar_prev = rb[1 - in];
+    a.aux_next = aux[1 - in];
+    a.have_prev = first ? 0 : 1;
+    if (!density_ready) hipLaunchKernelGGL((tlbk::adj_density<St>), grid, block, 0, d.stream, a);
     hipLaunchKernelGGL((tlbk::adj_local<St, true>), tiles, block, 0, d.stream, a);
     hipLaunchKernelGGL((tlbk::adj_scatter<St, true>), tiles, block, 0, d.stream, a);
-    hipLaunchKernelGGL((tlbk::adj_pull<St, true>), grid, block, 0, d.stream, a);
   } else {
+    if (!density_ready) hipLaunchKernelGGL((tlbk::adj_density<St>), grid, block, 0, d.stream, a);
     hipLaunchKernelGGL((tlbk::adj_local<St, false>), tiles, block, 0, d.stream, a);
     hipLaunchKernelGGL((tlbk::adj_scatter<St, false>), tiles, block, 0, d.stream, a);
     hipLaunchKernelGGL((tlbk::adj_pull<St, false>), grid, block, 0, d.stream, a);

@@ -51,10 +51,18 @@ struct AdjArgs {
   double* grad;          // [lx] accumulated dL/dT_b
   double* loss_terms;    // per-step loss terms (forward)
   const void* next_state;  // state of the next reverse step, or null: adj_pull
-                           // then also fills aux for it
+                           // (adj_scatter at tau = 1) then also fills its aux
   C kappa_top;           // dL/dT of each top-row node for this step
   int step_index;
   int loss_stride;       // slots per step in loss_terms
+  // tau = 1: the compact planes (fbar) and dL/drho (rbar) of the previous
+  // reverse step (time t+1), from which adj_local gathers lambda(t+1), or
+  // have_prev = 0 at the first reverse step (lambda = 0); aux_next receives
+  // the densities of next_state
+  const C* cmp_prev;
+  const C* rbar_prev;
+  C* aux_next;
+  int have_prev;
 };
 
 // Element index of plane p at node (x, y) in a population-layout array. The
@@ -124,10 +132,11 @@ __device__ inline void adj_pull_thermal_node(const AdjArgs<typename St::C>& a, i
   pull_thermal<St, 0u>(a.s, m, L, x, y, lm, g);
 }
 
-// Densities and pseudopotentials of `state` pulled at node (x, y), into aux.
+// Densities and pseudopotentials of `state` pulled at node (x, y), into out
+// (4 planes: rho_A, rho_B, psi_A, psi_B).
 template <class St>
 __device__ inline void density_node(const AdjArgs<typename St::C>& a, const void* state, int x,
-                                    int y) {
+                                    int y, typename St::C* out) {
   using C = typename St::C;
   using O = Off<0>;
   const O row_b = (O)a.s.pitch * sizeof(typename St::T);
@@ -138,17 +147,17 @@ __device__ inline void density_node(const AdjArgs<typename St::C>& a, const void
   C f[18];
   pull_fluid<St, 0u>(a.s, m, L, y, lm, f);
   const C ra = sum9(f), rb = sum9(f + 9);
-  a.aux[plane_index(a.s, 0, x, y)] = ra;
-  a.aux[plane_index(a.s, 1, x, y)] = rb;
-  a.aux[plane_index(a.s, 2, x, y)] = psi_exp(ra, a.s.rho0, a.s.inv_rho0);
-  a.aux[plane_index(a.s, 3, x, y)] = psi_exp(rb, a.s.rho0, a.s.inv_rho0);
+  out[plane_index(a.s, 0, x, y)] = ra;
+  out[plane_index(a.s, 1, x, y)] = rb;
+  out[plane_index(a.s, 2, x, y)] = psi_exp(ra, a.s.rho0, a.s.inv_rho0);
+  out[plane_index(a.s, 3, x, y)] = psi_exp(rb, a.s.rho0, a.s.inv_rho0);
 }
 
 template <class St>
 __global__ __launch_bounds__(256) void adj_density(AdjArgs<typename St::C> a) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
   if (x >= a.s.lx) return;
-  density_node<St>(a, a.state, x, y);
+  density_node<St>(a, a.state, x, y, a.aux);
 }
 
 // Forward loss term of one step: sum over the top row of T - T_top from the
@@ -247,6 +256,36 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
   }
   const C hx = ux + Fx * C(0.5) * inv_rho, hy = uy + Fy * C(0.5) * inv_rho;
 
+  // ---- lambda(t+1) of the node: loaded, or at tau = 1 gathered from the
+  // previous reverse step's compact planes (the transpose of the pull: the
+  // population this node streamed in direction i was pulled by x + c_i, or
+  // bounced back into the node itself across a wall)
+  C lamv[27];
+  if constexpr (kTauOne) {
+    const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int nx = wrapx(s, x + dir_cx(i)), ny = y + dir_cy(i);
+      const bool wall = ny < 0 || ny >= s.ly;
+      const int sx = wall ? x : nx, sy = wall ? y : ny, si = wall ? opp[i] : i;
+      C r0 = 0, r1 = 0, t = 0, cj = 0;
+      if (a.have_prev) {
+        const C jx = a.cmp_prev[plane_index(s, kCompactJx, sx, sy)];
+        const C jy = a.cmp_prev[plane_index(s, kCompactJy, sx, sy)];
+        cj = C(dir_cx(si)) * jx + C(dir_cy(si)) * jy;
+        r0 = a.rbar_prev[plane_index(s, 0, sx, sy)];
+        r1 = a.rbar_prev[plane_index(s, 1, sx, sy)];
+        t = a.cmp_prev[plane_index(s, kCompactT, sx, sy)];
+      }
+      lamv[i] = r0 + cj;
+      lamv[9 + i] = r1 + cj;
+      lamv[18 + i] = wall ? -t : t;
+    }
+  } else {
+#pragma unroll
+    for (int p = 0; p < 27; ++p) lamv[p] = a.lam_next[plane_index(s, p, x, y)];
+  }
+
   // ---- adjoint of the BGK relaxation and of the equilibria
   const C ka = C(1) - s.inv_tau, kg = C(1) - s.inv_tau_g;
   C fb[18], gb[9];
@@ -255,7 +294,7 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
     const C u2 = ul[l][0] * ul[l][0] + ul[l][1] * ul[l][1];
     for (int i = 0; i < 9; ++i) {
       const C cx = C(dir_cx(i)), cy = C(dir_cy(i)), w = w_dir<C>(i);
-      const C lam = a.lam_next[plane_index(s, 9 * l + i, x, y)];
+      const C lam = lamv[9 * l + i];
       fb[9 * l + i] = ka * lam;
       const C e = (C(1) - ka) * lam;  // adjoint of f^eq_i
       const C cu = cx * ul[l][0] + cy * ul[l][1];
@@ -269,7 +308,7 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
     const C u2 = hx * hx + hy * hy;
     for (int i = 0; i < 9; ++i) {
       const C cx = C(dir_cx(i)), cy = C(dir_cy(i)), w = w_dir<C>(i);
-      const C lam = a.lam_next[plane_index(s, 18 + i, x, y)];
+      const C lam = lamv[18 + i];
       gb[i] = kg * lam;
       const C e = (C(1) - kg) * lam;
       const C cu = cx * hx + cy * hy;
@@ -327,6 +366,21 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
     for (int d = 0; d < 2; ++d) a.Fbar[plane_index(s, 2 * l + d, x, y)] = Fbar[l][d];
 }
 
+// dL/dT_b(c) += sum of 2 w_i gbar_i(x, 0) over the bottom links whose solid
+// source lies in column c: i = 2 at x = c, i = 5 at x = c + 1, i = 6 at
+// x = c - 1 (gbar = dL/d of the pulled g, complete once adj_local is done).
+template <class St, bool kTauOne>
+__device__ inline void grad_tb_column(const AdjArgs<typename St::C>& a, int c) {
+  using C = typename St::C;
+  const StepArgs<C>& s = a.s;
+  // plane of gbar_i: its own, or the compact tbar (the same for every i)
+  auto gp = [](int i) { return kTauOne ? kCompactT : 18 + i; };
+  const double v = 2.0 * ((double)w_dir<C>(2) * (double)a.fbar[plane_index(s, gp(2), c, 0)] +
+                          (double)w_dir<C>(5) * (double)a.fbar[plane_index(s, gp(5), wrapx(s, c + 1), 0)] +
+                          (double)w_dir<C>(6) * (double)a.fbar[plane_index(s, gp(6), wrapx(s, c - 1), 0)]);
+  a.grad[c] += v;
+}
+
 // Transpose of the force stencils: rho_l(x') enters the self forces of its
 // 24 neighbours through psi_l and the cross forces of the other component's
 // 8 neighbours through rho_l / rho0.
@@ -377,21 +431,13 @@ __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
     if constexpr (kTauOne) v = a.fbar[plane_index(s, kCompactRbar + l, x, y)] + v;
     a.rbar[plane_index(s, l, x, y)] = v;
   }
-}
-
-// dL/dT_b(c) += sum of 2 w_i gbar_i(x, 0) over the bottom links whose solid
-// source lies in column c: i = 2 at x = c, i = 5 at x = c + 1, i = 6 at
-// x = c - 1 (gbar = dL/d of the pulled g, complete once adj_local is done).
-template <class St, bool kTauOne>
-__device__ inline void grad_tb_column(const AdjArgs<typename St::C>& a, int c) {
-  using C = typename St::C;
-  const StepArgs<C>& s = a.s;
-  // plane of gbar_i: its own, or the compact tbar (the same for every i)
-  auto gp = [](int i) { return kTauOne ? kCompactT : 18 + i; };
-  const double v = 2.0 * ((double)w_dir<C>(2) * (double)a.fbar[plane_index(s, gp(2), c, 0)] +
-                          (double)w_dir<C>(5) * (double)a.fbar[plane_index(s, gp(5), wrapx(s, c + 1), 0)] +
-                          (double)w_dir<C>(6) * (double)a.fbar[plane_index(s, gp(6), wrapx(s, c - 1), 0)]);
-  a.grad[c] += v;
+  if constexpr (kTauOne) {
+    // no adj_pull at tau = 1 (the next adj_local gathers lambda): the bottom
+    // row adds dL/dT_b of its columns here, and the next reverse step's
+    // densities go to the other aux buffer
+    if (y == 0) grad_tb_column<St, true>(a, x);
+    if (a.next_state) density_node<St>(a, a.next_state, x, y, a.aux_next);
+  }
 }
 
 // Transpose of the pull: f*_i(y) was pulled by the node y + c_i, or, when
@@ -430,7 +476,7 @@ __global__ __launch_bounds__(256) void adj_pull(AdjArgs<typename St::C> a) {
   if (y == 0) grad_tb_column<St, kTauOne>(a, x);
   // densities of the next reverse step's state: aux is free again once
   // adj_local and adj_scatter of this step are done
-  if (a.next_state) density_node<St>(a, a.next_state, x, y);
+  if (a.next_state) density_node<St>(a, a.next_state, x, y, a.aux);
 }
 
 

@@ -101,11 +101,15 @@ struct Adjoint {
   // Reverse step of state -> next state: lambda[1 - in] from lambda[in]
   // (dL/d of the next state), adding the top-row loss term with weight
   // kappa_top and accumulating dL/dT_b into w.grad. density_ready: the
-  // densities of `state` are already in w.aux (done by the previous reverse
+  // densities of `state` are already prepared (by the previous reverse
   // step); next_state (or null): the state of the following reverse step,
-  // whose densities this step then prepares.
+  // whose densities this step then prepares; first: the sweep's first
+  // reverse step (lambda of the next state is zero). At tau = tau_g = 1 the
+  // adjoint of a step is carried in compact per-node planes instead of
+  // lambda, alternating with `in`.
   static void reverse_step(const Device& d, const AdjointWork& w, const void* state, int in,
-                           double kappa_top, const void* next_state, bool density_ready);
+                           double kappa_top, const void* next_state, bool density_ready,
+                           bool first);
 };
 
 }  // namespace tlbh

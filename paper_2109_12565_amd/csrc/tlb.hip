@@ -950,6 +950,7 @@ int tlb_adjoint_step(tlb_handle* h, int64_t nsteps, double seed, double* grad_t_
   const tlbh::Device d = device_view(h);
   const int64_t nck = (nsteps + K - 1) / K;
   int in = 0;
+  bool first = true;
   for (int64_t seg = nck - 1; seg >= 0; --seg) {
     const int64_t s0 = seg * K;
     const int len = (int)std::min<int64_t>(K, nsteps - s0);
@@ -965,9 +966,10 @@ int tlb_adjoint_step(tlb_handle* h, int64_t nsteps, double seed, double* grad_t_
     for (int j = len - 1; j >= 0; --j) {
       void* next = j > 0 ? slot(j - 1) : nullptr;
       with_adjoint_storage(h, [&](auto st) {
-        tlbh::Adjoint<decltype(st)>::reverse_step(d, w, slot(j), in, kappa_top, next, ready);
+        tlbh::Adjoint<decltype(st)>::reverse_step(d, w, slot(j), in, kappa_top, next, ready, first);
       });
       ready = next != nullptr;
+      first = false;
       in = 1 - in;
     }
   }
