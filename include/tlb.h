@@ -79,7 +79,7 @@ enum tlb_launch_flags {
 
 /* tlb_params.fused: use of the fused two-step kernel (see tlb_step). */
 enum tlb_fused_mode {
-  TLB_FUSED_AUTO = 0,    /* where it pays (chunks of >= 6 rows, 2 blocks per CU) */
+  TLB_FUSED_AUTO = 0,    /* where it pays (two blocks per CU: FP32, 16-bit) */
   TLB_FUSED_NEVER = 1,
   TLB_FUSED_ALWAYS = 2   /* wherever it applies */
 };

@@ -56,8 +56,10 @@ enum class Pass {
   kStress,       // fields and xy stress of time t (general path), no store
   kStressInit,   // same at t = 0 from f(0)
   kStep2,        // f*(t) -> f*(t+2), fused two-step kernel (Geometry::rows2 > 0)
-  kStep2TopRow   // same (flat walls at rest), and per strip the sums of T - t_top over
+  kStep2TopRow,  // same (flat walls at rest), and per strip the sums of T - t_top over
                  // the top row of both steps into Device::partials [2][strips]
+  kStep2Tape     // same (flat walls at rest, FP64 / FP32), and the intermediate state
+                 // f*(t+1) into a second buffer
 };
 
 template <class St>
@@ -67,7 +69,8 @@ struct Launcher {
   // Resident blocks per CU of the two-step kernel; 0 where the storage has
   // no two-step kernel.
   static int step2_blocks_per_cu(bool solid);
-  static void step(const Device& d, Pass pass, const void* src, void* dst);
+  // dst2: the second output of kStep2Tape
+  static void step(const Device& d, Pass pass, const void* src, void* dst, void* dst2 = nullptr);
   // f(0) = equilibria of the initial fields (rho_a, rho_b, temp, ux0, uy0;
   // the velocities may be null).
   static void init_equilibrium(const Device& d, void* buf, const double* rho_a, const double* rho_b,

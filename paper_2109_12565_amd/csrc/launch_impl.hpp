@@ -122,14 +122,22 @@ template <class St>
 constexpr bool kHasStep2 = !St::kFix && (!St::kDev || St::kRest32);
 
 template <class St>
-void launch_step2(const Device& d, const void* src, void* dst, bool top_row) {
+void launch_step2(const Device& d, const void* src, void* dst, Pass pass, void* dst2) {
   if constexpr (kHasStep2<St>) {
     auto a = make_args<typename St::C>(d, src, dst);
     a.rows_per_block = d.geo.rows2;
+    a.dst2 = dst2;
     constexpr unsigned M = tlbk::kModeStore | tlbk::kModeTauOne;
     constexpr unsigned S = tlbk::kModeSolid, V = tlbk::kModeMoving;
-    if (top_row) {  // the taped run of the adjoint: flat walls at rest only
+    // the adjoint's variants: flat walls at rest only
+    if (pass == Pass::kStep2TopRow) {
       if (!d.moving && !d.has_solid) launch_step2_kernel<St, M | tlbk::kModeTopRow>(d, a);
+      return;
+    }
+    if (pass == Pass::kStep2Tape) {
+      if constexpr (!St::kDev) {
+        if (!d.moving && !d.has_solid) launch_step2_kernel<St, M | tlbk::kModeTape>(d, a);
+      }
       return;
     }
     if (d.moving) {
@@ -179,7 +187,7 @@ int Launcher<St>::blocks_per_cu(int bx, bool wide, bool solid, bool tau_one) {
 }
 
 template <class St>
-void Launcher<St>::step(const Device& d, Pass pass, const void* src, void* dst) {
+void Launcher<St>::step(const Device& d, Pass pass, const void* src, void* dst, void* dst2) {
   using namespace tlbk;
   switch (pass) {
     case Pass::kStep: detail::launch_mode<St, kModeStore>(d, src, dst); break;
@@ -195,8 +203,9 @@ void Launcher<St>::step(const Device& d, Pass pass, const void* src, void* dst) 
     case Pass::kStressInit:
       detail::launch_mode<St, kModeFields | kModeStress | kModeInit>(d, src, dst);
       break;
-    case Pass::kStep2: detail::launch_step2<St>(d, src, dst, false); break;
-    case Pass::kStep2TopRow: detail::launch_step2<St>(d, src, dst, true); break;
+    case Pass::kStep2:
+    case Pass::kStep2TopRow:
+    case Pass::kStep2Tape: detail::launch_step2<St>(d, src, dst, pass, dst2); break;
   }
 }
 

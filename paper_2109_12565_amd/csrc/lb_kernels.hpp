@@ -187,6 +187,7 @@ template <typename C>
 struct StepArgs {
   const void* src;          // post-collision populations f*(t) (or f(0))
   void* dst;                // receives f*(t+1)
+  void* dst2;               // fused kernel, kModeTape: receives the intermediate f*(t+1)
   const uint16_t* link;     // [ly*lx] link masks (solid cells present only)
   const uint8_t* solid;     // [ly*lx] 0 fluid, 1 bottom-held, 2 top-held
   const C* t_bottom;        // [lx]
@@ -212,8 +213,10 @@ enum : unsigned {
   kModeTauOne = 64u,  // tau = tau_g = 1: the collision returns the equilibria
   kModeStress = 128u, // with kModeFields: also write the xy stress fields
   kModeMoving = 256u, // the flat walls move (momentum term in their bounce-back)
-  kModeTopRow = 512u  // fused kernel: per-strip sums of T - t_top over the top row
+  kModeTopRow = 512u, // fused kernel: per-strip sums of T - t_top over the top row
                       // at both levels into partials (the taped run's loss terms)
+  kModeTape = 1024u   // fused kernel: also store the intermediate level's
+                      // populations into dst2 (the adjoint's segment recompute)
 };
 
 // rho0 (1 - exp(-rho/rho0)) of Eq. (12), evaluated as -rho0 expm1(-rho/rho0)

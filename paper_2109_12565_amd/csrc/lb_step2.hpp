@@ -204,6 +204,8 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   static_assert((kMode & (kModeWide | kModeInit | kModeObserve | kModeFields)) == 0,
                 "32-bit offsets, no observables");
   constexpr bool kTop = (kMode & kModeTopRow) != 0;
+  constexpr bool kTape = (kMode & kModeTape) != 0;
+  static_assert(!kTape || !St::kDev, "the tape holds FP64 / FP32 states");
   constexpr int kH = 5;          // left halo lanes
   constexpr int R1 = 5, RM = 3;  // density ring rows, moment ring rows
   constexpr int W = BT + 4;      // density ring row: lanes plus 2 padding columns each side
@@ -235,6 +237,7 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   const O plane_b = (O)a.pop_stride * sizeof(T);
   const PopMem<St, kMode> msrc(a.src, (uint64_t)plane_b * kPlaneUnits<St>);
   const PopMem<St, kMode> mdst(a.dst, (uint64_t)plane_b * kPlaneUnits<St>);
+  const PopMem<St, kMode> mtape(kTape ? a.dst2 : a.dst, (uint64_t)plane_b * kPlaneUnits<St>);
 
   // lane column (periodic); lanes kH .. kH + strip_w - 1 inside the lattice
   // store, the others compute halo columns only
@@ -322,9 +325,33 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
     const C ub2 = ubx * ubx + uby * uby;
     const C uh2 = hx * hx + hy * hy;
     Mom4<C>* m = sm[ring_slot<RM>(r)][cm];
-    m[0] = Mom4<C>{Da, uax, uay, ua2};
-    m[1] = Mom4<C>{Db, ubx, uby, ub2};
-    m[2] = Mom4<C>{Dt, hx, hy, uh2};
+    const Mom4<C> mv[3] = {{Da, uax, uay, ua2}, {Db, ubx, uby, ub2}, {Dt, hx, hy, uh2}};
+    m[0] = mv[0];
+    m[1] = mv[1];
+    m[2] = mv[2];
+    if constexpr (kTape) {
+      // the intermediate state f*(t+1) of the chunk's own rows, each value
+      // evaluated as level 2 pulls it (pull_level2, moving_sum)
+      if (out_lane && r >= y0 && r < y1) {
+        // S + D not contracted, as in pull_level2 and moving_sum
+#pragma clang fp contract(off)
+        const O yrow = (O)r * row_b;
+#pragma unroll
+        for (int fld = 0; fld < 3; ++fld) {
+          const O base = (O)(9 * fld) * plane_b + yrow;
+#define TLB_TAPE_PAIR(P)                                                        \
+  {                                                                             \
+    C S, D;                                                                     \
+    eq_even_odd<P>(mv[fld].rho, mv[fld].ux, mv[fld].uy, mv[fld].u2, S, D);      \
+    mtape.st(base + (O)P * plane_b, Lo.v0, S + D);                              \
+    mtape.st(base + (O)Dir<P>::opp * plane_b, Lo.v0, S - D);                    \
+  }
+          TLB_TAPE_PAIR(1) TLB_TAPE_PAIR(2) TLB_TAPE_PAIR(5) TLB_TAPE_PAIR(6)
+#undef TLB_TAPE_PAIR
+          mtape.st(base, Lo.v0, mv[fld].rho - moving_sum(mv[fld]));
+        }
+      }
+    }
   };
 
   // Level 2, phase 1: pull row r from the moment ring; densities and psi

@@ -156,8 +156,7 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
   // Fused two-step kernel: tau = tau_g = 1, any storage but fixed point, 32-bit
   // offsets. Its strips overlap by kStep2Halo columns and its
   // chunks recompute 5 rows of the first step on each side, so it pays
-  // where the chunks can be tall enough and the grid still fills every CU
-  // once: chunks of at least 6 rows, one block per resident slot.
+  // where the grid fills every CU once: one block per resident slot.
   // TLB_FUSED_ALWAYS selects it wherever it applies (FP64 included),
   // TLB_FUSED_NEVER never.
   const bool eligible = tau_one && !l.wide && p.precision != TLB_FIX16_DEV;
@@ -175,14 +174,16 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
     const long long slots = (long long)cus * std::max(per_cu2, 1);
     const long long max_chunks = std::max(1LL, slots / strips2);
     long long rows2 = (ly + max_chunks - 1) / max_chunks;
-    // it pays with chunks of at least 6 rows and at least two resident
-    // blocks per CU. Measured FP32 steps: 1024 x 512 (lattice resident in
-    // the MALL, halo rows cheap) 27.7 us fused with 6-row chunks against
-    // 36.3 us single (8 rows 32.1, 4 rows 39.3); 4096 x 2048 with 69-row
-    // chunks 263 us against 377 us. FP64 (139 KB of LDS, one block per CU)
-    // measured 1577 us per fused launch against 2 x 766 us of single steps
-    // at 4096 x 2048.
-    const bool pays = rows2 >= 6 && per_cu2 >= 2;
+    // with at least two resident blocks per CU it pays at every lattice size
+    // measured, the chunk height being the one that fills the slots once
+    // (FP32 per step, fused / single: 128 x 64 12.7 / 20.1 us, 1024 x 64
+    // 14.9 / 20.7, 1024 x 256 20.9 / 28.0, 1024 x 512 28.1 / 36.8, 2048 x
+    // 1024 68.7 / 101.5, 4096 x 2048 263 / 377; the 16-bit storages equal or
+    // faster); taller chunks in a second wave of blocks cost more than the
+    // halo rows they save. FP64 (139 KB of LDS, one block per CU) measured
+    // 1577 us per fused launch against 2 x 766 us of single steps at 4096 x
+    // 2048.
+    const bool pays = per_cu2 >= 2;
     if (per_cu2 > 0 && (pays || p.fused == TLB_FUSED_ALWAYS)) {
       if (p.fused_rows > 0) rows2 = p.fused_rows;
       l.rows2 = (int)(rows2 < ly ? rows2 : ly);
@@ -213,10 +214,10 @@ tlbh::Device device_view(const tlb_handle* h, double* fields = nullptr,
 }
 
 void launch_pass(const tlb_handle* h, tlbh::Pass pass, const void* src, void* dst,
-                 double* fields = nullptr, double* partials = nullptr) {
+                 double* fields = nullptr, double* partials = nullptr, void* dst2 = nullptr) {
   const tlbh::Device d = device_view(h, fields, partials);
   with_storage(h->p.precision,
-               [&](auto st) { tlbh::Launcher<decltype(st)>::step(d, pass, src, dst); });
+               [&](auto st) { tlbh::Launcher<decltype(st)>::step(d, pass, src, dst, dst2); });
 }
 
 // Re-run the step that produced f*(t) without storing, to evaluate the
@@ -958,7 +959,18 @@ int tlb_adjoint_step(tlb_handle* h, int64_t nsteps, double seed, double* grad_t_
       return j == 0 ? static_cast<char*>(h->ckpt) + (size_t)seg * sb
                     : static_cast<char*>(h->tape) + (size_t)(j - 1) * sb;
     };
-    for (int j = 1; j < len; ++j) launch_pass(h, tlbh::Pass::kStep, slot(j - 1), slot(j));
+    // recompute the segment's states: fused launches that also store the
+    // intermediate state where two more are needed, else single steps
+    for (int j = 1; j < len;) {
+      if (h->launch.rows2 > 0 && j + 1 < len) {
+        launch_pass(h, tlbh::Pass::kStep2Tape, slot(j - 1), slot(j + 1), nullptr, nullptr,
+                    slot(j));
+        j += 2;
+      } else {
+        launch_pass(h, tlbh::Pass::kStep, slot(j - 1), slot(j));
+        j += 1;
+      }
+    }
     // within a segment each reverse step also prepares the densities of the
     // next one's state (the previous slot); the segment's first step (j = 0)
     // cannot, the previous segment is not recomputed yet
