@@ -102,7 +102,12 @@ def adjoint_ratio(steps: int, ckpt: int, precision: str, config: str = "mid") ->
     recompute included) over the time of the plain forward, for the same
     `steps` steps of an emulsion with a noisy bottom temperature: the
     1024x512 lattice (its gradient is zero: in 500 steps no signal crosses
-    512 rows) or the 1024x64 strip (a live gradient)."""
+    512 rows) or the 1024x64 strip (a live gradient). ckpt = 1 keeps every
+    state in HBM (no recompute); tape_gib is the device memory of the
+    checkpoints plus the recompute tape. Steady state: a first taped run and
+    reverse sweep on the handle (from the initial state; their loss and
+    gradient are reported, and their time, allocation of the checkpoints and
+    the tape included, as first_call_ms) precede the timed calls."""
     import torch
 
     from paper_2109_12565_amd import Simulation
@@ -121,19 +126,26 @@ def adjoint_ratio(steps: int, ckpt: int, precision: str, config: str = "mid") ->
         torch.cuda.synchronize()
         return time.perf_counter() - t0, r
 
-    with make() as sim:  # warm both paths once (allocations, code loading)
+    with make() as sim:  # load the code of every kernel once
         sim.step(10)
-        sim.forward_taped(ckpt, ckpt)
-        sim.adjoint(ckpt)
+        warm = max(2 * ckpt, 10)
+        sim.forward_taped(warm, ckpt)
+        sim.adjoint(warm)
+    state_bytes = 27 * w["lx"] * w["ly"] * (8 if precision == "fp64" else 4)  # without row padding
     with make() as sim:
+        t_first_tape, loss = timed(lambda: sim.forward_taped(steps, ckpt))
+        t_first_adj, g = timed(lambda: sim.adjoint(steps))
+        t_tape, _ = timed(lambda: sim.forward_taped(steps, ckpt))
+        t_adj, _ = timed(lambda: sim.adjoint(steps))
         t_fwd, _ = timed(lambda: sim.step(steps))
-    with make() as sim:
-        t_tape, loss = timed(lambda: sim.forward_taped(steps, ckpt))
-        t_adj, g = timed(lambda: sim.adjoint(steps))
+    nck = -(-steps // ckpt)
+    tape_gib = (nck + ckpt - 1) * state_bytes / 2**30
     return {"workload": w["name"], "storage": precision, "steps": steps, "ckpt_every": ckpt,
+            "tape_gib": round(tape_gib, 2),
             "forward_ms": round(t_fwd * 1e3, 2), "taped_forward_ms": round(t_tape * 1e3, 2),
             "reverse_ms": round(t_adj * 1e3, 2),
-            "ratio": round((t_tape + t_adj) / t_fwd, 2), "loss": loss,
+            "ratio": round((t_tape + t_adj) / t_fwd, 2),
+            "first_call_ms": round((t_first_tape + t_first_adj) * 1e3, 2), "loss": loss,
             "grad_max_abs": float(np.abs(g).max())}
 
 
@@ -400,8 +412,11 @@ def main() -> int:
     if args.companions:
         out["companions"] = companion_runs(args.config, args.precision)
     if args.adjoint_steps > 0:
-        out["adjoint"] = adjoint_ratio(args.adjoint_steps, 25, "fp32")
-        out["adjoint_strip"] = adjoint_ratio(args.adjoint_steps, 25, "fp32", "strip")
+        # every state kept (28 GiB at 1024x512 over 500 steps), then
+        # checkpoints every 25 steps with segment recompute
+        out["adjoint"] = adjoint_ratio(args.adjoint_steps, 1, "fp32")
+        out["adjoint_ckpt"] = adjoint_ratio(args.adjoint_steps, 25, "fp32")
+        out["adjoint_strip"] = adjoint_ratio(args.adjoint_steps, 1, "fp32", "strip")
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.cpu_steps_1t)
     print(json.dumps(out), flush=True)

@@ -58,8 +58,9 @@ enum class Pass {
   kStep2,        // f*(t) -> f*(t+2), fused two-step kernel (Geometry::rows2 > 0)
   kStep2TopRow,  // same (flat walls at rest), and per strip the sums of T - t_top over
                  // the top row of both steps into Device::partials [2][strips]
-  kStep2Tape     // same (flat walls at rest, FP64 / FP32), and the intermediate state
+  kStep2Tape,    // same (flat walls at rest, FP64 / FP32), and the intermediate state
                  // f*(t+1) into a second buffer
+  kStep2TapeTopRow  // both: the intermediate state and the top-row sums
 };
 
 template <class St>
@@ -69,7 +70,7 @@ struct Launcher {
   // Resident blocks per CU of the two-step kernel; 0 where the storage has
   // no two-step kernel.
   static int step2_blocks_per_cu(bool solid);
-  // dst2: the second output of kStep2Tape
+  // dst2: the second output of kStep2Tape and kStep2TapeTopRow
   static void step(const Device& d, Pass pass, const void* src, void* dst, void* dst2 = nullptr);
   // f(0) = equilibria of the initial fields (rho_a, rho_b, temp, ux0, uy0;
   // the velocities may be null).

@@ -134,9 +134,11 @@ void launch_step2(const Device& d, const void* src, void* dst, Pass pass, void* 
       if (!d.moving && !d.has_solid) launch_step2_kernel<St, M | tlbk::kModeTopRow>(d, a);
       return;
     }
-    if (pass == Pass::kStep2Tape) {
+    if (pass == Pass::kStep2Tape || pass == Pass::kStep2TapeTopRow) {
       if constexpr (!St::kDev) {
-        if (!d.moving && !d.has_solid) launch_step2_kernel<St, M | tlbk::kModeTape>(d, a);
+        if (d.moving || d.has_solid) return;
+        if (pass == Pass::kStep2Tape) launch_step2_kernel<St, M | tlbk::kModeTape>(d, a);
+        else launch_step2_kernel<St, M | tlbk::kModeTape | tlbk::kModeTopRow>(d, a);
       }
       return;
     }
@@ -205,7 +207,8 @@ void Launcher<St>::step(const Device& d, Pass pass, const void* src, void* dst, 
       break;
     case Pass::kStep2:
     case Pass::kStep2TopRow:
-    case Pass::kStep2Tape: detail::launch_step2<St>(d, src, dst, pass, dst2); break;
+    case Pass::kStep2Tape:
+    case Pass::kStep2TapeTopRow: detail::launch_step2<St>(d, src, dst, pass, dst2); break;
   }
 }
 

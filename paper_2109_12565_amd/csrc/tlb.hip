@@ -894,7 +894,34 @@ int tlb_forward_taped(tlb_handle* h, int64_t nsteps, int32_t ckpt_every, double*
   // single steps with the top-row sum of their pulled state.
   const int stride = loss_stride(h);
   const bool fused = h->launch.rows2 > 0;
-  for (int64_t k = 0; k < nsteps;) {
+  auto top_row = [&](const void* state, int64_t k) {
+    with_adjoint_storage(h, [&](auto st) {
+      tlbh::Adjoint<decltype(st)>::top_row_term(d, w, state, (int)k, stride);
+    });
+  };
+  if (ckpt_every == 1) {
+    // Full tape: the steps write every state f*(t0 + k), k < nsteps, straight
+    // into its slot (a fused pair also stores the state between its two
+    // steps), so the reverse sweep recomputes nothing. The last step runs
+    // from the handle's buffer, which then holds f*(t-1) as after tlb_step.
+    auto slot = [&](int64_t k) { return static_cast<char*>(h->ckpt) + (size_t)k * sb; };
+    TLB_HIP(h, hipMemcpyAsync(slot(0), h->buf[h->cur], sb, hipMemcpyDeviceToDevice, h->stream));
+    int64_t k = 0;
+    for (; fused && k + 2 < nsteps; k += 2)
+      launch_pass(h, tlbh::Pass::kStep2TapeTopRow, slot(k), slot(k + 2), nullptr,
+                  w.loss_terms + (size_t)k * stride, slot(k + 1));
+    for (; k + 1 < nsteps; ++k) {
+      top_row(slot(k), k);
+      launch_pass(h, tlbh::Pass::kStep, slot(k), slot(k + 1));
+    }
+    TLB_HIP(h, hipMemcpyAsync(h->buf[h->cur], slot(nsteps - 1), sb, hipMemcpyDeviceToDevice,
+                              h->stream));
+    top_row(h->buf[h->cur], nsteps - 1);
+    launch_pass(h, tlbh::Pass::kStep, h->buf[h->cur], h->buf[1 - h->cur]);
+    h->cur = 1 - h->cur;
+    h->t += nsteps;
+  }
+  for (int64_t k = 0; ckpt_every > 1 && k < nsteps;) {
     if (k % ckpt_every == 0)
       TLB_HIP(h, hipMemcpyAsync(static_cast<char*>(h->ckpt) + (size_t)(k / ckpt_every) * sb,
                                 h->buf[h->cur], sb, hipMemcpyDeviceToDevice, h->stream));
@@ -906,9 +933,7 @@ int tlb_forward_taped(tlb_handle* h, int64_t nsteps, int32_t ckpt_every, double*
       k += 2;
       continue;
     }
-    with_adjoint_storage(h, [&](auto st) {
-      tlbh::Adjoint<decltype(st)>::top_row_term(d, w, h->buf[h->cur], (int)k, stride);
-    });
+    top_row(h->buf[h->cur], k);
     launch_pass(h, tlbh::Pass::kStep, h->buf[h->cur], h->buf[1 - h->cur]);
     h->cur = 1 - h->cur;
     h->t += 1;
@@ -951,7 +976,7 @@ int tlb_adjoint_step(tlb_handle* h, int64_t nsteps, double seed, double* grad_t_
   const tlbh::Device d = device_view(h);
   const int64_t nck = (nsteps + K - 1) / K;
   int in = 0;
-  bool first = true;
+  bool first = true, ready = false;
   for (int64_t seg = nck - 1; seg >= 0; --seg) {
     const int64_t s0 = seg * K;
     const int len = (int)std::min<int64_t>(K, nsteps - s0);
@@ -973,10 +998,13 @@ int tlb_adjoint_step(tlb_handle* h, int64_t nsteps, double seed, double* grad_t_
     }
     // within a segment each reverse step also prepares the densities of the
     // next one's state (the previous slot); the segment's first step (j = 0)
-    // cannot, the previous segment is not recomputed yet
-    bool ready = false;
+    // cannot, the previous segment is not recomputed yet, except with the
+    // full tape (ckpt_every = 1), whose previous state is a checkpoint
+    if (K > 1) ready = false;
     for (int j = len - 1; j >= 0; --j) {
-      void* next = j > 0 ? slot(j - 1) : nullptr;
+      void* next = j > 0    ? slot(j - 1)
+                   : K == 1 && seg > 0 ? static_cast<char*>(h->ckpt) + (size_t)(seg - 1) * sb
+                                       : nullptr;
       with_adjoint_storage(h, [&](auto st) {
         tlbh::Adjoint<decltype(st)>::reverse_step(d, w, slot(j), in, kappa_top, next, ready, first);
       });

@@ -188,6 +188,35 @@ def test_fused_taped_run_matches_fused_steps_and_single_step_adjoint():
         assert np.abs(g - ref_g).max() <= 1e-11 * scale
 
 
+@pytest.mark.parametrize("n", [30, 31])
+def test_full_tape_fused_run_matches_steps_and_oracle(n):
+    """ckpt_every = 1 keeps every state, written by the steps themselves
+    (fused pairs store the state between their two steps); the run advances
+    bitwise like tlb_step, the other buffer holds the previous state (the
+    fields of the current time agree), and loss and gradient match the
+    oracle adjoint and the checkpointed run (FP64)."""
+    case = buoyant_case()
+    fused = {"fused": "always"}
+    with make_sim(case, "fp64", launch=fused) as a, make_sim(case, "fp64", launch=fused) as b, \
+            make_sim(case, "fp64", launch=fused) as c:
+        assert a.launch_info()["fused_rows"] > 0
+        loss = a.forward_taped(n, 1)
+        b.step(n)
+        assert np.array_equal(a.populations(), b.populations())
+        fa, fb = a.fields(), b.fields()
+        for k in fa:
+            assert np.array_equal(fa[k], fb[k]), k
+        ref_loss = c.forward_taped(n, 7)
+        assert loss == pytest.approx(ref_loss, rel=1e-13)
+        g, ref_g = a.adjoint(n), c.adjoint(n)
+    lo, go = oracle_loss_and_grad(case, case["t_bottom"], n)
+    assert abs(loss - lo) <= 1e-12 * abs(lo)
+    scale = np.abs(go).max()
+    assert scale > 1e-6
+    assert np.abs(g - go).max() <= 1e-10 * scale
+    assert np.abs(g - ref_g).max() <= 1e-11 * scale
+
+
 def test_autograd_function_matches_adjoint():
     case = buoyant_case()
     n = 20
