@@ -30,8 +30,9 @@
 // straight through, so dL/d f_{l,i}(t) at a node is rbar_l + c_i.jbar and
 // dL/d g_i(t) is tbar, five numbers per node: adj_local writes those (planes
 // 0..4 of fbar: rbar_A, rbar_B, jbar_x, jbar_y, tbar) instead of 27 values,
-// adj_scatter adds the stencil transpose to rbar_l, and adj_pull gathers the
-// five numbers of each source node.
+// adj_scatter adds the stencil transpose to rbar_l, and the next reverse
+// step's adj_local gathers lambda from the five numbers of each source node
+// (no adj_pull; adj_scatter takes over its T_b gradient and densities).
 #pragma once
 
 #include "lb_kernels.hpp"
@@ -91,6 +92,14 @@ struct AdjTile {
   C v[NF][kAdjTH][kAdjTW];
 };
 
+// Lattice column of tile column x (x >= -kAdjHalo, lx >= 3): one period
+// folds it, except on lattices narrower than a tile.
+__device__ inline int tile_column(int x, int lx) {
+  if (x < 0) x += lx;
+  if (x >= lx) x = x - lx < lx ? x - lx : x % lx;
+  return x;
+}
+
 // Fill the tile of the block at (x0, y0): field f of cell (cx, cy) is
 // load(f, x, y) at the lattice node (x, y), or wall[f] outside the rows.
 template <typename C, int NF, class Load>
@@ -98,7 +107,7 @@ __device__ inline void fill_tile(AdjTile<C, NF>& t, int x0, int y0, int lx, int 
                                  const C (&wall)[NF], Load load) {
   for (int c = threadIdx.x; c < kAdjTW * kAdjTH; c += 256) {
     const int cx = c % kAdjTW, cy = c / kAdjTW;
-    const int x = ((x0 - kAdjHalo + cx) % lx + lx) % lx, y = y0 - kAdjHalo + cy;
+    const int x = tile_column(x0 - kAdjHalo + cx, lx), y = y0 - kAdjHalo + cy;
     const bool in = y >= 0 && y < ly;
 #pragma unroll
     for (int f = 0; f < NF; ++f) t.v[f][cy][cx] = in ? load(f, x, y) : wall[f];
@@ -189,19 +198,105 @@ __global__ __launch_bounds__(256) void adj_top_row_sum(AdjArgs<typename St::C> a
 // Compact planes of the tau = 1 form (in the fbar array).
 constexpr int kCompactRbar = 0, kCompactJx = 2, kCompactJy = 3, kCompactT = 4;
 
+// Weighted moments of nine values v_i over the D2Q9 directions: sum w_i v_i,
+// sum w_i v_i c_i and the three distinct entries of sum w_i v_i c_i c_i.
+template <typename C>
+struct WMom {
+  C m0, mx, my, mxx, myy, mxy;
+};
+
+template <typename C>
+__device__ inline WMom<C> weighted_moments(const C* v) {
+  constexpr C w0 = w_c2<C>(0), w1 = w_c2<C>(1), w2 = w_c2<C>(2);
+  const C ax = v[1] + v[3], ay = v[2] + v[4];
+  const C dp = v[5] + v[7], dm = v[6] + v[8];
+  const C d = dp + dm;
+  const C r = v[5] - v[7];
+  WMom<C> m;
+  m.m0 = w0 * v[0] + w1 * (ax + ay) + w2 * d;
+  m.mx = w1 * (v[1] - v[3]) + w2 * (r + (v[8] - v[6]));
+  m.my = w1 * (v[2] - v[4]) + w2 * (r + (v[6] - v[8]));
+  m.mxx = w1 * ax + w2 * d;
+  m.myy = w1 * ay + w2 * d;
+  m.mxy = w2 * (dp - dm);
+  return m;
+}
+
+// Adjoint of the equilibrium w_i rho (1 + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u^2)
+// (Eqs. (2), (3), (16)): given the weighted moments m of the sensitivities
+// of the nine values, adds d/drho to rbar and d/du to ubar.
+template <typename C>
+__device__ inline void eq_adjoint(const WMom<C>& m, C rho, C ux, C uy, C& rbar, C& ubx, C& uby) {
+  const C qx = m.mxx * ux + m.mxy * uy, qy = m.mxy * ux + m.myy * uy;
+  const C u2 = ux * ux + uy * uy;
+  rbar += m.m0 * (C(1) - C(1.5) * u2) + C(3) * (m.mx * ux + m.my * uy) + C(4.5) * (qx * ux + qy * uy);
+  ubx += rho * (C(3) * m.mx + C(9) * qx - C(3) * ux * m.m0);
+  uby += rho * (C(3) * m.my + C(9) * qy - C(3) * uy * m.m0);
+}
+
+// Pair-difference sums of a 5 x 5 stencil of tile field v around (cy0, cx0):
+// sum over c != 0 of p(|c|^2) v(x + c) c (q) and of the nearest-neighbour
+// w(|c|^2) v(x + c) c (n), each pair c, -c as one difference.
+template <typename C, int NF>
+__device__ inline void stencil_sums(const AdjTile<C, NF>& t, int f, int cy0, int cx0, C (&q)[2],
+                                    C (&n)[2]) {
+  q[0] = q[1] = n[0] = n[1] = C(0);
+#pragma unroll
+  for (int dy = -2; dy <= 2; ++dy)
+#pragma unroll
+    for (int dx = 1; dx <= 2; ++dx) {
+      const int c2 = dx * dx + dy * dy;
+      const C diff = t.v[f][cy0 + dy][cx0 + dx] - t.v[f][cy0 + dy][cx0 - dx];
+      q[0] += (p_c2<C>(c2) * C(dx)) * diff;
+      if (c2 <= 2) n[0] += (w_c2<C>(c2) * C(dx)) * diff;
+    }
+#pragma unroll
+  for (int dx = -2; dx <= 2; ++dx)
+#pragma unroll
+    for (int dy = 1; dy <= 2; ++dy) {
+      const int c2 = dx * dx + dy * dy;
+      const C diff = t.v[f][cy0 + dy][cx0 + dx] - t.v[f][cy0 - dy][cx0 + dx];
+      q[1] += (p_c2<C>(c2) * C(dy)) * diff;
+      if (c2 <= 2) n[1] += (w_c2<C>(c2) * C(dy)) * diff;
+    }
+}
+
+// Nearest-neighbour sum of w(|c|^2) v(x + c) c only.
+template <typename C, int NF>
+__device__ inline void nn_sums(const AdjTile<C, NF>& t, int f, int cy0, int cx0, C (&n)[2]) {
+  n[0] = n[1] = C(0);
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+    n[0] += w_c2<C>(1 + dy * dy) * (t.v[f][cy0 + dy][cx0 + 1] - t.v[f][cy0 + dy][cx0 - 1]);
+#pragma unroll
+  for (int dx = -1; dx <= 1; ++dx)
+    n[1] += w_c2<C>(1 + dx * dx) * (t.v[f][cy0 + 1][cx0 + dx] - t.v[f][cy0 - 1][cx0 + dx]);
+}
+
+// Tile fields of adj_local: densities and pseudopotentials of the pulled
+// state (0..3), and at tau = 1 the previous reverse step's dL/drho_l (4, 5),
+// jbar (6, 7) and tbar (8) from which lambda(t+1) is gathered.
+constexpr int kLocRho = 0, kLocPsi = 2, kLocR = 4, kLocJ = 6, kLocT = 8;
+
 template <class St, bool kTauOne>
 __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
   using C = typename St::C;
   const StepArgs<C>& s = a.s;
-  // densities and pseudopotentials of the tile and its halo (fields rho_A,
-  // rho_B, psi_A, psi_B; the wall rows carry the wetting values)
-  __shared__ AdjTile<C, 4> tile;
+  constexpr int NF = kTauOne ? 9 : 4;
+  __shared__ AdjTile<C, NF> tile;
   const int x0 = blockIdx.x * kAdjTX, y0 = blockIdx.y * kAdjTY;
   {
-    const C pw0 = psi_exp(s.rho_wall0, s.rho0, s.inv_rho0), pw1 = psi_exp(s.rho_wall1, s.rho0, s.inv_rho0);
-    const C wall[4] = {s.rho_wall0, s.rho_wall1, pw0, pw1};
-    fill_tile(tile, x0, y0, s.lx, s.ly, wall,
-              [&](int f, int xx, int yy) { return a.aux[plane_index(s, f, xx, yy)]; });
+    // wall rows: the wetting densities; no lambda is gathered from them
+    C wall[NF] = {s.rho_wall0, s.rho_wall1, psi_exp(s.rho_wall0, s.rho0, s.inv_rho0),
+                  psi_exp(s.rho_wall1, s.rho0, s.inv_rho0)};
+    for (int f = 4; f < NF; ++f) wall[f] = C(0);
+    const bool prev = a.have_prev != 0;
+    fill_tile(tile, x0, y0, s.lx, s.ly, wall, [&](int f, int xx, int yy) -> C {
+      if (f < 4) return a.aux[plane_index(s, f, xx, yy)];
+      if (!prev) return C(0);
+      return f < kLocJ ? a.rbar_prev[plane_index(s, f - kLocR, xx, yy)]
+                       : a.cmp_prev[plane_index(s, kCompactJx + f - kLocJ, xx, yy)];
+    });
   }
   __syncthreads();
   const int tx = threadIdx.x % kAdjTX, ty = threadIdx.x / kAdjTX;
@@ -214,32 +309,19 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
   // ---- forward recompute
   const C ra = sum9(f), rb = sum9(f + 9), temp = sum9(g);
   const C jx = momentum_x(f, f + 9), jy = momentum_y(f, f + 9);
-  const C rho = ra + rb, inv_rho = C(1) / rho;
+  const C rl[2] = {ra, rb};
+  const C inv_rl[2] = {C(1) / ra, C(1) / rb};
+  const C inv_rho = C(1) / (ra + rb);
   const C ux = jx * inv_rho, uy = jy * inv_rho;
-  C Sa[2][2], Sr[2][2], X[2][2], ps[2], dps[2], rl[2] = {ra, rb};
+  // Sr: 25-point sums of psi_l, Sa: nearest-neighbour sums of psi_l, X:
+  // nearest-neighbour sums of the other component's density
+  C Sa[2][2], Sr[2][2], X[2][2], ps[2], dps[2];
   for (int l = 0; l < 2; ++l) {
-    ps[l] = tile.v[2 + l][cy0][cx0];
+    ps[l] = tile.v[kLocPsi + l][cy0][cx0];
     dps[l] = C(1) - ps[l] * s.inv_rho0;  // d psi / d rho = exp(-rho / rho0)
-    Sa[l][0] = Sa[l][1] = Sr[l][0] = Sr[l][1] = X[l][0] = X[l][1] = C(0);
+    stencil_sums(tile, kLocPsi + l, cy0, cx0, Sr[l], Sa[l]);
+    nn_sums(tile, kLocRho + 1 - l, cy0, cx0, X[l]);
   }
-  for (int dy = -2; dy <= 2; ++dy)
-    for (int dx = -2; dx <= 2; ++dx) {
-      if (dx == 0 && dy == 0) continue;
-      const int c2 = dx * dx + dy * dy;
-      const C pw = p_c2<C>(c2), ww = w_c2<C>(c2);
-      for (int l = 0; l < 2; ++l) {
-        const C v = tile.v[2 + l][cy0 + dy][cx0 + dx];
-        Sr[l][0] += pw * v * C(dx);
-        Sr[l][1] += pw * v * C(dy);
-        if (c2 <= 2) {
-          Sa[l][0] += ww * v * C(dx);
-          Sa[l][1] += ww * v * C(dy);
-          const C r = tile.v[1 - l][cy0 + dy][cx0 + dx];  // other component
-          X[l][0] += ww * r * C(dx);
-          X[l][1] += ww * r * C(dy);
-        }
-      }
-    }
   const C gcross = s.g12 * s.inv_rho0 * s.inv_rho0;
   const C ga[2] = {s.ga0, s.ga1}, gr[2] = {s.gr0, s.gr1};
   C F[2][2];
@@ -251,83 +333,72 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
   const C Fx = F[0][0] + F[1][0], Fy = F[0][1] + F[1][1];
   C ul[2][2];
   for (int l = 0; l < 2; ++l) {
-    ul[l][0] = ux + s.tau * F[l][0] / rl[l];
-    ul[l][1] = uy + s.tau * F[l][1] / rl[l];
+    ul[l][0] = ux + s.tau * F[l][0] * inv_rl[l];
+    ul[l][1] = uy + s.tau * F[l][1] * inv_rl[l];
   }
   const C hx = ux + Fx * C(0.5) * inv_rho, hy = uy + Fy * C(0.5) * inv_rho;
 
   // ---- lambda(t+1) of the node: loaded, or at tau = 1 gathered from the
-  // previous reverse step's compact planes (the transpose of the pull: the
+  // previous reverse step's compact values (the transpose of the pull: the
   // population this node streamed in direction i was pulled by x + c_i, or
   // bounced back into the node itself across a wall)
   C lamv[27];
   if constexpr (kTauOne) {
-    const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    const bool lo = y == 0, hi = y == s.ly - 1;
+    const C rA = tile.v[kLocR][cy0][cx0], rB = tile.v[kLocR + 1][cy0][cx0];
+    const C Jx = tile.v[kLocJ][cy0][cx0], Jy = tile.v[kLocJ + 1][cy0][cx0];
+    const C tt = tile.v[kLocT][cy0][cx0];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const int nx = wrapx(s, x + dir_cx(i)), ny = y + dir_cy(i);
-      const bool wall = ny < 0 || ny >= s.ly;
-      const int sx = wall ? x : nx, sy = wall ? y : ny, si = wall ? opp[i] : i;
-      C r0 = 0, r1 = 0, t = 0, cj = 0;
-      if (a.have_prev) {
-        const C jx = a.cmp_prev[plane_index(s, kCompactJx, sx, sy)];
-        const C jy = a.cmp_prev[plane_index(s, kCompactJy, sx, sy)];
-        cj = C(dir_cx(si)) * jx + C(dir_cy(si)) * jy;
-        r0 = a.rbar_prev[plane_index(s, 0, sx, sy)];
-        r1 = a.rbar_prev[plane_index(s, 1, sx, sy)];
-        t = a.cmp_prev[plane_index(s, kCompactT, sx, sy)];
+      const int cx = dir_cx(i), cy = dir_cy(i);
+      const int ny = cy0 + cy, nx = cx0 + cx;
+      const C cj = C(cx) * tile.v[kLocJ][ny][nx] + C(cy) * tile.v[kLocJ + 1][ny][nx];
+      C la = tile.v[kLocR][ny][nx] + cj, lb = tile.v[kLocR + 1][ny][nx] + cj;
+      C lt = tile.v[kLocT][ny][nx];
+      if (cy != 0) {
+        // across a wall: the node's own values in direction opp(i)
+        const bool wall = cy < 0 ? lo : hi;
+        const C oj = C(cx) * Jx + C(cy) * Jy;
+        la = wall ? rA - oj : la;
+        lb = wall ? rB - oj : lb;
+        lt = wall ? -tt : lt;
       }
-      lamv[i] = r0 + cj;
-      lamv[9 + i] = r1 + cj;
-      lamv[18 + i] = wall ? -t : t;
+      lamv[i] = la;
+      lamv[9 + i] = lb;
+      lamv[18 + i] = lt;
     }
   } else {
 #pragma unroll
     for (int p = 0; p < 27; ++p) lamv[p] = a.lam_next[plane_index(s, p, x, y)];
   }
 
-  // ---- adjoint of the BGK relaxation and of the equilibria
-  const C ka = C(1) - s.inv_tau, kg = C(1) - s.inv_tau_g;
-  C fb[18], gb[9];
+  // ---- adjoint of the BGK relaxation and of the equilibria: the
+  // equilibria take (1 - ka) lambda, the kept part ka lambda (zero at tau = 1)
   C rbar[2] = {0, 0}, ubar[2][2] = {{0, 0}, {0, 0}}, tbar = 0, hbar[2] = {0, 0};
-  for (int l = 0; l < 2; ++l) {
-    const C u2 = ul[l][0] * ul[l][0] + ul[l][1] * ul[l][1];
-    for (int i = 0; i < 9; ++i) {
-      const C cx = C(dir_cx(i)), cy = C(dir_cy(i)), w = w_dir<C>(i);
-      const C lam = lamv[9 * l + i];
-      fb[9 * l + i] = ka * lam;
-      const C e = (C(1) - ka) * lam;  // adjoint of f^eq_i
-      const C cu = cx * ul[l][0] + cy * ul[l][1];
-      rbar[l] += e * w * (C(1) + C(3) * cu + C(4.5) * cu * cu - C(1.5) * u2);
-      const C k = e * w * rl[l];
-      ubar[l][0] += k * (C(3) * cx + C(9) * cu * cx - C(3) * ul[l][0]);
-      ubar[l][1] += k * (C(3) * cy + C(9) * cu * cy - C(3) * ul[l][1]);
-    }
-  }
   {
-    const C u2 = hx * hx + hy * hy;
-    for (int i = 0; i < 9; ++i) {
-      const C cx = C(dir_cx(i)), cy = C(dir_cy(i)), w = w_dir<C>(i);
-      const C lam = lamv[18 + i];
-      gb[i] = kg * lam;
-      const C e = (C(1) - kg) * lam;
-      const C cu = cx * hx + cy * hy;
-      tbar += e * w * (C(1) + C(3) * cu + C(4.5) * cu * cu - C(1.5) * u2);
-      const C k = e * w * temp;
-      hbar[0] += k * (C(3) * cx + C(9) * cu * cx - C(3) * hx);
-      hbar[1] += k * (C(3) * cy + C(9) * cu * cy - C(3) * hy);
+    WMom<C> m[3] = {weighted_moments(lamv), weighted_moments(lamv + 9), weighted_moments(lamv + 18)};
+    if constexpr (!kTauOne) {
+      for (int k = 0; k < 3; ++k) {
+        const C e = k < 2 ? s.inv_tau : s.inv_tau_g;
+        m[k] = {e * m[k].m0, e * m[k].mx, e * m[k].my, e * m[k].mxx, e * m[k].myy, e * m[k].mxy};
+      }
     }
+    eq_adjoint(m[0], ra, ul[0][0], ul[0][1], rbar[0], ubar[0][0], ubar[0][1]);
+    eq_adjoint(m[1], rb, ul[1][0], ul[1][1], rbar[1], ubar[1][0], ubar[1][1]);
+    eq_adjoint(m[2], temp, hx, hy, tbar, hbar[0], hbar[1]);
   }
   // ---- velocities: u_l = u + tau F_l / rho_l, u^H = u + F / (2 rho), u = j / rho
-  C Fbar[2][2], uc[2] = {ubar[0][0] + ubar[1][0] + hbar[0], ubar[0][1] + ubar[1][1] + hbar[1]};
-  C rtot = C(0);
+  C Fbar[2][2];
+  const C uc[2] = {ubar[0][0] + ubar[1][0] + hbar[0], ubar[0][1] + ubar[1][1] + hbar[1]};
+  const C hh = C(0.5) * inv_rho;
   for (int l = 0; l < 2; ++l) {
-    for (int d = 0; d < 2; ++d) Fbar[l][d] = s.tau * ubar[l][d] / rl[l] + hbar[d] * C(0.5) * inv_rho;
-    rbar[l] -= s.tau * (ubar[l][0] * F[l][0] + ubar[l][1] * F[l][1]) / (rl[l] * rl[l]);
+    const C ti = s.tau * inv_rl[l];
+    for (int d = 0; d < 2; ++d) Fbar[l][d] = ti * ubar[l][d] + hbar[d] * hh;
+    rbar[l] -= ti * inv_rl[l] * (ubar[l][0] * F[l][0] + ubar[l][1] * F[l][1]);
   }
-  rtot -= (hbar[0] * Fx + hbar[1] * Fy) * C(0.5) * inv_rho * inv_rho;
+  const C rtot = -(hbar[0] * Fx + hbar[1] * Fy) * hh * inv_rho -
+                 (uc[0] * jx + uc[1] * jy) * inv_rho * inv_rho;
   const C jbx = uc[0] * inv_rho, jby = uc[1] * inv_rho;
-  rtot -= (uc[0] * jx + uc[1] * jy) * inv_rho * inv_rho;
   rbar[0] += rtot;
   rbar[1] += rtot;
   // ---- the node's own terms of the forces
@@ -344,26 +415,25 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
   }
   // ---- moments (and the loss term of the top row: dL/dT = kappa_top)
   if (y == s.ly - 1) tbar += a.kappa_top;
+  for (int l = 0; l < 2; ++l)
+    for (int d = 0; d < 2; ++d) a.Fbar[plane_index(s, 2 * l + d, x, y)] = Fbar[l][d];
   if constexpr (kTauOne) {
     a.fbar[plane_index(s, kCompactRbar, x, y)] = rbar[0];
     a.fbar[plane_index(s, kCompactRbar + 1, x, y)] = rbar[1];
     a.fbar[plane_index(s, kCompactJx, x, y)] = jbx;
     a.fbar[plane_index(s, kCompactJy, x, y)] = jby;
     a.fbar[plane_index(s, kCompactT, x, y)] = tbar;
-    for (int l = 0; l < 2; ++l)
-      for (int d = 0; d < 2; ++d) a.Fbar[plane_index(s, 2 * l + d, x, y)] = Fbar[l][d];
-    return;
+  } else {
+    const C ka = C(1) - s.inv_tau, kg = C(1) - s.inv_tau_g;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const C cx = C(dir_cx(i)), cy = C(dir_cy(i));
+      const C cj = cx * jbx + cy * jby;
+      a.fbar[plane_index(s, i, x, y)] = ka * lamv[i] + (rbar[0] + cj);
+      a.fbar[plane_index(s, 9 + i, x, y)] = ka * lamv[9 + i] + (rbar[1] + cj);
+      a.fbar[plane_index(s, 18 + i, x, y)] = kg * lamv[18 + i] + tbar;
+    }
   }
-  for (int i = 0; i < 9; ++i) {
-    const C cx = C(dir_cx(i)), cy = C(dir_cy(i));
-    fb[i] += rbar[0] + cx * jbx + cy * jby;
-    fb[9 + i] += rbar[1] + cx * jbx + cy * jby;
-    gb[i] += tbar;
-  }
-  for (int p = 0; p < 18; ++p) a.fbar[plane_index(s, p, x, y)] = fb[p];
-  for (int i = 0; i < 9; ++i) a.fbar[plane_index(s, 18 + i, x, y)] = gb[i];
-  for (int l = 0; l < 2; ++l)
-    for (int d = 0; d < 2; ++d) a.Fbar[plane_index(s, 2 * l + d, x, y)] = Fbar[l][d];
 }
 
 // dL/dT_b(c) += sum of 2 w_i gbar_i(x, 0) over the bottom links whose solid
@@ -383,21 +453,36 @@ __device__ inline void grad_tb_column(const AdjArgs<typename St::C>& a, int c) {
 
 // Transpose of the force stencils: rho_l(x') enters the self forces of its
 // 24 neighbours through psi_l and the cross forces of the other component's
-// 8 neighbours through rho_l / rho0.
+// 8 neighbours through rho_l / rho0. With H_l = psi_l Fbar_l and K_l = rho_l
+// Fbar_l of each node (formed as the tile is filled), dL/dpsi_l(x) gets
+// -sum_c (ga_l w + gr_l p)(|c|^2) c.H_l(x - c) and dL/drho_{1-l}(x) gets
+// -g12/rho0^2 sum_c w(|c|^2) c.K_l(x - c), each pair c, -c as one difference.
 template <class St, bool kTauOne>
 __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
   using C = typename St::C;
   const StepArgs<C>& s = a.s;
-  // F-bar (A_x, A_y, B_x, B_y), rho_A, rho_B, psi_A, psi_B of the tile and
-  // its halo (no force beyond the walls)
+  // H_A (x, y), H_B (x, y), K_A (x, y), K_B (x, y) of the tile and its
+  // halo; zero beyond the walls (no force there)
   __shared__ AdjTile<C, 8> tile;
   const int x0 = blockIdx.x * kAdjTX, y0 = blockIdx.y * kAdjTY;
-  {
-    const C wall[8] = {C(0), C(0), C(0), C(0), s.rho_wall0, s.rho_wall1,
-                       psi_exp(s.rho_wall0, s.rho0, s.inv_rho0), psi_exp(s.rho_wall1, s.rho0, s.inv_rho0)};
-    fill_tile(tile, x0, y0, s.lx, s.ly, wall, [&](int f, int xx, int yy) {
-      return f < 4 ? a.Fbar[plane_index(s, f, xx, yy)] : a.aux[plane_index(s, f - 4, xx, yy)];
-    });
+  for (int c = threadIdx.x; c < kAdjTW * kAdjTH; c += 256) {
+    const int cx = c % kAdjTW, cy = c / kAdjTW;
+    const int xx = tile_column(x0 - kAdjHalo + cx, s.lx), yy = y0 - kAdjHalo + cy;
+    const bool in = yy >= 0 && yy < s.ly;
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      C fx = 0, fy = 0, r = 0, p = 0;
+      if (in) {
+        fx = a.Fbar[plane_index(s, 2 * l, xx, yy)];
+        fy = a.Fbar[plane_index(s, 2 * l + 1, xx, yy)];
+        r = a.aux[plane_index(s, l, xx, yy)];
+        p = a.aux[plane_index(s, 2 + l, xx, yy)];
+      }
+      tile.v[2 * l][cy][cx] = p * fx;
+      tile.v[2 * l + 1][cy][cx] = p * fy;
+      tile.v[4 + 2 * l][cy][cx] = r * fx;
+      tile.v[5 + 2 * l][cy][cx] = r * fy;
+    }
   }
   __syncthreads();
   const int tx = threadIdx.x % kAdjTX, ty = threadIdx.x / kAdjTX;
@@ -406,30 +491,53 @@ __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
   const int cx0 = tx + kAdjHalo, cy0 = ty + kAdjHalo;
   const C gcross = s.g12 * s.inv_rho0 * s.inv_rho0;
   const C ga[2] = {s.ga0, s.ga1}, gr[2] = {s.gr0, s.gr1};
-  C psibar[2] = {0, 0}, rb[2] = {0, 0};
-  for (int dy = -2; dy <= 2; ++dy) {
-    // rows beyond the walls carry no force (F-bar is zero there)
-    if (y - dy < 0 || y - dy >= s.ly) continue;
-    for (int dx = -2; dx <= 2; ++dx) {
-      if (dx == 0 && dy == 0) continue;
-      // neighbour x - c whose stencil reaches this node with offset c
-      const int ncx = cx0 - dx, ncy = cy0 - dy;
+  C v[2];
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+    // sum over pairs of coef(|c|^2) c.(H(x - c) - H(x + c)), half-plane c
+    C acc = 0;
+    auto pair = [&](int dx, int dy) {
       const int c2 = dx * dx + dy * dy;
-      const C pw = p_c2<C>(c2), ww = w_c2<C>(c2);
-      for (int l = 0; l < 2; ++l) {
-        const C fx = tile.v[2 * l][ncy][ncx], fy = tile.v[2 * l + 1][ncy][ncx];
-        const C dot = fx * C(dx) + fy * C(dy);
-        psibar[l] -= tile.v[6 + l][ncy][ncx] * (ga[l] * ww + gr[l] * pw) * dot;
-        if (c2 <= 2) rb[1 - l] -= gcross * tile.v[4 + l][ncy][ncx] * ww * dot;
-      }
-    }
+      const C coef = ga[l] * w_c2<C>(c2) + gr[l] * p_c2<C>(c2);
+      C dot = 0;
+      if (dx != 0)
+        dot = C(dx) * (tile.v[2 * l][cy0 - dy][cx0 - dx] - tile.v[2 * l][cy0 + dy][cx0 + dx]);
+      if (dy != 0)
+        dot += C(dy) * (tile.v[2 * l + 1][cy0 - dy][cx0 - dx] - tile.v[2 * l + 1][cy0 + dy][cx0 + dx]);
+      acc += coef * dot;
+    };
+    pair(1, 0);
+    pair(2, 0);
+#pragma unroll
+    for (int dy = 1; dy <= 2; ++dy)
+#pragma unroll
+      for (int dx = -2; dx <= 2; ++dx) pair(dx, dy);
+    v[l] = -acc;
+  }
+  C cr[2];  // cross terms, by the component they act on
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+    C acc = 0;
+    auto pair = [&](int dx, int dy) {
+      C dot = 0;
+      if (dx != 0)
+        dot = C(dx) * (tile.v[4 + 2 * l][cy0 - dy][cx0 - dx] - tile.v[4 + 2 * l][cy0 + dy][cx0 + dx]);
+      if (dy != 0)
+        dot += C(dy) * (tile.v[5 + 2 * l][cy0 - dy][cx0 - dx] - tile.v[5 + 2 * l][cy0 + dy][cx0 + dx]);
+      acc += w_c2<C>(dx * dx + dy * dy) * dot;
+    };
+    pair(1, 0);
+    pair(-1, 1);
+    pair(0, 1);
+    pair(1, 1);
+    cr[1 - l] = -gcross * acc;
   }
   for (int l = 0; l < 2; ++l) {
-    const C dps = C(1) - tile.v[6 + l][cy0][cx0] * s.inv_rho0;
-    C v = rb[l] + psibar[l] * dps;
+    const C dps = C(1) - a.aux[plane_index(s, 2 + l, x, y)] * s.inv_rho0;
+    C r = cr[l] + v[l] * dps;
     // tau = 1: the node's own dL/drho_l joins it (one plane to gather later)
-    if constexpr (kTauOne) v = a.fbar[plane_index(s, kCompactRbar + l, x, y)] + v;
-    a.rbar[plane_index(s, l, x, y)] = v;
+    if constexpr (kTauOne) r = a.fbar[plane_index(s, kCompactRbar + l, x, y)] + r;
+    a.rbar[plane_index(s, l, x, y)] = r;
   }
   if constexpr (kTauOne) {
     // no adj_pull at tau = 1 (the next adj_local gathers lambda): the bottom
