@@ -297,6 +297,13 @@ def main() -> int:
     e2.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
+    # The first calls of the two analyses below allocate their buffers: one
+    # call each (the droplets' one timed as first_call_ms), then the timed
+    # steady-state calls.
+    sim.row_averages()
+    t_drop_first = time.perf_counter()
+    sim.droplets(0.8)
+    t_drop_first = time.perf_counter() - t_drop_first
     # stress fields + row averages of the same time level (Couette rheology
     # observables): one pass of the step kernel without store, then the row
     # reduction and the copy of 2 * ly doubles (synchronising)
@@ -405,7 +412,8 @@ def main() -> int:
                   "wall_s": round(wall, 3)},
         "row_averages": {"ms": round(t_rows * 1e3, 3), "pxy_av_mean": float(np.mean(rows["pxy_av"])),
                          "u_av_top": float(rows["u_av"][-1])},
-        "droplets": {"ms": round(t_drop * 1e3, 3), "count": int(len(drops["root"])),
+        "droplets": {"ms": round(t_drop * 1e3, 3), "first_call_ms": round(t_drop_first * 1e3, 3),
+                     "count": int(len(drops["root"])),
                      "threshold": 0.8, "nu_mean": float(np.mean(drops["nu"])) if len(drops["nu"]) else None},
     }
     sim.close()

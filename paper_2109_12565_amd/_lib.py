@@ -287,19 +287,32 @@ class Simulation:
         lab = np.empty((ly, lx), np.int32) if labels else None
         lab_p = lab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if labels else None
         fn = self._lib.tlb_droplets_noalloc if noalloc else self._lib.tlb_droplets
-        arr = np.empty(self._drop_cap, DROPLET_DTYPE)
+        arr = self._droplet_records()
         self._check(fn(self._h, float(threshold), arr.ctypes.data, len(arr), ctypes.byref(count),
                        lab_p))
         n = count.value
         if n > len(arr):  # more droplets than room: ask again with room for all
             self._drop_cap = n
-            arr = np.empty(n, DROPLET_DTYPE)
+            arr = self._droplet_records()
             self._check(fn(self._h, float(threshold), arr.ctypes.data, n, ctypes.byref(count),
                            None))
         out = {k: np.ascontiguousarray(arr[k][:n]) for k in DROPLET_DTYPE.names}
         if labels:
             out["label"] = lab
         return out
+
+    def _droplet_records(self) -> np.ndarray:
+        """Room for ``_drop_cap`` droplet records, in page-locked host memory
+        (the copy from the device is then one DMA, with no staging), kept
+        for the next call."""
+        buf = getattr(self, "_drop_buf", None)
+        if buf is None or len(buf) < self._drop_cap:
+            import torch
+            raw = torch.empty(self._drop_cap * DROPLET_DTYPE.itemsize, dtype=torch.uint8,
+                              pin_memory=True)
+            buf = np.frombuffer(raw.numpy(), DROPLET_DTYPE)
+            self._drop_raw, self._drop_buf = raw, buf
+        return buf
 
     def populations(self) -> np.ndarray:
         """Post-collision f*_A, f*_B, g* of the current time, [27, ly, lx]."""

@@ -47,8 +47,11 @@ struct DropArgs {
   DropRecord* out;          // [count]
   int32_t* label;           // [ly*lx] droplet number, -1 outside
   int* error;               // set when a bounded loop runs out
+  const int32_t* total;     // droplet count (written by drop_scan_tiles)
   double threshold, t_top, kappa, dt_nominal;
-  int lx, ly, n, count;
+  int lx, ly, n;
+  int capacity;             // droplets acc, roots and out have room for; the
+                            // droplets beyond it are numbered but not summed
 };
 
 constexpr int kDropItems = 16;                 // nodes per thread in the counting passes
@@ -265,7 +268,7 @@ __global__ __launch_bounds__(256) void drop_number_roots(DropArgs a) {
     const int q = base + j;
     if (q < a.n && a.parent[q] == q) {
       a.rid[q] = id;
-      a.roots[id] = q;
+      if (id < a.capacity) a.roots[id] = q;
       ++id;
     }
   }
@@ -283,52 +286,90 @@ __device__ inline double fixed_value(int64_t hi, int64_t lo) {
   return ((double)hi * 4294967296.0 + (double)lo) * (1.0 / 1099511627776.0);
 }
 
-__device__ inline int64_t wave_sum(int64_t v) {
+// Per node: its droplet number, and its terms of the droplet's sums (x
+// taken within half a period of the root's x). A block sums a tile of
+// kLocalW columns x kAccRows rows: each thread walks kAccRun rows of one
+// column (a wavefront reads one row at a time) and keeps the running sums
+// of the droplet it is in; when the droplet changes it adds them to the
+// droplet's slot of an LDS table (open addressing on the droplet number).
+// At the end each slot issues one set of global atomics; a run that finds
+// the table full adds to global memory directly. The sums are integers,
+// so the result does not depend on the order.
+constexpr int kAccSlots = 128;
+constexpr int kAccRun = 16;
+constexpr int kAccRows = kAccRun * (256 / kLocalW);
+
+__device__ inline void acc_flush(DropArgs& a, int32_t* key, unsigned long long (*val)[7], int d,
+                                 const int64_t (&sum)[7]) {
+  int slot = d & (kAccSlots - 1), found = -1;
+  for (int probe = 0; probe < kAccSlots; ++probe) {
+    const int32_t old = atomicCAS(&key[slot], -1, d);
+    if (old == -1 || old == d) {
+      found = slot;
+      break;
+    }
+    slot = (slot + 1) & (kAccSlots - 1);
+  }
+  if (found >= 0) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+    for (int j = 0; j < 7; ++j) atomicAdd(&val[found][j], (unsigned long long)sum[j]);
+  } else {
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(a.acc + (size_t)d * 7);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) atomicAdd(c + j, (unsigned long long)sum[j]);
+  }
 }
 
-// Per node: its droplet number, and its terms of the droplet's sums (x
-// taken within half a period of the root's x). The lanes of a wavefront
-// that belong to one droplet add their terms first (one group per distinct
-// droplet, taken in lane order), so each group issues one set of atomics.
 __global__ __launch_bounds__(256) void drop_accumulate(DropArgs a) {
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  int d = -1;
-  int64_t t[7] = {0, 0, 0, 0, 0, 0, 0};
-  if (q < a.n) {
+  __shared__ int32_t key[kAccSlots];
+  __shared__ unsigned long long val[kAccSlots][7];
+  for (int i = threadIdx.x; i < kAccSlots; i += 256) {
+    key[i] = -1;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) val[i][j] = 0;
+  }
+  __syncthreads();
+  const int x = blockIdx.x * kLocalW + (threadIdx.x % kLocalW);
+  const int ys = blockIdx.y * kAccRows + (threadIdx.x / kLocalW) * kAccRun;
+  int cur = -1;  // droplet of the running sums
+  int64_t sum[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < kAccRun; ++k) {
+    const int y = ys + k;
+    if (x >= a.lx || y >= a.ly) break;
+    const int q = y * a.lx + x;
     const int32_t root = a.parent[q];
-    if (root >= 0) {
-      d = a.rid[root];
-      const int x = q % a.lx, y = q / a.lx, xr = root % a.lx, yr = root / a.lx;
+    const int lab = root >= 0 ? a.rid[root] : -1;
+    a.label[q] = lab;
+    const int d = lab < a.capacity ? lab : -1;  // droplets beyond the room: not summed
+    if (d != cur) {
+      if (cur >= 0) acc_flush(a, key, val, cur, sum);
+      cur = d;
+#pragma unroll
+      for (int j = 0; j < 7; ++j) sum[j] = 0;
+    }
+    if (d >= 0) {
+      const int xr = root % a.lx, yr = root / a.lx;
       double dx = (double)(x - xr);
       if (dx > 0.5 * a.lx) dx -= a.lx;
       if (dx < -0.5 * a.lx) dx += a.lx;
       const double r = a.fields[q];
+      int64_t t[7];
       t[0] = 1;
       split_fixed(r, t[1], t[2]);
       split_fixed(r * ((double)xr + dx), t[3], t[4]);
       split_fixed(r * (double)(yr + (y - yr)), t[5], t[6]);
+#pragma unroll
+      for (int j = 0; j < 7; ++j) sum[j] += t[j];
     }
-    a.label[q] = d;
   }
-  uint64_t pending = __ballot(d >= 0);
-  while (pending != 0) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const int dl = __shfl(d, leader, 64);
-    const bool mine = d == dl;
-    const uint64_t group = __ballot(mine);
-    int64_t sum[7];
+  if (cur >= 0) acc_flush(a, key, val, cur, sum);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kAccSlots; i += 256) {
+    const int32_t dl = key[i];
+    if (dl < 0) continue;
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(a.acc + (size_t)dl * 7);
 #pragma unroll
-    for (int j = 0; j < 7; ++j) sum[j] = wave_sum(mine ? t[j] : 0);
-    if (lane == leader) {
-      unsigned long long* c = reinterpret_cast<unsigned long long*>(a.acc + (size_t)dl * 7);
-#pragma unroll
-      for (int j = 0; j < 7; ++j) atomicAdd(c + j, (unsigned long long)sum[j]);
-    }
-    pending &= ~group;
+    for (int j = 0; j < 7; ++j) atomicAdd(c + j, val[i][j]);
   }
 }
 
@@ -377,7 +418,7 @@ __device__ inline double node_dtdy(const DropArgs& a, int x, int y) {
 // interpolated bilinearly at the centre (x periodic, y clamped).
 __global__ __launch_bounds__(256) void drop_finalize(DropArgs a) {
   const int d = blockIdx.x * 256 + threadIdx.x;
-  if (d >= a.count) return;
+  if (d >= *a.total || d >= a.capacity) return;
   const int64_t* c = a.acc + (size_t)d * 7;
   const double m = fixed_value(c[1], c[2]);
   double X = fixed_value(c[3], c[4]) / m;

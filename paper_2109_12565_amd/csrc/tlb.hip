@@ -424,16 +424,36 @@ int run_droplets(tlb_handle* h, const char* who, DropBuffers& b, bool grow, doub
   const dim3 nodes((n + 255) / 256), block(256);
   const dim3 local_tiles((lx + tlbk::kLocalW - 1) / tlbk::kLocalW,
                          (ly + tlbk::kLocalH - 1) / tlbk::kLocalH);
+  const dim3 acc_tiles((lx + tlbk::kLocalW - 1) / tlbk::kLocalW,
+                       (ly + tlbk::kAccRows - 1) / tlbk::kAccRows);
   hipLaunchKernelGGL(tlbk::drop_local, local_tiles, block, 0, h->stream, a);
   hipLaunchKernelGGL(tlbk::drop_union_border, nodes, block, 0, h->stream, a);
   hipLaunchKernelGGL(tlbk::drop_compress, nodes, block, 0, h->stream, a);
   hipLaunchKernelGGL(tlbk::drop_count_roots, dim3(tiles), block, 0, h->stream, a);
   hipLaunchKernelGGL(tlbk::drop_scan_tiles, dim3(1), block, 0, h->stream, b.tiles, tiles);
+  a.total = b.tiles + tiles;
+  // Numbering, sums and records for the droplets the buffer has room for,
+  // launched without waiting for the count (kernels read it on the device);
+  // when the count exceeds the room, a growing call repeats this part.
+  auto sums = [&]() {
+    a.acc = static_cast<int64_t*>(b.acc);
+    a.roots = a.acc + 7 * (size_t)b.acc_count;
+    a.out = reinterpret_cast<tlbk::DropRecord*>(a.roots + b.acc_count);
+    a.capacity = (int)b.acc_count;
+    const dim3 per_droplet((unsigned)((b.acc_count + 255) / 256));
+    if (b.acc_count > 0)
+      hipLaunchKernelGGL(tlbk::drop_clear, per_droplet, block, 0, h->stream, a.acc, a.total,
+                         a.capacity);
+    hipLaunchKernelGGL(tlbk::drop_number_roots, dim3(tiles), block, 0, h->stream, a);
+    hipLaunchKernelGGL(tlbk::drop_accumulate, acc_tiles, block, 0, h->stream, a);
+    if (b.acc_count > 0)
+      hipLaunchKernelGGL(tlbk::drop_finalize, per_droplet, block, 0, h->stream, a);
+  };
+  sums();
   TLB_HIP(h, hipGetLastError());
   int32_t total = 0;
   int err = 0;
-  TLB_HIP(h, hipMemcpyAsync(&total, b.tiles + tiles, sizeof(int32_t), hipMemcpyDeviceToHost,
-                            h->stream));
+  TLB_HIP(h, hipMemcpyAsync(&total, a.total, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
   TLB_HIP(h, hipMemcpyAsync(&err, b.error, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   TLB_HIP(h, hipStreamSynchronize(h->stream));
   if (err) return fail(h, TLB_EDEVICE, "%s: cluster walk exceeded its bound", who);
@@ -449,20 +469,9 @@ int run_droplets(tlb_handle* h, const char* who, DropBuffers& b, bool grow, doub
     h->drop_acc_cap = (size_t)total;
     b.acc = h->drop_acc;
     b.acc_count = total;
+    sums();
+    TLB_HIP(h, hipGetLastError());
   }
-  a.acc = static_cast<int64_t*>(b.acc);
-  a.roots = a.acc + 7 * (size_t)b.acc_count;
-  a.out = reinterpret_cast<tlbk::DropRecord*>(a.roots + b.acc_count);
-  a.count = total;
-  if (total > 0) {
-    hipLaunchKernelGGL(tlbk::drop_clear, dim3((total + 255) / 256), block, 0, h->stream, a.acc,
-                       b.tiles + tiles, total);
-  }
-  hipLaunchKernelGGL(tlbk::drop_number_roots, dim3(tiles), block, 0, h->stream, a);
-  hipLaunchKernelGGL(tlbk::drop_accumulate, nodes, block, 0, h->stream, a);
-  if (total > 0)
-    hipLaunchKernelGGL(tlbk::drop_finalize, dim3((total + 255) / 256), block, 0, h->stream, a);
-  TLB_HIP(h, hipGetLastError());
   const int64_t m = std::min<int64_t>(cap, total);
   if (m > 0)
     TLB_HIP(h, hipMemcpyAsync(out, a.out, (size_t)m * sizeof(tlb_droplet), hipMemcpyDeviceToHost,
@@ -790,6 +799,12 @@ int tlb_droplets(tlb_handle* h, double threshold, tlb_droplet* out, int64_t cap,
   b.tiles = h->drop_tiles;
   b.error = h->drop_error;
   b.tb = h->drop_tb;
+  if (!h->drop_acc) {
+    // room for one droplet per 64 nodes at first; grown when exceeded
+    const size_t room = std::max<size_t>(4096, (size_t)n / 64);
+    TLB_HIP(h, hipMalloc(&h->drop_acc, room * kDropBytesPerDroplet));
+    h->drop_acc_cap = room;
+  }
   b.acc = h->drop_acc;
   b.acc_count = (int64_t)h->drop_acc_cap;
   return run_droplets(h, "tlb_droplets", b, true, threshold, out, cap, count, labels);

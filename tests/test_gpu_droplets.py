@@ -114,3 +114,22 @@ def test_full_size_partition_properties():
     assert np.all(np.diff(d["root"]) > 0)
     np.testing.assert_array_equal(np.bincount(flat[idx], minlength=n), d["size"])
     assert np.all((d["x"] >= 0) & (d["x"] < w["lx"])) and np.all(np.isfinite(d["nu"]))
+
+
+def test_more_droplets_than_the_first_buffer_and_a_tile_table():
+    """8192 single-node droplets on 256 x 128: more than the per-droplet
+    buffer a handle starts with (4096; the call grows it and repeats the
+    sums) and, with 256 droplets in each 64 x 16 tile, more than the LDS
+    table of the summing kernel holds (those groups add to global memory
+    directly). A second call finds the buffer large enough."""
+    lx, ly = 256, 128
+    mask = np.zeros((ly, lx), bool)
+    mask[::2, ::2] = True
+    ra = np.where(mask, 1.36, 0.08)
+    case = dict(params=dict(workloads.BASE_PARAMS), rho_a=ra, rho_b=np.where(mask, 0.08, 1.36),
+                temp=workloads.conduction_profile(lx, ly), t_bottom=np.ones(lx))
+    sim, ora = pair(case, "fp64", 0)
+    ref = ora.droplets(0.8)
+    assert len(ref["root"]) == 8192
+    compare(sim.droplets(0.8, labels=True), ref)
+    compare(sim.droplets(0.8, labels=True), ref)
