@@ -97,6 +97,83 @@ __global__ __launch_bounds__(256) void step_pattern(const float* __restrict__ sr
   }
 }
 
+// The same pull pattern on 2-byte values (16-bit storages), plane layout and
+// step order: one column per lane with 2-byte loads and stores, or two
+// columns per lane with 4-byte ones, where the pulls from x - 1 and x + 1
+// take the neighbour column from the adjacent lane and the wavefront's edge
+// lanes load the word beyond it.
+__global__ __launch_bounds__(256) void step_pattern_h(const uint16_t* __restrict__ src,
+                                                      uint16_t* __restrict__ dst) {
+  const int nbx = gridDim.x, ntiles = gridDim.x * gridDim.y;
+  const int lin = blockIdx.y * nbx + blockIdx.x;
+  const int xcd = lin % 8;
+  const int tile = xcd * (ntiles / 8) + min(xcd, ntiles % 8) + lin / 8;
+  const int chunk = tile / nbx, strip = tile - chunk * nbx;
+  const int x = strip * 256 + threadIdx.x;
+  const int xm = x == 0 ? kPLx - 1 : x - 1, xp = x == kPLx - 1 ? 0 : x + 1;
+  const bool down = chunk & 1;
+  for (int k = 0; k < kPRows; ++k) {
+    const int r = down ? chunk * kPRows + kPRows - 1 - k : chunk * kPRows + k;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int p = 0; p < kPPlanes; ++p) {
+      const int i = p % 9;
+      int sr = r - kPcy[i];
+      sr = sr < 0 ? 0 : (sr >= kPLy ? kPLy - 1 : sr);
+      const int sx = kPcx[i] > 0 ? xm : (kPcx[i] < 0 ? xp : x);
+      acc += src[pattern_index<0>(sr, sx, p)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kPPlanes; ++p)
+      __builtin_nontemporal_store((uint16_t)(acc + p), dst + pattern_index<0>(r, x, p));
+  }
+}
+
+__global__ __launch_bounds__(256) void step_pattern_h2(const uint32_t* __restrict__ src,
+                                                       uint32_t* __restrict__ dst) {
+  constexpr int kW = kPLx / 2;  // words per row
+  const int nbx = gridDim.x, ntiles = gridDim.x * gridDim.y;
+  const int lin = blockIdx.y * nbx + blockIdx.x;
+  const int xcd = lin % 8;
+  const int tile = xcd * (ntiles / 8) + min(xcd, ntiles % 8) + lin / 8;
+  const int chunk = tile / nbx, strip = tile - chunk * nbx;
+  const int w = strip * 256 + threadIdx.x;  // grid covers the words of a row exactly
+  const int lane = threadIdx.x & 63;
+  const int wm = w == 0 ? kW - 1 : w - 1, wp = w == kW - 1 ? 0 : w + 1;
+  const bool down = chunk & 1;
+  auto word = [&](int p, int row, int ww) { return ((size_t)p * kPLy + row) * kW + ww; };
+  for (int k = 0; k < kPRows; ++k) {
+    const int r = down ? chunk * kPRows + kPRows - 1 - k : chunk * kPRows + k;
+    uint32_t a0 = 0, a1 = 0;  // columns 2w and 2w + 1
+#pragma unroll
+    for (int p = 0; p < kPPlanes; ++p) {
+      const int i = p % 9;
+      int sr = r - kPcy[i];
+      sr = sr < 0 ? 0 : (sr >= kPLy ? kPLy - 1 : sr);
+      const uint32_t own = src[word(p, sr, w)];
+      if (kPcx[i] == 0) {
+        a0 += own & 0xffffu;
+        a1 += own >> 16;
+      } else if (kPcx[i] > 0) {  // from x - 1: the left word's high half
+        uint32_t left = __shfl_up(own, 1, 64);
+        if (lane == 0) left = src[word(p, sr, wm)];
+        a0 += left >> 16;
+        a1 += own & 0xffffu;
+      } else {  // from x + 1: the right word's low half
+        uint32_t right = __shfl_down(own, 1, 64);
+        if (lane == 63) right = src[word(p, sr, wp)];
+        a0 += own >> 16;
+        a1 += right & 0xffffu;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kPPlanes; ++p)
+      __builtin_nontemporal_store(((a0 + p) & 0xffffu) | ((a1 + p) << 16), dst + word(p, r, w));
+  }
+}
+
 int main() {
   const size_t bytes = (size_t)1 << 30;
   const size_t n4 = bytes / sizeof(v4f), n1 = bytes / sizeof(float);
@@ -170,6 +247,29 @@ int main() {
     ms /= 20;
     std::printf("%s{\"kernel\": \"%s\", \"us\": %.1f, \"GBps\": %.1f}", kind ? ", " : "",
                 pnames[kind], ms * 1e3, 2.0 * pbytes / ms / 1e6);
+  }
+  // 16-bit values: the same lattice, half the bytes
+  const dim3 hgrid(kPLx / 256, kPLy / kPRows), h2grid(kPLx / 512, kPLy / kPRows);
+  for (int kind = 0; kind < 2; ++kind) {
+    auto launch = [&]() {
+      if (kind == 0)
+        hipLaunchKernelGGL(step_pattern_h, hgrid, dim3(256), 0, 0, (const uint16_t*)pa, (uint16_t*)pb);
+      else
+        hipLaunchKernelGGL(step_pattern_h2, h2grid, dim3(256), 0, 0, (const uint32_t*)pa, (uint32_t*)pb);
+    };
+    launch();
+    CHECK(hipGetLastError());
+    CHECK(hipDeviceSynchronize());
+    CHECK(hipEventRecord(e0));
+    for (int it = 0; it < 20; ++it) launch();
+    CHECK(hipEventRecord(e1));
+    CHECK(hipEventSynchronize(e1));
+    float ms = 0;
+    CHECK(hipEventElapsedTime(&ms, e0, e1));
+    ms /= 20;
+    std::printf(", {\"kernel\": \"%s\", \"us\": %.1f, \"GBps\": %.1f}",
+                kind ? "planes16_two_columns_per_lane" : "planes16_step_order", ms * 1e3,
+                pbytes / ms / 1e6);
   }
   std::printf("]}\n");
   CHECK(hipFree(pa));
