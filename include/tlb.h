@@ -116,6 +116,9 @@ typedef struct tlb_params {
                             (1..245), 0: chosen */
   int32_t rows;          /* rows per chunk of the single-step kernel (1..4096),
                             0: chosen */
+  int32_t fused_lanes;   /* lanes per block of the fused kernel, 128 or 256
+                            (at most lanes - 10 stored columns per strip),
+                            0: chosen */
 } tlb_params;
 
 /* Observables at time `step` (Sec. 3.1, Sec. 3.3.2 Eq. (24)); sums and means
@@ -288,13 +291,14 @@ int64_t tlb_time(const tlb_handle *h);
  * lattice onto GPU threads; here a block of `bx` threads marches over a
  * chunk of `rows` rows of a `bx`-column strip). fused_rows > 0 means that
  * tlb_step advances pairs of steps with the fused two-step kernel (tau =
- * tau_g = 1, flat walls at rest or moving; strips of fused_strip stored
- * columns, chunks of fused_rows rows); every tlb_step call still ends with a
- * single step. Host struct, written by the call. Returns TLB_EINVAL on a
- * NULL argument. */
+ * tau_g = 1, flat walls at rest or moving; blocks of fused_lanes lanes,
+ * strips of fused_strip stored columns, chunks of fused_rows rows); every
+ * tlb_step call still ends with a single step. Host struct, written by the
+ * call. Returns TLB_EINVAL on a NULL argument. */
 typedef struct tlb_launch {
   int32_t bx, rows, grid_x, grid_y;
   int32_t fused_rows, fused_strip, fused_grid_x, fused_grid_y;
+  int32_t fused_lanes;
 } tlb_launch;
 int tlb_launch_info(const tlb_handle *h, tlb_launch *out);
 

@@ -46,13 +46,14 @@ class Params(ctypes.Structure):
         ("rho_ref", ctypes.c_double * 2), ("t_ref", ctypes.c_double),
         ("u_wall", ctypes.c_double * 2),
         ("fused", ctypes.c_int32), ("fused_rows", ctypes.c_int32),
-        ("fused_strip", ctypes.c_int32), ("rows", ctypes.c_int32),
+        ("fused_strip", ctypes.c_int32), ("rows", ctypes.c_int32), ("fused_lanes", ctypes.c_int32),
     ]
 
 
 TLB_LAUNCH_GENERAL_PATH, TLB_LAUNCH_WIDE_OFFSETS = 1, 2
 FUSED_MODES = {"auto": 0, "never": 1, "always": 2}
-LAUNCH_KEYS = ("fused", "fused_rows", "fused_strip", "rows", "general_path", "wide_offsets")
+LAUNCH_KEYS = ("fused", "fused_rows", "fused_strip", "fused_lanes", "rows", "general_path",
+               "wide_offsets")
 
 
 class Obs(ctypes.Structure):
@@ -64,7 +65,7 @@ class Obs(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in
                 ("bx", "rows", "grid_x", "grid_y",
-                 "fused_rows", "fused_strip", "fused_grid_x", "fused_grid_y")]
+                 "fused_rows", "fused_strip", "fused_grid_x", "fused_grid_y", "fused_lanes")]
 
 
 class Droplet(ctypes.Structure):
@@ -162,7 +163,7 @@ class Simulation:
     torch's current stream.
 
     ``launch`` (optional) sets the launch choices of ``tlb_params``: ``fused``
-    ("auto", "never", "always"), ``fused_rows``, ``fused_strip``, ``rows``
+    ("auto", "never", "always"), ``fused_rows``, ``fused_strip``, ``fused_lanes``, ``rows``
     (0 or absent: chosen by the library), and the kernel-selection flags
     ``general_path`` and ``wide_offsets``.
     """
@@ -204,6 +205,7 @@ class Simulation:
         p.fused_rows = int(launch.get("fused_rows", 0))
         p.fused_strip = int(launch.get("fused_strip", 0))
         p.rows = int(launch.get("rows", 0))
+        p.fused_lanes = int(launch.get("fused_lanes", 0))
         p.tau, p.tau_g = params["tau"], params["tau_g"]
         p.rho0, p.g12 = params["rho0"], params["g12"]
         p.g_a[0], p.g_a[1] = params["g_a"]

@@ -18,13 +18,15 @@ struct Geometry {
   // fused two-step kernel (tau = tau_g = 1; flat walls at rest or moving);
   // rows2 == 0: not used
   int rows2 = 0;     // rows per block chunk
-  int strip2 = 0;    // stored columns per strip (kStep2Lanes - kStep2Halo at most)
+  int lanes2 = 256;  // lanes per block (kStep2Lanes or kStep2LanesNarrow)
+  int strip2 = 0;    // stored columns per strip (lanes2 - kStep2Halo at most)
   dim3 grid2;
 };
 
-// Lanes per block of the two-step kernel and the columns of each strip that
-// only feed the others (5 on each side).
+// Lanes per block of the two-step kernel (wide and narrow blocks) and the
+// columns of each strip that only feed the others (5 on each side).
 constexpr int kStep2Lanes = 256;
+constexpr int kStep2LanesNarrow = 128;
 constexpr int kStep2Halo = 10;
 
 // Everything a launch needs from a handle.
@@ -69,7 +71,7 @@ struct Launcher {
   static int blocks_per_cu(int bx, bool wide, bool solid, bool tau_one);
   // Resident blocks per CU of the two-step kernel; 0 where the storage has
   // no two-step kernel.
-  static int step2_blocks_per_cu(bool solid);
+  static int step2_blocks_per_cu(bool solid, int lanes);
   // dst2: the second output of kStep2Tape and kStep2TapeTopRow
   static void step(const Device& d, Pass pass, const void* src, void* dst, void* dst2 = nullptr);
   // f(0) = equilibria of the initial fields (rho_a, rho_b, temp, ux0, uy0;

@@ -111,8 +111,12 @@ int occupancy_geometry(int bx, bool wide) {
 
 template <class St, unsigned kMode>
 void launch_step2_kernel(const Device& d, const tlbk::StepArgs<typename St::C>& a) {
-  hipLaunchKernelGGL((tlbk::lb_step2_kernel<St, kStep2Lanes, kMode>), d.geo.grid2,
-                     dim3(kStep2Lanes), 0, d.stream, a, d.geo.strip2);
+  if (d.geo.lanes2 == kStep2LanesNarrow)
+    hipLaunchKernelGGL((tlbk::lb_step2_kernel<St, kStep2LanesNarrow, kMode>), d.geo.grid2,
+                       dim3(kStep2LanesNarrow), 0, d.stream, a, d.geo.strip2);
+  else
+    hipLaunchKernelGGL((tlbk::lb_step2_kernel<St, kStep2Lanes, kMode>), d.geo.grid2,
+                       dim3(kStep2Lanes), 0, d.stream, a, d.geo.strip2);
 }
 
 // Storages with a two-step kernel: FP64, FP32 and the 16-bit floating
@@ -152,26 +156,33 @@ void launch_step2(const Device& d, const void* src, void* dst, Pass pass, void* 
   }
 }
 
-template <class St, unsigned kMode>
+template <class St, int BT, unsigned kMode>
 int step2_occupancy() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &n, tlbk::lb_step2_kernel<St, kStep2Lanes, kMode>, kStep2Lanes, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tlbk::lb_step2_kernel<St, BT, kMode>, BT,
+                                                   0) != hipSuccess ||
       n < 1)
     n = 1;
   return n;
 }
 
+template <class St, unsigned kMode>
+int step2_occupancy_lanes(int lanes) {
+  return lanes == kStep2LanesNarrow ? step2_occupancy<St, kStep2LanesNarrow, kMode>()
+                                    : step2_occupancy<St, kStep2Lanes, kMode>();
+}
+
 }  // namespace detail
 
 template <class St>
-int Launcher<St>::step2_blocks_per_cu(bool solid) {
+int Launcher<St>::step2_blocks_per_cu(bool solid, int lanes) {
   if constexpr (detail::kHasStep2<St>) {
     constexpr unsigned M = tlbk::kModeStore | tlbk::kModeTauOne;
-    return solid ? detail::step2_occupancy<St, M | tlbk::kModeSolid>()
-                 : detail::step2_occupancy<St, M>();
+    return solid ? detail::step2_occupancy_lanes<St, M | tlbk::kModeSolid>(lanes)
+                 : detail::step2_occupancy_lanes<St, M>(lanes);
   } else {
     (void)solid;
+    (void)lanes;
     return 0;
   }
 }

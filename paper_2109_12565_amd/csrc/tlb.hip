@@ -161,19 +161,41 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
   // TLB_FUSED_NEVER never.
   const bool eligible = tau_one && !l.wide && p.precision != TLB_FIX16_DEV;
   if (eligible && p.fused != TLB_FUSED_NEVER) {
-    int per_cu2 = 0;
-    with_storage(p.precision, [&](auto st) {
-      per_cu2 = tlbh::Launcher<decltype(st)>::step2_blocks_per_cu(solid);
-    });
-    int max_strip = tlbh::kStep2Lanes - tlbh::kStep2Halo;
-    if (p.fused_strip > 0) max_strip = p.fused_strip;
-    const long long strips2 = (lx + max_strip - 1) / max_strip;
-    const int strip2 = (int)((lx + strips2 - 1) / strips2);
-    // at most one block per resident slot: a second, partial wave of blocks
-    // would take as long as the first
-    const long long slots = (long long)cus * std::max(per_cu2, 1);
-    const long long max_chunks = std::max(1LL, slots / strips2);
-    long long rows2 = (ly + max_chunks - 1) / max_chunks;
+    // Geometry for blocks of `lanes` lanes: strips of at most lanes -
+    // kStep2Halo stored columns, and at most one block per resident slot (a
+    // second, partial wave of blocks would take as long as the first).
+    struct Fused {
+      int per_cu = 0, strip = 0;
+      long long strips = 1, rows = 1;
+    };
+    auto fused_geometry = [&](int lanes) {
+      Fused g;
+      with_storage(p.precision, [&](auto st) {
+        g.per_cu = tlbh::Launcher<decltype(st)>::step2_blocks_per_cu(solid, lanes);
+      });
+      int max_strip = lanes - tlbh::kStep2Halo;
+      if (p.fused_strip > 0) max_strip = std::min(max_strip, (int)p.fused_strip);
+      g.strips = (lx + max_strip - 1) / max_strip;
+      g.strip = (int)((lx + g.strips - 1) / g.strips);
+      const long long slots = (long long)cus * std::max(g.per_cu, 1);
+      const long long max_chunks = std::max(1LL, slots / g.strips);
+      g.rows = (ly + max_chunks - 1) / max_chunks;
+      return g;
+    };
+    const Fused wide = fused_geometry(tlbh::kStep2Lanes);
+    const int per_cu2 = wide.per_cu;
+    // Narrow blocks where wide ones would leave chunks of fewer than 16 rows:
+    // a block's time is then mostly its chain of first-level halo rows, and
+    // twice as many resident narrow blocks take shorter chunks (FP32 per
+    // fused launch, 256 / 128 lanes: 1024 x 512 54.8 / 49.5 us, 1024 x 64
+    // 28.7 / 27.0, 128 x 64 24.8 / 23.5; 4096 x 2048 with 69-row chunks
+    // 527 / 596, FP16 deviations 494 / 512).
+    const bool narrow = p.fused_lanes == tlbh::kStep2LanesNarrow ||
+                        (p.fused_lanes == 0 && wide.rows < 16);
+    const Fused g2 = narrow ? fused_geometry(tlbh::kStep2LanesNarrow) : wide;
+    const long long strips2 = g2.strips;
+    const int strip2 = g2.strip;
+    long long rows2 = g2.rows;
     // with at least two resident blocks per CU it pays at every lattice size
     // measured, the chunk height being the one that fills the slots once
     // (FP32 per step, fused / single: 128 x 64 12.7 / 20.1 us, 1024 x 64
@@ -187,6 +209,7 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
     if (per_cu2 > 0 && (pays || p.fused == TLB_FUSED_ALWAYS)) {
       if (p.fused_rows > 0) rows2 = p.fused_rows;
       l.rows2 = (int)(rows2 < ly ? rows2 : ly);
+      l.lanes2 = narrow ? tlbh::kStep2LanesNarrow : tlbh::kStep2Lanes;
       l.strip2 = strip2;
       l.grid2 = dim3((unsigned)strips2, (unsigned)((ly + l.rows2 - 1) / l.rows2), 1);
     }
@@ -506,11 +529,13 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
   if ((p->launch_flags & ~(TLB_LAUNCH_GENERAL_PATH | TLB_LAUNCH_WIDE_OFFSETS)) != 0 ||
       p->fused < TLB_FUSED_AUTO || p->fused > TLB_FUSED_ALWAYS || p->fused_rows < 0 ||
       p->fused_rows > 4096 || p->fused_strip < 0 ||
-      p->fused_strip >= tlbh::kStep2Lanes - tlbh::kStep2Halo || p->rows < 0 || p->rows > 4096)
+      p->fused_strip >= tlbh::kStep2Lanes - tlbh::kStep2Halo || p->rows < 0 || p->rows > 4096 ||
+      (p->fused_lanes != 0 && p->fused_lanes != tlbh::kStep2Lanes &&
+       p->fused_lanes != tlbh::kStep2LanesNarrow))
     return fail(nullptr, TLB_EINVAL,
                 "tlb_init: launch options out of range (flags %d, fused %d, fused_rows %d, "
-                "fused_strip %d, rows %d)",
-                p->launch_flags, p->fused, p->fused_rows, p->fused_strip, p->rows);
+                "fused_strip %d, rows %d, fused_lanes %d)",
+                p->launch_flags, p->fused, p->fused_rows, p->fused_strip, p->rows, p->fused_lanes);
   if (!(p->tau > 0.5) || !(p->tau_g > 0.5) || !finite_positive(p->rho0) || !(p->dt_nominal != 0) ||
       !std::isfinite(p->dt_nominal))
     return fail(nullptr, TLB_EINVAL, "tlb_init: need tau > 1/2, tau_g > 1/2, rho0 > 0, dt_nominal != 0");
@@ -689,6 +714,7 @@ int tlb_launch_info(const tlb_handle* h, tlb_launch* out) {
   out->fused_strip = g.strip2;
   out->fused_grid_x = g.rows2 > 0 ? (int32_t)g.grid2.x : 0;
   out->fused_grid_y = g.rows2 > 0 ? (int32_t)g.grid2.y : 0;
+  out->fused_lanes = g.rows2 > 0 ? g.lanes2 : 0;
   return TLB_OK;
 }
 

@@ -67,7 +67,7 @@ def _params(**kw):
     p.alpha_g, p.t_top = 0.0, 0.0
     p.rho_wall[0], p.rho_wall[1] = 0.612, 0.612
     p.dt_nominal = kw.get("dt_nominal", 1.0)
-    for k in ("launch_flags", "fused", "fused_rows", "fused_strip", "rows"):
+    for k in ("launch_flags", "fused", "fused_rows", "fused_strip", "rows", "fused_lanes"):
         setattr(p, k, kw.get(k, 0))
     return p
 
@@ -103,6 +103,8 @@ def _init(p, solid=None, null_field=False):
     (dict(fused_rows=5000), "launch options"),
     (dict(fused_strip=246), "launch options"),
     (dict(rows=4097), "launch options"),
+    (dict(fused_lanes=64), "launch options"),
+    (dict(fused_lanes=512), "launch options"),
 ])
 def test_init_rejects_bad_params_without_device(kw, msg):
     rc, h, err = _init(_params(**kw))

@@ -16,7 +16,9 @@ populations (3e-5 of max|u| for velocities).
 The launch option fused = "always" forces the fused kernel wherever it
 applies (it is otherwise chosen only for lattices where it pays), "never"
 disables it, and fused_rows sets its chunk height, so short chunks exercise
-chunk edges in both marching directions.
+chunk edges in both marching directions. fused_lanes sets the block width:
+on these small lattices the library picks 128 lanes, so 256 is forced as
+the second case.
 """
 import numpy as np
 import pytest
@@ -30,9 +32,9 @@ from test_gpu_parity import FIELDS, field_errors, pop_errors, posts_case
 pytestmark = pytest.mark.gpu
 
 
-def make(case, precision, fused, rows=None, strip=None, **extra):
+def make(case, precision, fused, rows=None, strip=None, lanes=None, **extra):
     launch = {"fused": "always" if fused else "never", "fused_rows": rows or 0,
-              "fused_strip": strip or 0}
+              "fused_strip": strip or 0, "fused_lanes": lanes or 0}
     p = dict(case["params"], **extra)
     sim = Simulation(p, case["rho_a"], case["rho_b"], case["temp"], solid=case.get("solid"),
                      t_bottom=case.get("t_bottom"), precision=precision, launch=launch)
@@ -78,10 +80,13 @@ CASES = {
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("rows", [None, 1, 7])
-def test_fused_matches_single_steps(precision, name, rows):
+@pytest.mark.parametrize("lanes", [None, 256])
+def test_fused_matches_single_steps(precision, name, rows, lanes):
     case = CASES[name]()
-    fused, info = make(case, precision, True, rows)
+    fused, info = make(case, precision, True, rows, lanes=lanes)
     assert info["fused_rows"] > 0
+    assert info["fused_lanes"] == (lanes or 128)
+    assert info["fused_strip"] <= info["fused_lanes"] - 10
     single, info0 = make(case, precision, False)
     assert info0["fused_rows"] == 0
     for n in (9, 1, 2, 6):   # odd and even calls; every call ends with a single step
@@ -111,7 +116,8 @@ HALF_ULP_BITS = {"fp16dev": (10, -14), "bf16dev": (7, -126)}
 @pytest.mark.parametrize("name,u_wall", [(n, (0.0, 0.0)) for n in sorted(CASES)] +
                          [("small", (-0.01, 0.02)), ("posts", (-0.01, 0.02))])
 @pytest.mark.parametrize("rows", [None, 7])
-def test_dev16_fused_launch_from_gpu_state(precision, name, u_wall, rows):
+@pytest.mark.parametrize("lanes", [None, 256])
+def test_dev16_fused_launch_from_gpu_state(precision, name, u_wall, rows, lanes):
     """16-bit deviation storage, fused kernel forced on: from the GPU's own
     state after 4 steps (decoded exactly), tlb_step(3) runs one fused launch
     and one single step; the oracle takes 3 FP64 steps from the same state.
@@ -124,8 +130,8 @@ def test_dev16_fused_launch_from_gpu_state(precision, name, u_wall, rows):
     arithmetic. Walls at rest, and moving Couette walls on two lattices."""
     case = CASES[name]()
     case["params"] = dict(case["params"], u_wall=u_wall)
-    sim, info = make(case, precision, True, rows)
-    assert info["fused_rows"] > 0
+    sim, info = make(case, precision, True, rows, lanes=lanes)
+    assert info["fused_rows"] > 0 and info["fused_lanes"] == (lanes or 128)
     sim.step(4)
     state = sim.populations()
     sim.step(3)
@@ -207,16 +213,18 @@ def test_full_size_fused_steps_from_gpu_state():
     assert max(perr.values()) <= 1e-5, perr
 
 
-@pytest.mark.parametrize("lx,ly", [(5, 3), (64, 1), (7, 2), (250, 9)])
-def test_fused_edge_shapes_fp64(lx, ly):
+@pytest.mark.parametrize("lx,ly", [(5, 3), (64, 1), (7, 2), (250, 9), (120, 5)])
+@pytest.mark.parametrize("lanes", [None, 256])
+def test_fused_edge_shapes_fp64(lx, ly, lanes):
     """Lattices narrower than the kernel's halo (columns wrap several times
-    across one block), a single row (both walls on it), and a strip just
-    above one block's stored width. Velocities get 1e-11 of max|u|: on these
-    lattices max|u| is small (about 1e-4 on the single row), while u carries
-    the absolute rounding of its populations."""
+    across one block), a single row (both walls on it), and strips just
+    above one block's stored width (246 columns of 256 lanes, 118 of 128).
+    Velocities get 1e-11 of max|u|: on these lattices max|u| is small
+    (about 1e-4 on the single row), while u carries the absolute rounding of
+    its populations."""
     case = droplet_case(lx, ly, seed=lx + ly)
-    fused, info = make(case, "fp64", True)
-    assert info["fused_rows"] > 0
+    fused, info = make(case, "fp64", True, lanes=lanes)
+    assert info["fused_rows"] > 0 and info["fused_lanes"] == (lanes or 128)
     single, _ = make(case, "fp64", False)
     for n in (7, 4):
         fused.step(n)
@@ -233,6 +241,7 @@ def test_fused_launch_geometry():
     lx, ly = w["lx"], w["ly"]
     sim, info = make(w, "fp32", True)
     sim.close()
+    assert info["fused_lanes"] == 256
     assert 24 <= info["fused_rows"] <= ly and info["fused_strip"] <= 246
     assert info["fused_grid_x"] * info["fused_strip"] >= lx
     assert (info["fused_grid_x"] - 1) * info["fused_strip"] < lx
@@ -245,19 +254,40 @@ def test_fused_launch_geometry():
     assert info2["fused_rows"] == 40 and info2["fused_strip"] <= 200
 
 
+def test_fused_launch_geometry_narrow_blocks():
+    """At 1024 x 512 blocks of 256 lanes would leave chunks of 6 rows: the
+    library takes 128-lane blocks (strips of at most 118 stored columns),
+    still one block per resident slot; fused_lanes = 256 overrides it."""
+    w = workloads.mid()
+    lx, ly = w["lx"], w["ly"]
+    sim, info = make(w, "fp32", True)
+    sim.close()
+    assert info["fused_lanes"] == 128 and info["fused_strip"] <= 118
+    assert info["fused_grid_x"] * info["fused_strip"] >= lx
+    assert (info["fused_grid_x"] - 1) * info["fused_strip"] < lx
+    assert info["fused_grid_y"] * info["fused_rows"] >= ly
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert info["fused_grid_x"] * info["fused_grid_y"] <= 4 * cus
+    sim, info2 = make(w, "fp32", True, lanes=256)
+    sim.close()
+    assert info2["fused_lanes"] == 256 and info2["fused_rows"] == 6
+
+
 U_WALL = (-0.01, 0.02)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", ["small", "posts"])
-def test_fused_moving_walls_match_single_steps(precision, name):
+@pytest.mark.parametrize("lanes", [None, 256])
+def test_fused_moving_walls_match_single_steps(precision, name, lanes):
     """Couette walls (Sec. 2.2): the second level adds the wall momentum to
     the bounced diagonal links with the node's own intermediate zeroth
     moment as rho_w, which equals the sum of its stored populations in the
     single step up to rounding."""
     case = CASES[name]()
-    fused, info = make(case, precision, True, rows=7, u_wall=U_WALL)
-    assert info["fused_rows"] > 0
+    fused, info = make(case, precision, True, rows=7, lanes=lanes, u_wall=U_WALL)
+    assert info["fused_rows"] > 0 and info["fused_lanes"] == (lanes or 128)
     single, _ = make(case, precision, False, u_wall=U_WALL)
     for n in (9, 1, 2, 6):
         fused.step(n)
