@@ -102,9 +102,9 @@ def adjoint_ratio(steps: int, ckpt: int, precision: str, config: str = "mid") ->
     recompute included) over the time of the plain forward, for the same
     `steps` steps of an emulsion with a noisy bottom temperature: the
     1024x512 lattice (its gradient is zero: in 500 steps no signal crosses
-    512 rows) or the 1024x64 strip (a live gradient). ckpt = 1 keeps every
-    state in HBM (no recompute); tape_gib is the device memory of the
-    checkpoints plus the recompute tape. Steady state: a first taped run and
+    512 rows) or the 1024x64 strip (a live gradient). ckpt = 1 keeps the
+    moments of every step's pulled state in HBM (no recompute); tape_gib is
+    the device memory of the tape (moments, checkpoints, recompute buffers). Steady state: a first taped run and
     reverse sweep on the handle (from the initial state; their loss and
     gradient are reported, and their time, allocation of the checkpoints and
     the tape included, as first_call_ms) precede the timed calls."""
@@ -131,7 +131,13 @@ def adjoint_ratio(steps: int, ckpt: int, precision: str, config: str = "mid") ->
         warm = max(2 * ckpt, 10)
         sim.forward_taped(warm, ckpt)
         sim.adjoint(warm)
-    state_bytes = 27 * w["lx"] * w["ly"] * (8 if precision == "fp64" else 4)  # without row padding
+    # device memory of the tape (without row padding): at tau = tau_g = 1 the
+    # moments of every step (K = 1), or checkpoints, a segment's moments and
+    # two scratch states; else states
+    elem = 8 if precision == "fp64" else 4
+    state_bytes = 27 * w["lx"] * w["ly"] * elem
+    moment_bytes = 5 * w["lx"] * w["ly"] * elem
+    tau_one = w["params"]["tau"] == 1.0 and w["params"]["tau_g"] == 1.0
     with make() as sim:
         t_first_tape, loss = timed(lambda: sim.forward_taped(steps, ckpt))
         t_first_adj, g = timed(lambda: sim.adjoint(steps))
@@ -139,7 +145,11 @@ def adjoint_ratio(steps: int, ckpt: int, precision: str, config: str = "mid") ->
         t_adj, _ = timed(lambda: sim.adjoint(steps))
         t_fwd, _ = timed(lambda: sim.step(steps))
     nck = -(-steps // ckpt)
-    tape_gib = (nck + ckpt - 1) * state_bytes / 2**30
+    if tau_one:
+        tape = steps * moment_bytes if ckpt == 1 else (nck + 2) * state_bytes + ckpt * moment_bytes
+    else:
+        tape = (nck + ckpt - 1) * state_bytes
+    tape_gib = tape / 2**30
     return {"workload": w["name"], "storage": precision, "steps": steps, "ckpt_every": ckpt,
             "tape_gib": round(tape_gib, 2),
             "forward_ms": round(t_fwd * 1e3, 2), "taped_forward_ms": round(t_tape * 1e3, 2),
@@ -420,8 +430,8 @@ def main() -> int:
     if args.companions:
         out["companions"] = companion_runs(args.config, args.precision)
     if args.adjoint_steps > 0:
-        # every state kept (28 GiB at 1024x512 over 500 steps), then
-        # checkpoints every 25 steps with segment recompute
+        # the moments of every step kept (4.9 GiB at 1024x512 over 500
+        # steps), then checkpoints every 25 steps with segment recompute
         out["adjoint"] = adjoint_ratio(args.adjoint_steps, 1, "fp32")
         out["adjoint_ckpt"] = adjoint_ratio(args.adjoint_steps, 25, "fp32")
         out["adjoint_strip"] = adjoint_ratio(args.adjoint_steps, 1, "fp32", "strip")

@@ -265,9 +265,11 @@ int tlb_set_bottom_temperature(tlb_handle *h, const double *t_bottom);
  * The tape (checkpoints) replaces any previous one and stays valid until the
  * next tlb_forward_taped, tlb_set_bottom_temperature or tlb_destroy; later
  * tlb_step calls do not touch it. Checkpoint memory is
- * ceil(nsteps / ckpt_every) copies of the state; ckpt_every = 1 keeps every
- * state (the steps write into the tape directly, and the reverse sweep
- * recomputes nothing). Synchronises the stream.
+ * ceil(nsteps / ckpt_every) copies of the state. ckpt_every = 1 keeps every
+ * step instead and the reverse sweep recomputes nothing: at tau = tau_g = 1
+ * the steps write the moments rho_A, rho_B, j, T of their pulled state (5
+ * values per node; the adjoint of a step at tau = 1 needs nothing else) and
+ * no state is kept, otherwise every state. Synchronises the stream.
  * Errors: TLB_EINVAL (solid cells, moving walls, 16-bit storage, bad counts,
  * state buffer of 4 GiB or more, lx < 3, ly > 65535), TLB_ENOMEM,
  * TLB_EDEVICE. */
@@ -277,8 +279,9 @@ int tlb_forward_taped(tlb_handle *h, int64_t nsteps, int32_t ckpt_every, double 
  * seed * dL/dT_b(x), the exact derivative of the discrete forward map (the
  * adjoint of Eqs. (1)-(3), (6)-(12), (16)-(18), (22) and of the
  * anti-bounce-back wall source 2 w_i T_b). Each checkpoint segment is
- * recomputed into a device tape of ckpt_every - 1 states (none for
- * ckpt_every = 1), then swept backwards one step at a time. nsteps must equal the taped count. The
+ * recomputed (at tau = tau_g = 1 into the moments of its ckpt_every steps,
+ * else into ckpt_every - 1 states; nothing for ckpt_every = 1), then swept
+ * backwards one step at a time. nsteps must equal the taped count. The
  * handle's current state is not changed. Synchronises the stream.
  * Errors: TLB_ESTATE (no valid tape, or nsteps differs from it),
  * TLB_EINVAL (NULL grad_t_bottom), TLB_ENOMEM, TLB_EDEVICE. */

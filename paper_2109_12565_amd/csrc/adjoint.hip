@@ -65,7 +65,13 @@ void Adjoint<St>::reverse_step(const Device& d, const AdjointWork& w, const void
     a.rbar_prev = rb[1 - in];
     a.aux_next = aux[1 - in];
     a.have_prev = first ? 0 : 1;
-    if (!density_ready) hipLaunchKernelGGL((tlbk::adj_density<St>), grid, block, 0, d.stream, a);
+    // state and next_state are moment-tape slots here
+    a.mom = static_cast<const C*>(state);
+    a.mom_next = static_cast<const C*>(next_state);
+    a.state = nullptr;
+    a.next_state = nullptr;
+    if (!density_ready)
+      hipLaunchKernelGGL((tlbk::adj_density_moments<St>), grid, block, 0, d.stream, a);
     hipLaunchKernelGGL((tlbk::adj_local<St, true>), tiles, block, 0, d.stream, a);
     hipLaunchKernelGGL((tlbk::adj_scatter<St, true>), tiles, block, 0, d.stream, a);
   } else {

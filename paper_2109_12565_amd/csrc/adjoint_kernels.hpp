@@ -52,7 +52,12 @@ struct AdjArgs {
   double* grad;          // [lx] accumulated dL/dT_b
   double* loss_terms;    // per-step loss terms (forward)
   const void* next_state;  // state of the next reverse step, or null: adj_pull
-                           // (adj_scatter at tau = 1) then also fills its aux
+                           // then also fills its aux (tau != 1)
+  // tau = 1: moments rho_A, rho_B, j_x, j_y, T of this step's pulled state
+  // and of the next reverse step's ([5] planes, population layout; mom_next
+  // null: not at hand), from the taped run instead of the states
+  const C* mom;
+  const C* mom_next;
   C kappa_top;           // dL/dT of each top-row node for this step
   int step_index;
   int loss_stride;       // slots per step in loss_terms
@@ -167,6 +172,24 @@ __global__ __launch_bounds__(256) void adj_density(AdjArgs<typename St::C> a) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
   if (x >= a.s.lx) return;
   density_node<St>(a, a.state, x, y, a.aux);
+}
+
+// The same from a moment-tape slot (tau = 1).
+template <typename C>
+__device__ inline void density_from_moments(const AdjArgs<C>& a, const C* mom, int x, int y,
+                                            C* out) {
+  const C ra = mom[plane_index(a.s, 0, x, y)], rb = mom[plane_index(a.s, 1, x, y)];
+  out[plane_index(a.s, 0, x, y)] = ra;
+  out[plane_index(a.s, 1, x, y)] = rb;
+  out[plane_index(a.s, 2, x, y)] = psi_exp(ra, a.s.rho0, a.s.inv_rho0);
+  out[plane_index(a.s, 3, x, y)] = psi_exp(rb, a.s.rho0, a.s.inv_rho0);
+}
+
+template <class St>
+__global__ __launch_bounds__(256) void adj_density_moments(AdjArgs<typename St::C> a) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= a.s.lx) return;
+  density_from_moments(a, a.mom, x, y, a.aux);
 }
 
 // Forward loss term of one step: sum over the top row of T - T_top from the
@@ -303,12 +326,25 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
   const int x = x0 + tx, y = y0 + ty;
   if (x >= s.lx || y >= s.ly) return;
   const int cx0 = tx + kAdjHalo, cy0 = ty + kAdjHalo;
-  C f[18], g[9];
-  adj_pull_node<St>(a, x, y, f, g);
 
-  // ---- forward recompute
-  const C ra = sum9(f), rb = sum9(f + 9), temp = sum9(g);
-  const C jx = momentum_x(f, f + 9), jy = momentum_y(f, f + 9);
+  // ---- forward recompute: the moments of the pulled state (taped at tau =
+  // 1, else pulled from the state)
+  C ra, rb, temp, jx, jy;
+  if constexpr (kTauOne) {
+    ra = a.mom[plane_index(s, 0, x, y)];
+    rb = a.mom[plane_index(s, 1, x, y)];
+    jx = a.mom[plane_index(s, 2, x, y)];
+    jy = a.mom[plane_index(s, 3, x, y)];
+    temp = a.mom[plane_index(s, 4, x, y)];
+  } else {
+    C f[18], g[9];
+    adj_pull_node<St>(a, x, y, f, g);
+    ra = sum9(f);
+    rb = sum9(f + 9);
+    temp = sum9(g);
+    jx = momentum_x(f, f + 9);
+    jy = momentum_y(f, f + 9);
+  }
   const C rl[2] = {ra, rb};
   const C inv_rl[2] = {C(1) / ra, C(1) / rb};
   const C inv_rho = C(1) / (ra + rb);
@@ -544,7 +580,7 @@ __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
     // row adds dL/dT_b of its columns here, and the next reverse step's
     // densities go to the other aux buffer
     if (y == 0) grad_tb_column<St, true>(a, x);
-    if (a.next_state) density_node<St>(a, a.next_state, x, y, a.aux_next);
+    if (a.mom_next) density_from_moments(a, a.mom_next, x, y, a.aux_next);
   }
 }
 

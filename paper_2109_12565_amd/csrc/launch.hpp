@@ -60,9 +60,12 @@ enum class Pass {
   kStep2,        // f*(t) -> f*(t+2), fused two-step kernel (Geometry::rows2 > 0)
   kStep2TopRow,  // same (flat walls at rest), and per strip the sums of T - t_top over
                  // the top row of both steps into Device::partials [2][strips]
-  kStep2Tape,    // same (flat walls at rest, FP64 / FP32), and the intermediate state
-                 // f*(t+1) into a second buffer
-  kStep2TapeTopRow  // both: the intermediate state and the top-row sums
+  // The adjoint's tape at tau = 1 (flat walls at rest, FP64 / FP32): the
+  // moments rho_A, rho_B, j_x, j_y, T of each step's pulled state, [5] planes
+  // of pop_stride compute-type values per step.
+  kStepMoments,         // kStep at tau = 1, and the step's moments
+  kStep2Moments,        // kStep2, and the moments of both steps
+  kStep2MomentsTopRow   // kStep2TopRow, and the moments of both steps
 };
 
 template <class St>
@@ -72,8 +75,9 @@ struct Launcher {
   // Resident blocks per CU of the two-step kernel; 0 where the storage has
   // no two-step kernel.
   static int step2_blocks_per_cu(bool solid, int lanes);
-  // dst2: the second output of kStep2Tape and kStep2TapeTopRow
-  static void step(const Device& d, Pass pass, const void* src, void* dst, void* dst2 = nullptr);
+  // moments: the moment output of the kStep*Moments passes
+  static void step(const Device& d, Pass pass, const void* src, void* dst,
+                   void* moments = nullptr);
   // f(0) = equilibria of the initial fields (rho_a, rho_b, temp, ux0, uy0;
   // the velocities may be null).
   static void init_equilibrium(const Device& d, void* buf, const double* rho_a, const double* rho_b,
@@ -112,7 +116,9 @@ struct Adjoint {
   // whose densities this step then prepares; first: the sweep's first
   // reverse step (lambda of the next state is zero). At tau = tau_g = 1 the
   // adjoint of a step is carried in compact per-node planes instead of
-  // lambda, alternating with `in`.
+  // lambda, alternating with `in`, and `state` / `next_state` are the
+  // moment-tape slots of the two steps (Pass::kStepMoments) instead of
+  // states.
   static void reverse_step(const Device& d, const AdjointWork& w, const void* state, int in,
                            double kappa_top, const void* next_state, bool density_ready,
                            bool first);

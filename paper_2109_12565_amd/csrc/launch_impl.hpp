@@ -125,12 +125,16 @@ void launch_step2_kernel(const Device& d, const tlbk::StepArgs<typename St::C>& 
 template <class St>
 constexpr bool kHasStep2 = !St::kFix && (!St::kDev || St::kRest32);
 
+// Storages with the adjoint (FP64, FP32).
 template <class St>
-void launch_step2(const Device& d, const void* src, void* dst, Pass pass, void* dst2) {
+constexpr bool kHasAdjoint = !St::kFix && !St::kDev;
+
+template <class St>
+void launch_step2(const Device& d, const void* src, void* dst, Pass pass, void* moments) {
   if constexpr (kHasStep2<St>) {
     auto a = make_args<typename St::C>(d, src, dst);
     a.rows_per_block = d.geo.rows2;
-    a.dst2 = dst2;
+    a.moments = moments;
     constexpr unsigned M = tlbk::kModeStore | tlbk::kModeTauOne;
     constexpr unsigned S = tlbk::kModeSolid, V = tlbk::kModeMoving;
     // the adjoint's variants: flat walls at rest only
@@ -138,11 +142,12 @@ void launch_step2(const Device& d, const void* src, void* dst, Pass pass, void* 
       if (!d.moving && !d.has_solid) launch_step2_kernel<St, M | tlbk::kModeTopRow>(d, a);
       return;
     }
-    if (pass == Pass::kStep2Tape || pass == Pass::kStep2TapeTopRow) {
-      if constexpr (!St::kDev) {
+    if (pass == Pass::kStep2Moments || pass == Pass::kStep2MomentsTopRow) {
+      if constexpr (kHasAdjoint<St>) {
+        constexpr unsigned MM = M | tlbk::kModeMoments;
         if (d.moving || d.has_solid) return;
-        if (pass == Pass::kStep2Tape) launch_step2_kernel<St, M | tlbk::kModeTape>(d, a);
-        else launch_step2_kernel<St, M | tlbk::kModeTape | tlbk::kModeTopRow>(d, a);
+        if (pass == Pass::kStep2Moments) launch_step2_kernel<St, MM>(d, a);
+        else launch_step2_kernel<St, MM | tlbk::kModeTopRow>(d, a);
       }
       return;
     }
@@ -200,7 +205,7 @@ int Launcher<St>::blocks_per_cu(int bx, bool wide, bool solid, bool tau_one) {
 }
 
 template <class St>
-void Launcher<St>::step(const Device& d, Pass pass, const void* src, void* dst, void* dst2) {
+void Launcher<St>::step(const Device& d, Pass pass, const void* src, void* dst, void* moments) {
   using namespace tlbk;
   switch (pass) {
     case Pass::kStep: detail::launch_mode<St, kModeStore>(d, src, dst); break;
@@ -216,10 +221,19 @@ void Launcher<St>::step(const Device& d, Pass pass, const void* src, void* dst, 
     case Pass::kStressInit:
       detail::launch_mode<St, kModeFields | kModeStress | kModeInit>(d, src, dst);
       break;
+    case Pass::kStepMoments:
+      if constexpr (detail::kHasAdjoint<St>) {
+        if (d.tau_one && !d.moving && !d.has_solid) {
+          auto a = detail::make_args<typename St::C>(d, src, dst);
+          a.moments = moments;
+          detail::launch_geometry<St, kModeStore | kModeTauOne | kModeMoments>(d, a);
+        }
+      }
+      break;
     case Pass::kStep2:
     case Pass::kStep2TopRow:
-    case Pass::kStep2Tape:
-    case Pass::kStep2TapeTopRow: detail::launch_step2<St>(d, src, dst, pass, dst2); break;
+    case Pass::kStep2Moments:
+    case Pass::kStep2MomentsTopRow: detail::launch_step2<St>(d, src, dst, pass, moments); break;
   }
 }
 

@@ -187,7 +187,9 @@ template <typename C>
 struct StepArgs {
   const void* src;          // post-collision populations f*(t) (or f(0))
   void* dst;                // receives f*(t+1)
-  void* dst2;               // fused kernel, kModeTape: receives the intermediate f*(t+1)
+  void* moments;            // kModeMoments: [5][pop_stride] rho_A, rho_B, j_x, j_y, T of
+                            // the pulled state, compute type (the fused kernel
+                            // writes its second level at + 5 pop_stride)
   const uint16_t* link;     // [ly*lx] link masks (solid cells present only)
   const uint8_t* solid;     // [ly*lx] 0 fluid, 1 bottom-held, 2 top-held
   const C* t_bottom;        // [lx]
@@ -215,8 +217,8 @@ enum : unsigned {
   kModeMoving = 256u, // the flat walls move (momentum term in their bounce-back)
   kModeTopRow = 512u, // fused kernel: per-strip sums of T - t_top over the top row
                       // at both levels into partials (the taped run's loss terms)
-  kModeTape = 1024u   // fused kernel: also store the intermediate level's
-                      // populations into dst2 (the adjoint's segment recompute)
+  kModeMoments = 1024u // also write the moments of the pulled state (both
+                       // levels in the fused kernel): the adjoint's tape at tau = 1
 };
 
 // rho0 (1 - exp(-rho/rho0)) of Eq. (12), evaluated as -rho0 expm1(-rho/rho0)
@@ -987,6 +989,16 @@ __global__ __launch_bounds__(BX) void lb_step_kernel(StepArgs<typename St::C> a)
         mdst.st(yrow + p9, Lo.v0, eb + ka * (fb[0] - eb));
         mdst.st(yrow + p18, Lo.v0, eg + kg * (g[0] - eg));
       }
+    }
+    if constexpr ((kMode & kModeMoments) != 0) {
+      static_assert(!St::kDev && !St::kFix, "moments of the FP64 / FP32 storages");
+      C* mo = static_cast<C*>(a.moments);
+      const size_t ps = (size_t)a.pop_stride, q = (size_t)y * (size_t)a.pitch + (size_t)xo;
+      mo[q] = ra;
+      mo[ps + q] = rb;
+      mo[2 * ps + q] = jx;
+      mo[3 * ps + q] = jy;
+      mo[4 * ps + q] = temp;
     }
     // FP64 densities for output: reference plus the stored-form sum
     const double dra = St::kDev ? (double)a.ref_a + (double)Da : (double)ra;

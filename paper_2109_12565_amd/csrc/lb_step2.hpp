@@ -204,8 +204,8 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   static_assert((kMode & (kModeWide | kModeInit | kModeObserve | kModeFields)) == 0,
                 "32-bit offsets, no observables");
   constexpr bool kTop = (kMode & kModeTopRow) != 0;
-  constexpr bool kTape = (kMode & kModeTape) != 0;
-  static_assert(!kTape || !St::kDev, "the tape holds FP64 / FP32 states");
+  constexpr bool kMoments = (kMode & kModeMoments) != 0;
+  static_assert(!kMoments || !St::kDev, "moments of the FP64 / FP32 storages");
   constexpr int kH = 5;          // left halo lanes
   constexpr int R1 = 5, RM = 3;  // density ring rows, moment ring rows
   constexpr int W = BT + 4;      // density ring row: lanes plus 2 padding columns each side
@@ -237,7 +237,6 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   const O plane_b = (O)a.pop_stride * sizeof(T);
   const PopMem<St, kMode> msrc(a.src, (uint64_t)plane_b * kPlaneUnits<St>);
   const PopMem<St, kMode> mdst(a.dst, (uint64_t)plane_b * kPlaneUnits<St>);
-  const PopMem<St, kMode> mtape(kTape ? a.dst2 : a.dst, (uint64_t)plane_b * kPlaneUnits<St>);
 
   // lane column (periodic); lanes kH .. kH + strip_w - 1 inside the lattice
   // store, the others compute halo columns only
@@ -247,6 +246,16 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
   const LaneOff<kMode> Lo = lane_off<St, kMode>(xw, lx, plane_b, row_b);
   const int c1 = tid + 2;  // column in the density rings
   const int cm = tid + 1;  // column in the moment ring
+  // kMoments: moments of the pulled state of each level, [level][5][pop_stride]
+  auto put_moments = [&](int level, int r, C rho_a, C rho_b, C jx, C jy, C temp) {
+    C* mo = static_cast<C*>(a.moments) + (size_t)level * 5 * (size_t)a.pop_stride;
+    const size_t ps = (size_t)a.pop_stride, q = (size_t)r * (size_t)a.pitch + (size_t)xw;
+    mo[q] = rho_a;
+    mo[ps + q] = rho_b;
+    mo[2 * ps + q] = jx;
+    mo[3 * ps + q] = jy;
+    mo[4 * ps + q] = temp;
+  };
 
   const C psi_w0 = psi_of<St>(a.rho_wall0, a.rho0, a.inv_rho0);
   const C psi_w1 = psi_of<St>(a.rho_wall1, a.rho0, a.inv_rho0);
@@ -329,28 +338,8 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
     m[0] = mv[0];
     m[1] = mv[1];
     m[2] = mv[2];
-    if constexpr (kTape) {
-      // the intermediate state f*(t+1) of the chunk's own rows, each value
-      // evaluated as level 2 pulls it (pull_level2, moving_sum)
-      if (out_lane && r >= y0 && r < y1) {
-        // S + D not contracted, as in pull_level2 and moving_sum
-#pragma clang fp contract(off)
-        const O yrow = (O)r * row_b;
-#pragma unroll
-        for (int fld = 0; fld < 3; ++fld) {
-          const O base = (O)(9 * fld) * plane_b + yrow;
-#define TLB_TAPE_PAIR(P)                                                        \
-  {                                                                             \
-    C S, D;                                                                     \
-    eq_even_odd<P>(mv[fld].rho, mv[fld].ux, mv[fld].uy, mv[fld].u2, S, D);      \
-    mtape.st(base + (O)P * plane_b, Lo.v0, S + D);                              \
-    mtape.st(base + (O)Dir<P>::opp * plane_b, Lo.v0, S - D);                    \
-  }
-          TLB_TAPE_PAIR(1) TLB_TAPE_PAIR(2) TLB_TAPE_PAIR(5) TLB_TAPE_PAIR(6)
-#undef TLB_TAPE_PAIR
-          mtape.st(base, Lo.v0, mv[fld].rho - moving_sum(mv[fld]));
-        }
-      }
+    if constexpr (kMoments) {
+      if (out_lane && r >= y0 && r < y1) put_moments(0, r, Da, Db, jx, jy, Dt);
     }
   };
 
@@ -443,6 +432,7 @@ __global__ __launch_bounds__(BT) void lb_step2_kernel(StepArgs<typename St::C> a
     if constexpr (kTop) {
       if (top_chunk && r == ly - 1) top_sum[1] += (double)temp - (double)a.t_top;
     }
+    if constexpr (kMoments) put_moments(1, r, Da, Db, jx, jy, Dt);
     int rs[5];
 #pragma unroll
     for (int d = 0; d < 5; ++d) rs[d] = ring_slot<R1>(r - 2 + d);

@@ -64,6 +64,8 @@ struct tlb_handle {
   size_t ckpt_cap = 0;
   void* tape = nullptr;            // recomputed states of one segment
   size_t tape_cap = 0;
+  void* mtape = nullptr;           // tau = 1: moments of the pulled state of each
+  size_t mtape_cap = 0;            // taped step (or of one segment), 5 planes each
   void* adj = nullptr;             // AdjointWork planes
   double* adj_scalars = nullptr;   // grad [lx] + loss terms [loss_cap]
   size_t loss_cap = 0;
@@ -237,10 +239,10 @@ tlbh::Device device_view(const tlb_handle* h, double* fields = nullptr,
 }
 
 void launch_pass(const tlb_handle* h, tlbh::Pass pass, const void* src, void* dst,
-                 double* fields = nullptr, double* partials = nullptr, void* dst2 = nullptr) {
+                 double* fields = nullptr, double* partials = nullptr, void* moments = nullptr) {
   const tlbh::Device d = device_view(h, fields, partials);
   with_storage(h->p.precision,
-               [&](auto st) { tlbh::Launcher<decltype(st)>::step(d, pass, src, dst, dst2); });
+               [&](auto st) { tlbh::Launcher<decltype(st)>::step(d, pass, src, dst, moments); });
 }
 
 // Re-run the step that produced f*(t) without storing, to evaluate the
@@ -290,6 +292,12 @@ double dtdy_sum(const tlb_handle* h) {
 
 size_t state_bytes(const tlb_handle* h) {
   return buffer_planes(h->p.precision) * h->pop_stride * h->elem;
+}
+
+// Bytes of one moment-tape slot: rho_A, rho_B, j_x, j_y, T of every node in
+// the compute type (the adjoint's storages: FP64, FP32).
+size_t moment_bytes(const tlb_handle* h) {
+  return (size_t)5 * h->pop_stride * (h->p.precision == TLB_FP64 ? sizeof(double) : sizeof(float));
 }
 
 // Device buffer of at least `bytes`, reallocated when too small.
@@ -921,8 +929,17 @@ int tlb_forward_taped(tlb_handle* h, int64_t nsteps, int32_t ckpt_every, double*
   if (h->p.lx < 3) return fail(h, TLB_EINVAL, "tlb_forward_taped: lx < 3 columns");
   h->tape_valid = false;
   const size_t sb = state_bytes(h);
-  const int64_t nck = (nsteps + ckpt_every - 1) / ckpt_every;
-  int rc = ensure_buffer(h, &h->ckpt, &h->ckpt_cap, (size_t)nck * sb, "checkpoints");
+  // At tau = tau_g = 1 the reverse sweep needs only the moments of each
+  // step's pulled state: with ckpt_every = 1 the steps write those (5 values
+  // per node) and no state is kept; otherwise states are checkpointed every
+  // ckpt_every steps and each segment's moments recomputed in the sweep.
+  const bool moment_tape = h->tau_one && ckpt_every == 1;
+  const int64_t nck = moment_tape ? 0 : (nsteps + ckpt_every - 1) / ckpt_every;
+  int rc = nck > 0 ? ensure_buffer(h, &h->ckpt, &h->ckpt_cap, (size_t)nck * sb, "checkpoints")
+                   : TLB_OK;
+  if (rc == TLB_OK && moment_tape)
+    rc = ensure_buffer(h, &h->mtape, &h->mtape_cap, (size_t)nsteps * moment_bytes(h),
+                       "moment tape");
   if (rc != TLB_OK) return rc;
   tlbh::AdjointWork w;
   rc = ensure_adjoint_work(h, nsteps, &w);
@@ -940,18 +957,32 @@ int tlb_forward_taped(tlb_handle* h, int64_t nsteps, int32_t ckpt_every, double*
       tlbh::Adjoint<decltype(st)>::top_row_term(d, w, state, (int)k, stride);
     });
   };
-  if (ckpt_every == 1) {
-    // Full tape: the steps write every state f*(t0 + k), k < nsteps, straight
-    // into its slot (a fused pair also stores the state between its two
-    // steps), so the reverse sweep recomputes nothing. The last step runs
-    // from the handle's buffer, which then holds f*(t-1) as after tlb_step.
+  auto advance = [&](int n) {
+    h->cur = 1 - h->cur;
+    h->t += n;
+  };
+  if (moment_tape) {
+    auto mslot = [&](int64_t k) { return static_cast<char*>(h->mtape) + (size_t)k * moment_bytes(h); };
+    int64_t k = 0;
+    for (; fused && k + 2 < nsteps; k += 2) {
+      launch_pass(h, tlbh::Pass::kStep2MomentsTopRow, h->buf[h->cur], h->buf[1 - h->cur], nullptr,
+                  w.loss_terms + (size_t)k * stride, mslot(k));
+      advance(2);
+    }
+    for (; k < nsteps; ++k) {
+      top_row(h->buf[h->cur], k);
+      launch_pass(h, tlbh::Pass::kStepMoments, h->buf[h->cur], h->buf[1 - h->cur], nullptr,
+                  nullptr, mslot(k));
+      advance(1);
+    }
+  } else if (ckpt_every == 1) {
+    // tau != 1, every state kept: the steps write each state f*(t0 + k),
+    // k < nsteps, straight into its slot, so the sweep recomputes nothing;
+    // the last step runs from the handle's buffer, which then holds f*(t-1)
+    // as after tlb_step
     auto slot = [&](int64_t k) { return static_cast<char*>(h->ckpt) + (size_t)k * sb; };
     TLB_HIP(h, hipMemcpyAsync(slot(0), h->buf[h->cur], sb, hipMemcpyDeviceToDevice, h->stream));
-    int64_t k = 0;
-    for (; fused && k + 2 < nsteps; k += 2)
-      launch_pass(h, tlbh::Pass::kStep2TapeTopRow, slot(k), slot(k + 2), nullptr,
-                  w.loss_terms + (size_t)k * stride, slot(k + 1));
-    for (; k + 1 < nsteps; ++k) {
+    for (int64_t k = 0; k + 1 < nsteps; ++k) {
       top_row(slot(k), k);
       launch_pass(h, tlbh::Pass::kStep, slot(k), slot(k + 1));
     }
@@ -969,15 +1000,13 @@ int tlb_forward_taped(tlb_handle* h, int64_t nsteps, int32_t ckpt_every, double*
     if (fused && k + 2 < nsteps && (k + 1) % ckpt_every != 0) {
       launch_pass(h, tlbh::Pass::kStep2TopRow, h->buf[h->cur], h->buf[1 - h->cur], nullptr,
                   w.loss_terms + (size_t)k * stride);
-      h->cur = 1 - h->cur;
-      h->t += 2;
+      advance(2);
       k += 2;
       continue;
     }
     top_row(h->buf[h->cur], k);
     launch_pass(h, tlbh::Pass::kStep, h->buf[h->cur], h->buf[1 - h->cur]);
-    h->cur = 1 - h->cur;
-    h->t += 1;
+    advance(1);
     k += 1;
   }
   TLB_HIP(h, hipGetLastError());
@@ -1003,8 +1032,18 @@ int tlb_adjoint_step(tlb_handle* h, int64_t nsteps, double seed, double* grad_t_
     return fail(h, TLB_ESTATE, "tlb_adjoint_step: %lld steps requested, the tape holds %lld",
                 (long long)nsteps, (long long)h->taped_steps);
   const int K = h->ckpt_every;
-  const size_t sb = state_bytes(h);
-  int rc = K > 1 ? ensure_buffer(h, &h->tape, &h->tape_cap, (size_t)(K - 1) * sb, "tape") : TLB_OK;
+  const size_t sb = state_bytes(h), mb = moment_bytes(h);
+  // tau = 1: moments of the pulled states (all of them with K = 1; with K > 1
+  // a segment's, recomputed through two scratch states); else states (a
+  // segment's K - 1 recomputed ones)
+  const bool moments = h->tau_one;
+  int rc = TLB_OK;
+  if (moments && K > 1) {
+    rc = ensure_buffer(h, &h->tape, &h->tape_cap, 2 * sb, "tape");
+    if (rc == TLB_OK) rc = ensure_buffer(h, &h->mtape, &h->mtape_cap, (size_t)K * mb, "moment tape");
+  } else if (!moments && K > 1) {
+    rc = ensure_buffer(h, &h->tape, &h->tape_cap, (size_t)(K - 1) * sb, "tape");
+  }
   if (rc != TLB_OK) return rc;
   tlbh::AdjointWork w;
   rc = ensure_adjoint_work(h, nsteps, &w);
@@ -1015,43 +1054,68 @@ int tlb_adjoint_step(tlb_handle* h, int64_t nsteps, double seed, double* grad_t_
   // dL/dT(x) of each top-row node at each step
   const double kappa_top = seed * 2.0 * h->p.ly / (h->p.dt_nominal * h->p.lx * (double)nsteps);
   const tlbh::Device d = device_view(h);
-  const int64_t nck = (nsteps + K - 1) / K;
+  const bool fused = h->launch.rows2 > 0;
+  // segments swept in reverse; the full moment tape is one segment
+  const int64_t seg_len = moments && K == 1 ? nsteps : K;
+  const int64_t nseg = (nsteps + seg_len - 1) / seg_len;
   int in = 0;
   bool first = true, ready = false;
-  for (int64_t seg = nck - 1; seg >= 0; --seg) {
-    const int64_t s0 = seg * K;
-    const int len = (int)std::min<int64_t>(K, nsteps - s0);
+  auto reverse = [&](const void* state, const void* next) {
+    with_adjoint_storage(h, [&](auto st) {
+      tlbh::Adjoint<decltype(st)>::reverse_step(d, w, state, in, kappa_top, next, ready, first);
+    });
+    ready = next != nullptr;
+    first = false;
+    in = 1 - in;
+  };
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t s0 = seg * seg_len;
+    const int len = (int)std::min<int64_t>(seg_len, nsteps - s0);
+    const void* ck = K > 1 ? static_cast<char*>(h->ckpt) + (size_t)seg * sb : nullptr;
+    if (moments) {
+      auto mslot = [&](int64_t j) {
+        return static_cast<char*>(h->mtape) + (size_t)(K == 1 ? s0 + j : j) * mb;
+      };
+      if (K > 1) {
+        // the moments of steps s0 .. s0 + len - 1, from the checkpoint
+        // through the two scratch states
+        const void* src = ck;
+        int b = 0;
+        for (int j = 0; j < len;) {
+          void* dst = static_cast<char*>(h->tape) + (size_t)b * sb;
+          if (fused && j + 1 < len) {
+            launch_pass(h, tlbh::Pass::kStep2Moments, src, dst, nullptr, nullptr, mslot(j));
+            j += 2;
+          } else {
+            launch_pass(h, tlbh::Pass::kStepMoments, src, dst, nullptr, nullptr, mslot(j));
+            j += 1;
+          }
+          src = dst;
+          b = 1 - b;
+        }
+        // the segment's first reverse step cannot prepare the next one's
+        // densities: the previous segment is not recomputed yet
+        ready = false;
+      }
+      for (int j = len - 1; j >= 0; --j) reverse(mslot(j), j > 0 ? mslot(j - 1) : nullptr);
+      continue;
+    }
     auto slot = [&](int j) -> void* {
       return j == 0 ? static_cast<char*>(h->ckpt) + (size_t)seg * sb
                     : static_cast<char*>(h->tape) + (size_t)(j - 1) * sb;
     };
-    // recompute the segment's states: fused launches that also store the
-    // intermediate state where two more are needed, else single steps
-    for (int j = 1; j < len;) {
-      if (h->launch.rows2 > 0 && j + 1 < len) {
-        launch_pass(h, tlbh::Pass::kStep2Tape, slot(j - 1), slot(j + 1), nullptr, nullptr,
-                    slot(j));
-        j += 2;
-      } else {
-        launch_pass(h, tlbh::Pass::kStep, slot(j - 1), slot(j));
-        j += 1;
-      }
-    }
+    // tau != 1: recompute the segment's states with single steps
+    for (int j = 1; j < len; ++j) launch_pass(h, tlbh::Pass::kStep, slot(j - 1), slot(j));
     // within a segment each reverse step also prepares the densities of the
     // next one's state (the previous slot); the segment's first step (j = 0)
-    // cannot, the previous segment is not recomputed yet, except with the
-    // full tape (ckpt_every = 1), whose previous state is a checkpoint
+    // cannot, the previous segment is not recomputed yet, except with every
+    // state kept (K = 1), whose previous state is a checkpoint
     if (K > 1) ready = false;
     for (int j = len - 1; j >= 0; --j) {
       void* next = j > 0    ? slot(j - 1)
                    : K == 1 && seg > 0 ? static_cast<char*>(h->ckpt) + (size_t)(seg - 1) * sb
                                        : nullptr;
-      with_adjoint_storage(h, [&](auto st) {
-        tlbh::Adjoint<decltype(st)>::reverse_step(d, w, slot(j), in, kappa_top, next, ready, first);
-      });
-      ready = next != nullptr;
-      first = false;
-      in = 1 - in;
+      reverse(slot(j), next);
     }
   }
   TLB_HIP(h, hipGetLastError());
@@ -1068,8 +1132,8 @@ int tlb_destroy(tlb_handle* h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   void* ptrs[] = {h->buf[0],   h->buf[1],     h->link,       h->solid,      h->t_bottom,
                   h->partials, h->obs,        h->fields,     h->rows,       h->export_buf,
-                  h->ckpt,     h->tape,       h->adj,        h->adj_scalars, h->drop_nodes,
-                  h->drop_tiles, h->drop_error, h->drop_tb,  h->drop_acc};
+                  h->ckpt,     h->tape,       h->mtape,      h->adj,        h->adj_scalars,
+                  h->drop_nodes, h->drop_tiles, h->drop_error, h->drop_tb,  h->drop_acc};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);

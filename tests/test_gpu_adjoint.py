@@ -190,11 +190,12 @@ def test_fused_taped_run_matches_fused_steps_and_single_step_adjoint():
 
 @pytest.mark.parametrize("n", [30, 31])
 def test_full_tape_fused_run_matches_steps_and_oracle(n):
-    """ckpt_every = 1 keeps every state, written by the steps themselves
-    (fused pairs store the state between their two steps); the run advances
-    bitwise like tlb_step, the other buffer holds the previous state (the
-    fields of the current time agree), and loss and gradient match the
-    oracle adjoint and the checkpointed run (FP64)."""
+    """ckpt_every = 1 at tau = 1 keeps the moments of every step's pulled
+    state, written by the steps themselves (fused pairs both levels'), and no
+    state; the run advances bitwise like tlb_step, the other buffer holds the
+    previous state (the fields of the current time agree), and loss and
+    gradient match the oracle adjoint and the checkpointed run, whose
+    segments are recomputed into moments (FP64)."""
     case = buoyant_case()
     fused = {"fused": "always"}
     with make_sim(case, "fp64", launch=fused) as a, make_sim(case, "fp64", launch=fused) as b, \
