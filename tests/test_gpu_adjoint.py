@@ -12,7 +12,8 @@ Bars:
     segments are ragged;
   * FP32 GPU gradient = central finite differences of the FP64 GPU loss
     (h = 1e-3) to 1e-3 of max|FD| at 16 seeded columns of a 1024 x 64
-    strip, N = 500, checkpoints every 25 steps;
+    strip, N = 500, checkpoints every 25 steps; with the moments of every
+    step kept, = the FP64 gradient to 1e-3 of its max;
   * at 1024 x 512 over 500 steps the top wall is outside the bottom wall's
     domain of dependence for any practical purpose (sound front c_s N ~ 289
     rows, thermal diffusion length sqrt(kappa N) ~ 9 rows): both the adjoint
@@ -70,7 +71,7 @@ def buoyant_case():
                 params=dict(workloads.BASE_PARAMS, alpha_g=5e-3))
 
 
-@pytest.mark.parametrize("ckpt", [25, 7, 1])
+@pytest.mark.parametrize("ckpt", [25, 7, 2, 1])
 def test_fp64_adjoint_matches_oracle_buoyant(ckpt):
     case = buoyant_case()
     n = 60
@@ -92,11 +93,13 @@ def test_fp64_adjoint_matches_oracle_small_case():
     assert np.abs(g - go).max() <= 1e-10 * np.abs(go).max()
 
 
-def test_fp64_adjoint_matches_oracle_general_tau():
-    """tau != 1 exercises the relaxation terms of the adjoint (FP64)."""
+@pytest.mark.parametrize("ckpt", [10, 1])
+def test_fp64_adjoint_matches_oracle_general_tau(ckpt):
+    """tau != 1 exercises the relaxation terms of the adjoint (FP64); its
+    tape holds states (checkpoints every 10 steps, or every state)."""
     case = buoyant_case()
     n = 40
-    loss, g = gpu_loss_and_grad(case, "fp64", case["t_bottom"], n, 10, tau=0.8, tau_g=1.3)
+    loss, g = gpu_loss_and_grad(case, "fp64", case["t_bottom"], n, ckpt, tau=0.8, tau_g=1.3)
     lo, go = oracle_loss_and_grad(case, case["t_bottom"], n, tau=0.8, tau_g=1.3)
     assert abs(loss - lo) <= 1e-12 * abs(lo)
     assert np.abs(g - go).max() <= 1e-10 * np.abs(go).max()
@@ -113,6 +116,7 @@ def test_fp32_adjoint_matches_finite_differences_strip():
     tb = workloads.bottom_temperature_noise(lx, 5)
     cols = np.sort(np.random.default_rng(6).choice(lx, 16, replace=False))
     _, g32 = gpu_loss_and_grad(case, "fp32", tb, n, 25)
+    _, g32_all = gpu_loss_and_grad(case, "fp32", tb, n, 1)  # moments of every step
     _, g64 = gpu_loss_and_grad(case, "fp64", tb, n, 25)
     fd = []
     for c in cols:
@@ -126,6 +130,7 @@ def test_fp32_adjoint_matches_finite_differences_strip():
     assert np.abs(g64[cols] - fd).max() <= 1e-5 * scale
     assert np.abs(g32[cols] - fd).max() <= 1e-3 * scale
     assert np.abs(g32 - g64).max() <= 1e-3 * np.abs(g64).max()
+    assert np.abs(g32_all - g64).max() <= 1e-3 * np.abs(g64).max()
 
 
 def test_adjoint_vanishes_outside_domain_of_dependence_mid():
