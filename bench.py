@@ -395,6 +395,23 @@ def main() -> int:
         roof["traffic"] = round(traffic / per_launch_s / 1e9, 1)
         roof["traffic_bytes_per_launch"] = traffic
         roof["traffic_frac"] = round(traffic / per_launch_s / 1e9 / HBM_PEAK_GBS, 4)
+    # measured device-copy ceiling (1 GiB read + 1 GiB written, best of 3),
+    # the practical bound beside the nominal peak
+    cbuf = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+    csrc, cdst = cbuf[: 1 << 30], cbuf[1 << 30:]
+    best = float("inf")
+    for _ in range(4):
+        ea, eb = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+        ea.record(stream)
+        cdst.copy_(csrc)
+        eb.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, ea.elapsed_time(eb))
+    del cbuf, csrc, cdst
+    copy_gbs = 2.0 * (1 << 30) / (best * 1e-3) / 1e9
+    roof["copy_ceiling"] = {"GBps": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
+                            "how": "torch device copy of 1 GiB, HIP events, best of 4"}
+    roof["frac_of_copy_ceiling"] = round(achieved / copy_gbs, 4)
     single_gbs = bpn * nodes / single_s / 1e9
     roof["single_step_kernel"] = {"kernel": "lb_step_kernel (with the observable sums)",
                                   "launch_us": round(single_s * 1e6, 2),
