@@ -384,9 +384,10 @@ def main() -> int:
             "frac_of_min_bytes": round(moved / HBM_PEAK_GBS, 4),
             "launches": {"fused": n_fused, "single": n_single},
             # what the counters show limits the kernel: the fused kernel does two
-            # steps' arithmetic per pass over HBM and is bound by vector
-            # instruction issue; the 4- and 8-byte single step by HBM
-            "limiter": "valu-issue" if n_fused > 0 or BYTES_PER_UPDATE[args.precision] <= 120
+            # steps' arithmetic per pass over HBM at 8 wavefronts per CU (LDS
+            # caps it) and is bound by latency and instruction issue, as is the
+            # 16-bit single step; the 4- and 8-byte single step by HBM
+            "limiter": "latency-issue" if n_fused > 0 or BYTES_PER_UPDATE[args.precision] <= 120
                        else "hbm"}
     traffic = measured_traffic(w["name"], args.precision, kernel)
     if traffic is not None:
