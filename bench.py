@@ -410,9 +410,13 @@ def main() -> int:
         best = min(best, ea.elapsed_time(eb))
     del cbuf, csrc, cdst
     copy_gbs = 2.0 * (1 << 30) / (best * 1e-3) / 1e9
-    roof["copy_ceiling"] = {"GBps": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
-                            "how": "torch device copy of 1 GiB, HIP events, best of 4"}
-    roof["frac_of_copy_ceiling"] = round(achieved / copy_gbs, 4)
+    # achieved over it can exceed 1 for the fused kernel (two updates per
+    # pass over HBM); the counted traffic over it cannot
+    roof["copy_ceiling"] = {
+        "GBps": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
+        "how": "torch device copy of 1 GiB, HIP events, best of 4",
+        "achieved_over_copy": round(achieved / copy_gbs, 4),
+        "traffic_over_copy": None if roof["traffic"] is None else round(roof["traffic"] / copy_gbs, 4)}
     single_gbs = bpn * nodes / single_s / 1e9
     roof["single_step_kernel"] = {"kernel": "lb_step_kernel (with the observable sums)",
                                   "launch_us": round(single_s * 1e6, 2),
