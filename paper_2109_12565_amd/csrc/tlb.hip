@@ -185,16 +185,19 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
       return g;
     };
     const Fused wide = fused_geometry(tlbh::kStep2Lanes);
-    const int per_cu2 = wide.per_cu;
     // Narrow blocks where wide ones would leave chunks of fewer than 16 rows:
     // a block's time is then mostly its chain of first-level halo rows, and
     // twice as many resident narrow blocks take shorter chunks (FP32 per
     // fused launch, 256 / 128 lanes: 1024 x 512 54.8 / 49.5 us, 1024 x 64
     // 28.7 / 27.0, 128 x 64 24.8 / 23.5; 4096 x 2048 with 69-row chunks
-    // 527 / 596, FP16 deviations 494 / 512).
+    // 527 / 596, FP16 deviations 494 / 512). Also where wide blocks do not
+    // fit twice per CU (FP64: 158 KB of LDS), since one resident block per
+    // CU does not pay (FP64 per step, single / fused 256 / fused 128 lanes:
+    // 4096 x 2048 751.7 / 769.0 / 677.5 us, 1024 x 512 64.8 / 63.0 / 52.2).
     const bool narrow = p.fused_lanes == tlbh::kStep2LanesNarrow ||
-                        (p.fused_lanes == 0 && wide.rows < 16);
+                        (p.fused_lanes == 0 && (wide.rows < 16 || wide.per_cu < 2));
     const Fused g2 = narrow ? fused_geometry(tlbh::kStep2LanesNarrow) : wide;
+    const int per_cu2 = g2.per_cu;
     const long long strips2 = g2.strips;
     const int strip2 = g2.strip;
     long long rows2 = g2.rows;
@@ -202,11 +205,9 @@ tlbh::Geometry choose_launch(const tlb_params& p, size_t buffer_bytes, bool soli
     // measured, the chunk height being the one that fills the slots once
     // (FP32 per step, fused / single: 128 x 64 12.7 / 20.1 us, 1024 x 64
     // 14.9 / 20.7, 1024 x 256 20.9 / 28.0, 1024 x 512 28.1 / 36.8, 2048 x
-    // 1024 68.7 / 101.5, 4096 x 2048 263 / 377; the 16-bit storages equal or
-    // faster); taller chunks in a second wave of blocks cost more than the
-    // halo rows they save. FP64 (139 KB of LDS, one block per CU) measured
-    // 1577 us per fused launch against 2 x 766 us of single steps at 4096 x
-    // 2048.
+    // 1024 68.7 / 101.5, 4096 x 2048 263 / 377, all in 256-lane blocks; the
+    // 16-bit storages equal or faster); taller chunks in a second wave of
+    // blocks cost more than the halo rows they save.
     const bool pays = per_cu2 >= 2;
     if (per_cu2 > 0 && (pays || p.fused == TLB_FUSED_ALWAYS)) {
       if (p.fused_rows > 0) rows2 = p.fused_rows;

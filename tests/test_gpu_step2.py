@@ -254,6 +254,19 @@ def test_fused_launch_geometry():
     assert info2["fused_rows"] == 40 and info2["fused_strip"] <= 200
 
 
+def test_fp64_runs_the_fused_kernel_in_narrow_blocks():
+    """FP64: a 256-lane block needs most of a CU's LDS, so the library takes
+    128-lane blocks (two per CU) at 4096 x 2048 too."""
+    w = workloads.large()
+    sim = Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], solid=w["solid"],
+                     t_bottom=w["t_bottom"], precision="fp64")
+    info = sim.launch_info()
+    sim.close()
+    assert info["fused_rows"] > 0 and info["fused_lanes"] == 128 and info["fused_strip"] <= 118
+    assert info["fused_grid_x"] * info["fused_strip"] >= w["lx"]
+    assert info["fused_grid_y"] * info["fused_rows"] >= w["ly"]
+
+
 def test_fused_launch_geometry_narrow_blocks():
     """At 1024 x 512 blocks of 256 lanes would leave chunks of 6 rows: the
     library takes 128-lane blocks (strips of at most 118 stored columns),
