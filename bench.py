@@ -132,8 +132,8 @@ def adjoint_ratio(steps: int, ckpt: int, precision: str, config: str = "mid") ->
         sim.forward_taped(warm, ckpt)
         sim.adjoint(warm)
     # device memory of the tape (without row padding): at tau = tau_g = 1 the
-    # moments of every step (K = 1), or checkpoints, a segment's moments and
-    # two scratch states; else states
+    # moments of every step (K = 1), or checkpoints, two segments' moments
+    # and two scratch states; else states
     elem = 8 if precision == "fp64" else 4
     state_bytes = 27 * w["lx"] * w["ly"] * elem
     moment_bytes = 5 * w["lx"] * w["ly"] * elem
@@ -146,7 +146,7 @@ def adjoint_ratio(steps: int, ckpt: int, precision: str, config: str = "mid") ->
         t_fwd, _ = timed(lambda: sim.step(steps))
     nck = -(-steps // ckpt)
     if tau_one:
-        tape = steps * moment_bytes if ckpt == 1 else (nck + 2) * state_bytes + ckpt * moment_bytes
+        tape = steps * moment_bytes if ckpt == 1 else (nck + 2) * state_bytes + 2 * ckpt * moment_bytes
     else:
         tape = (nck + ckpt - 1) * state_bytes
     tape_gib = tape / 2**30

@@ -30,6 +30,11 @@ struct tlb_handle {
   int device = 0;                  // HIP device current at tlb_init
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // the adjoint's second stream (segment recompute beside the reverse
+  // sweep, default priority) and its events, created on first use
+  hipStream_t side = nullptr;
+  hipEvent_t ev_side[2] = {nullptr, nullptr};   // recompute of a segment done
+  hipEvent_t ev_main[3] = {nullptr, nullptr, nullptr};  // reverse sweep done, start
   int pitch = 0;
   long long pop_stride = 0;
   size_t elem = 0;                 // bytes per stored population value
@@ -1035,13 +1040,20 @@ int tlb_adjoint_step(tlb_handle* h, int64_t nsteps, double seed, double* grad_t_
   const int K = h->ckpt_every;
   const size_t sb = state_bytes(h), mb = moment_bytes(h);
   // tau = 1: moments of the pulled states (all of them with K = 1; with K > 1
-  // a segment's, recomputed through two scratch states); else states (a
+  // two segments' worth, recomputed through two scratch states on the side
+  // stream while the main stream sweeps the segment after); else states (a
   // segment's K - 1 recomputed ones)
   const bool moments = h->tau_one;
   int rc = TLB_OK;
   if (moments && K > 1) {
     rc = ensure_buffer(h, &h->tape, &h->tape_cap, 2 * sb, "tape");
-    if (rc == TLB_OK) rc = ensure_buffer(h, &h->mtape, &h->mtape_cap, (size_t)K * mb, "moment tape");
+    if (rc == TLB_OK)
+      rc = ensure_buffer(h, &h->mtape, &h->mtape_cap, 2 * (size_t)K * mb, "moment tape");
+    if (rc == TLB_OK && !h->side) {
+      TLB_HIP(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+      for (hipEvent_t& e : h->ev_side) TLB_HIP(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      for (hipEvent_t& e : h->ev_main) TLB_HIP(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
   } else if (!moments && K > 1) {
     rc = ensure_buffer(h, &h->tape, &h->tape_cap, (size_t)(K - 1) * sb, "tape");
   }
@@ -1069,35 +1081,59 @@ int tlb_adjoint_step(tlb_handle* h, int64_t nsteps, double seed, double* grad_t_
     first = false;
     in = 1 - in;
   };
+  // tau = 1, K > 1: the moments of segment `seg` (steps s0 .. s0 + len - 1)
+  // from its checkpoint through the two scratch states, on the side stream,
+  // into half seg % 2 of the moment tape
+  tlbh::Device side = d;
+  side.stream = h->side;
+  auto mseg = [&](int64_t seg, int64_t j) {
+    return static_cast<char*>(h->mtape) + ((size_t)(seg % 2) * K + (size_t)j) * mb;
+  };
+  auto recompute = [&](int64_t seg) {
+    const int len = (int)std::min<int64_t>(K, nsteps - seg * K);
+    const void* src = static_cast<char*>(h->ckpt) + (size_t)seg * sb;
+    int b = 0;
+    for (int j = 0; j < len;) {
+      void* dst = static_cast<char*>(h->tape) + (size_t)b * sb;
+      const bool pair = fused && j + 1 < len;
+      with_storage(h->p.precision, [&](auto st) {
+        tlbh::Launcher<decltype(st)>::step(
+            side, pair ? tlbh::Pass::kStep2Moments : tlbh::Pass::kStepMoments, src, dst, mseg(seg, j));
+      });
+      j += pair ? 2 : 1;
+      src = dst;
+      b = 1 - b;
+    }
+  };
+  if (moments && K > 1) {
+    // the side stream starts after the main stream's work so far
+    TLB_HIP(h, hipEventRecord(h->ev_main[2], h->stream));
+    TLB_HIP(h, hipStreamWaitEvent(h->side, h->ev_main[2], 0));
+    recompute(nseg - 1);
+    TLB_HIP(h, hipEventRecord(h->ev_side[(nseg - 1) % 2], h->side));
+  }
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t s0 = seg * seg_len;
     const int len = (int)std::min<int64_t>(seg_len, nsteps - s0);
-    const void* ck = K > 1 ? static_cast<char*>(h->ckpt) + (size_t)seg * sb : nullptr;
-    if (moments) {
-      auto mslot = [&](int64_t j) {
-        return static_cast<char*>(h->mtape) + (size_t)(K == 1 ? s0 + j : j) * mb;
-      };
-      if (K > 1) {
-        // the moments of steps s0 .. s0 + len - 1, from the checkpoint
-        // through the two scratch states
-        const void* src = ck;
-        int b = 0;
-        for (int j = 0; j < len;) {
-          void* dst = static_cast<char*>(h->tape) + (size_t)b * sb;
-          if (fused && j + 1 < len) {
-            launch_pass(h, tlbh::Pass::kStep2Moments, src, dst, nullptr, nullptr, mslot(j));
-            j += 2;
-          } else {
-            launch_pass(h, tlbh::Pass::kStepMoments, src, dst, nullptr, nullptr, mslot(j));
-            j += 1;
-          }
-          src = dst;
-          b = 1 - b;
-        }
-        // the segment's first reverse step cannot prepare the next one's
-        // densities: the previous segment is not recomputed yet
-        ready = false;
+    if (moments && K > 1) {
+      // recompute the segment before on the side stream once the sweep of
+      // the segment after (which used the same half of the moment tape) is
+      // done, then sweep this one when its own recompute is done
+      if (seg > 0) {
+        if (seg + 1 < nseg) TLB_HIP(h, hipStreamWaitEvent(h->side, h->ev_main[(seg + 1) % 2], 0));
+        recompute(seg - 1);
+        TLB_HIP(h, hipEventRecord(h->ev_side[(seg - 1) % 2], h->side));
       }
+      TLB_HIP(h, hipStreamWaitEvent(h->stream, h->ev_side[seg % 2], 0));
+      // the segment's first reverse step cannot prepare the next one's
+      // densities: the previous segment is not recomputed yet
+      ready = false;
+      for (int j = len - 1; j >= 0; --j) reverse(mseg(seg, j), j > 0 ? mseg(seg, j - 1) : nullptr);
+      TLB_HIP(h, hipEventRecord(h->ev_main[seg % 2], h->stream));
+      continue;
+    }
+    if (moments) {
+      auto mslot = [&](int64_t j) { return static_cast<char*>(h->mtape) + (size_t)(s0 + j) * mb; };
       for (int j = len - 1; j >= 0; --j) reverse(mslot(j), j > 0 ? mslot(j - 1) : nullptr);
       continue;
     }
@@ -1137,6 +1173,11 @@ int tlb_destroy(tlb_handle* h) {
                   h->drop_nodes, h->drop_tiles, h->drop_error, h->drop_tb,  h->drop_acc};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  for (hipEvent_t e : h->ev_side)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->ev_main)
+    if (e) (void)hipEventDestroy(e);
+  if (h->side) (void)hipStreamDestroy(h->side);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return TLB_OK;
