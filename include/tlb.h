@@ -280,8 +280,10 @@ int tlb_forward_taped(tlb_handle *h, int64_t nsteps, int32_t ckpt_every, double 
  * adjoint of Eqs. (1)-(3), (6)-(12), (16)-(18), (22) and of the
  * anti-bounce-back wall source 2 w_i T_b). Each checkpoint segment is
  * recomputed (at tau = tau_g = 1 into the moments of its ckpt_every steps,
- * else into ckpt_every - 1 states; nothing for ckpt_every = 1), then swept
- * backwards one step at a time. nsteps must equal the taped count. The
+ * on a second stream the handle owns, one segment ahead of the sweep and
+ * ordered with the handle's stream by events; else into ckpt_every - 1
+ * states; nothing for ckpt_every = 1), then swept backwards one step at a
+ * time. nsteps must equal the taped count. The
  * handle's current state is not changed. Synchronises the stream.
  * Errors: TLB_ESTATE (no valid tape, or nsteps differs from it),
  * TLB_EINVAL (NULL grad_t_bottom), TLB_ENOMEM, TLB_EDEVICE. */
