@@ -308,6 +308,18 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
   constexpr int NF = kTauOne ? 9 : 4;
   __shared__ AdjTile<C, NF> tile;
   const int x0 = blockIdx.x * kAdjTX, y0 = blockIdx.y * kAdjTY;
+  const int tx = threadIdx.x % kAdjTX, ty = threadIdx.x / kAdjTX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool valid = x < s.lx && y < s.ly;
+  // tau = 1: the node's taped moments, loaded before the tile so that the
+  // two latencies overlap
+  C mo[5] = {0, 0, 0, 0, 0};
+  if constexpr (kTauOne) {
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) mo[k] = a.mom[plane_index(s, k, x, y)];
+    }
+  }
   {
     // wall rows: the wetting densities; no lambda is gathered from them
     C wall[NF] = {s.rho_wall0, s.rho_wall1, psi_exp(s.rho_wall0, s.rho0, s.inv_rho0),
@@ -322,20 +334,18 @@ __global__ __launch_bounds__(256) void adj_local(AdjArgs<typename St::C> a) {
     });
   }
   __syncthreads();
-  const int tx = threadIdx.x % kAdjTX, ty = threadIdx.x / kAdjTX;
-  const int x = x0 + tx, y = y0 + ty;
-  if (x >= s.lx || y >= s.ly) return;
+  if (!valid) return;
   const int cx0 = tx + kAdjHalo, cy0 = ty + kAdjHalo;
 
   // ---- forward recompute: the moments of the pulled state (taped at tau =
   // 1, else pulled from the state)
   C ra, rb, temp, jx, jy;
   if constexpr (kTauOne) {
-    ra = a.mom[plane_index(s, 0, x, y)];
-    rb = a.mom[plane_index(s, 1, x, y)];
-    jx = a.mom[plane_index(s, 2, x, y)];
-    jy = a.mom[plane_index(s, 3, x, y)];
-    temp = a.mom[plane_index(s, 4, x, y)];
+    ra = mo[0];
+    rb = mo[1];
+    jx = mo[2];
+    jy = mo[3];
+    temp = mo[4];
   } else {
     C f[18], g[9];
     adj_pull_node<St>(a, x, y, f, g);
@@ -501,6 +511,25 @@ __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
   // halo; zero beyond the walls (no force there)
   __shared__ AdjTile<C, 8> tile;
   const int x0 = blockIdx.x * kAdjTX, y0 = blockIdx.y * kAdjTY;
+  const int tx = threadIdx.x % kAdjTX, ty = threadIdx.x / kAdjTX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool valid = x < s.lx && y < s.ly;
+  // the node's own inputs, loaded before the tile so that the latencies
+  // overlap: psi_l (for d psi / d rho), at tau = 1 its own dL/drho_l and the
+  // next reverse step's densities
+  C own_psi[2] = {0, 0}, own_rbar[2] = {0, 0}, next_rho[2] = {0, 0};
+  if (valid) {
+    own_psi[0] = a.aux[plane_index(s, 2, x, y)];
+    own_psi[1] = a.aux[plane_index(s, 3, x, y)];
+    if constexpr (kTauOne) {
+      own_rbar[0] = a.fbar[plane_index(s, kCompactRbar, x, y)];
+      own_rbar[1] = a.fbar[plane_index(s, kCompactRbar + 1, x, y)];
+      if (a.mom_next) {
+        next_rho[0] = a.mom_next[plane_index(s, 0, x, y)];
+        next_rho[1] = a.mom_next[plane_index(s, 1, x, y)];
+      }
+    }
+  }
   for (int c = threadIdx.x; c < kAdjTW * kAdjTH; c += 256) {
     const int cx = c % kAdjTW, cy = c / kAdjTW;
     const int xx = tile_column(x0 - kAdjHalo + cx, s.lx), yy = y0 - kAdjHalo + cy;
@@ -521,9 +550,7 @@ __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
     }
   }
   __syncthreads();
-  const int tx = threadIdx.x % kAdjTX, ty = threadIdx.x / kAdjTX;
-  const int x = x0 + tx, y = y0 + ty;
-  if (x >= s.lx || y >= s.ly) return;
+  if (!valid) return;
   const int cx0 = tx + kAdjHalo, cy0 = ty + kAdjHalo;
   const C gcross = s.g12 * s.inv_rho0 * s.inv_rho0;
   const C ga[2] = {s.ga0, s.ga1}, gr[2] = {s.gr0, s.gr1};
@@ -569,10 +596,10 @@ __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
     cr[1 - l] = -gcross * acc;
   }
   for (int l = 0; l < 2; ++l) {
-    const C dps = C(1) - a.aux[plane_index(s, 2 + l, x, y)] * s.inv_rho0;
+    const C dps = C(1) - own_psi[l] * s.inv_rho0;
     C r = cr[l] + v[l] * dps;
     // tau = 1: the node's own dL/drho_l joins it (one plane to gather later)
-    if constexpr (kTauOne) r = a.fbar[plane_index(s, kCompactRbar + l, x, y)] + r;
+    if constexpr (kTauOne) r = own_rbar[l] + r;
     a.rbar[plane_index(s, l, x, y)] = r;
   }
   if constexpr (kTauOne) {
@@ -580,7 +607,12 @@ __global__ __launch_bounds__(256) void adj_scatter(AdjArgs<typename St::C> a) {
     // row adds dL/dT_b of its columns here, and the next reverse step's
     // densities go to the other aux buffer
     if (y == 0) grad_tb_column<St, true>(a, x);
-    if (a.mom_next) density_from_moments(a, a.mom_next, x, y, a.aux_next);
+    if (a.mom_next) {
+      a.aux_next[plane_index(s, 0, x, y)] = next_rho[0];
+      a.aux_next[plane_index(s, 1, x, y)] = next_rho[1];
+      a.aux_next[plane_index(s, 2, x, y)] = psi_exp(next_rho[0], s.rho0, s.inv_rho0);
+      a.aux_next[plane_index(s, 3, x, y)] = psi_exp(next_rho[1], s.rho0, s.inv_rho0);
+    }
   }
 }
 
