@@ -256,7 +256,9 @@ int tlb_set_bottom_temperature(tlb_handle *h, const double *t_bottom);
 /* Taped forward run for the discrete adjoint (flat walls only, FP64 or FP32
  * storage). Advances nsteps >= 1 steps exactly as tlb_step does, keeping a
  * device copy of the state f* every ckpt_every >= 1 steps (the first at the
- * current time t0), and evaluates the loss
+ * current time t0; ckpt_every = 0: 1 when the tape of every step fits in
+ * half of the free device memory, else the shortest interval whose
+ * checkpoints do), and evaluates the loss
  *   L = (1/nsteps) sum_{t = t0+1}^{t0+nsteps} Nu_top(t),
  * Nu_top(t) = 2 ly / dt_nominal * mean over row ly-1 of (T(t) - t_top), the
  * time-averaged top-wall Nusselt number (Sec. 3.3.2, Eq. (24) in top-wall

@@ -328,8 +328,9 @@ class Simulation:
         self._check(self._lib.tlb_set_bottom_temperature(self._h, _dp(tb)))
 
     def forward_taped(self, nsteps: int, ckpt_every: int = 25) -> float:
-        """Advance ``nsteps`` steps keeping checkpoints every ``ckpt_every``;
-        returns the time-averaged top-wall Nusselt number over them."""
+        """Advance ``nsteps`` steps keeping checkpoints every ``ckpt_every``
+        (0: chosen by the library from the free device memory); returns the
+        time-averaged top-wall Nusselt number over them."""
         loss = ctypes.c_double()
         self._tape_generation += 1
         self._check(self._lib.tlb_forward_taped(self._h, int(nsteps), int(ckpt_every),

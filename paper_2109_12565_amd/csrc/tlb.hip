@@ -919,8 +919,8 @@ int tlb_set_bottom_temperature(tlb_handle* h, const double* t_bottom) {
 
 int tlb_forward_taped(tlb_handle* h, int64_t nsteps, int32_t ckpt_every, double* loss) {
   if (!h) return fail(nullptr, TLB_EINVAL, "tlb_forward_taped: NULL handle");
-  if (nsteps < 1 || ckpt_every < 1)
-    return fail(h, TLB_EINVAL, "tlb_forward_taped: need nsteps >= 1 and ckpt_every >= 1");
+  if (nsteps < 1 || ckpt_every < 0)
+    return fail(h, TLB_EINVAL, "tlb_forward_taped: need nsteps >= 1 and ckpt_every >= 0");
   if (h->has_solid)
     return fail(h, TLB_EINVAL, "tlb_forward_taped: the adjoint supports flat walls only");
   if (h->p.precision != TLB_FP64 && h->p.precision != TLB_FP32)
@@ -935,6 +935,21 @@ int tlb_forward_taped(tlb_handle* h, int64_t nsteps, int32_t ckpt_every, double*
   if (h->p.lx < 3) return fail(h, TLB_EINVAL, "tlb_forward_taped: lx < 3 columns");
   h->tape_valid = false;
   const size_t sb = state_bytes(h);
+  if (ckpt_every == 0) {
+    // every step when its tape (moments at tau = 1, else states) fits in half
+    // of the free device memory; else the shortest checkpoint interval whose
+    // checkpoints do
+    size_t free_b = 0, total_b = 0;
+    TLB_HIP(h, hipMemGetInfo(&free_b, &total_b));
+    const double budget = 0.5 * (double)free_b;
+    const double per_step = h->tau_one ? (double)moment_bytes(h) : (double)sb;
+    if ((double)nsteps * per_step <= budget) {
+      ckpt_every = 1;
+    } else {
+      const double k = std::ceil((double)nsteps * (double)sb / budget);
+      ckpt_every = (int32_t)std::min<double>(std::max(2.0, k), (double)std::max<int64_t>(nsteps, 2));
+    }
+  }
   // At tau = tau_g = 1 the reverse sweep needs only the moments of each
   // step's pulled state: with ckpt_every = 1 the steps write those (5 values
   // per node) and no state is kept; otherwise states are checkpointed every

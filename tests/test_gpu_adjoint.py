@@ -224,6 +224,18 @@ def test_full_tape_fused_run_matches_steps_and_oracle(n):
     assert np.abs(g - ref_g).max() <= 1e-11 * scale
 
 
+def test_automatic_tape_choice():
+    """ckpt_every = 0 lets the library choose: on a small lattice the tape of
+    every step fits, so the run and its gradient are those of ckpt_every = 1
+    (bitwise, FP32)."""
+    case = buoyant_case()
+    n = 40
+    with make_sim(case, "fp32") as a, make_sim(case, "fp32") as b:
+        la, lb = a.forward_taped(n, 0), b.forward_taped(n, 1)
+        assert la == lb
+        assert np.array_equal(a.adjoint(n), b.adjoint(n))
+
+
 def test_autograd_function_matches_adjoint():
     case = buoyant_case()
     n = 20
@@ -251,6 +263,9 @@ def test_adjoint_error_paths():
         assert e.value.code == -5
         with pytest.raises(TlbError) as e:
             sim.forward_taped(0, 1)
+        assert e.value.code == -1
+        with pytest.raises(TlbError) as e:
+            sim.forward_taped(5, -1)
         assert e.value.code == -1
     with make_sim(case, "fix16dev") as sim:
         with pytest.raises(TlbError) as e:
