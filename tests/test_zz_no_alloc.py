@@ -61,3 +61,38 @@ def test_noalloc_rejects_a_lattice_beyond_the_workspace():
             sim.droplets(0.8, noalloc=True)
         assert e.value.code == TLB_EINVAL
         assert "static workspace" in str(e.value)
+
+
+def test_noalloc_reports_more_droplets_than_the_workspace():
+    """131 072 single-node droplets on 1024 x 512 (the workspace holds 16 384):
+    the no-allocation call numbers them all but sums only those it has room
+    for, then reports TLB_EINVAL; the allocating call on the same handle grows
+    its buffer and returns them all."""
+    lx, ly = 1024, 512
+    mask = np.zeros((ly, lx), bool)
+    mask[::2, ::2] = True
+    print("noalloc: 1024x512 with 131072 single-node droplets", flush=True)
+    with Simulation(dict(workloads.BASE_PARAMS), np.where(mask, 1.36, 0.08),
+                    np.where(mask, 0.08, 1.36), workloads.conduction_profile(lx, ly),
+                    t_bottom=np.ones(lx), precision="fp32") as sim:
+        with pytest.raises(TlbError) as e:
+            sim.droplets(0.8, noalloc=True)
+        assert e.value.code == TLB_EINVAL and "workspace" in str(e.value)
+        d = sim.droplets(0.8, labels=True)
+        assert len(d["root"]) == 131072
+        assert np.all(d["size"] == 1)
+        np.testing.assert_array_equal(d["label"][mask], np.arange(131072))
+        assert np.all(d["label"][~mask] == -1)
+
+
+def test_no_droplets():
+    """A threshold above every density: no droplet, every label -1, on both
+    entry points."""
+    w = workloads.small()
+    print("noalloc: small 128x64, threshold above every density", flush=True)
+    with Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], t_bottom=w["t_bottom"],
+                    precision="fp32") as sim:
+        for noalloc in (False, True):
+            d = sim.droplets(10.0, labels=True, noalloc=noalloc)
+            assert len(d["root"]) == 0
+            assert np.all(d["label"] == -1)
