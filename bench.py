@@ -197,6 +197,9 @@ def precision_study(steps: int, every: int, storages) -> dict:
         e["nu_mean_rel_err"] = abs(e["nu_mean"] - nu_ref) / abs(nu_ref)
         e["mass_a_drift"] = (obs["mass_a"] - m0[pr]["mass_a"]) / m0[pr]["mass_a"]
         e["mass_b_drift"] = (obs["mass_b"] - m0[pr]["mass_b"]) / m0[pr]["mass_b"]
+        info = sim.launch_info()
+        e["launch"] = ("fused two-step, %d lanes, %d-row chunks" % (info["fused_lanes"], info["fused_rows"])
+                       if info["fused_rows"] > 0 else "single steps")
         out["storages"][pr] = e
     out["wall_s"] = round(time.perf_counter() - t0, 1)
     return out
