@@ -165,6 +165,27 @@ int tlb_init(tlb_handle **out, const tlb_params *p, const double *rho_a,
              const double *uy0, const uint8_t *solid, const double *t_bottom,
              void *hip_stream);
 
+/* Device bytes of the workspace tlb_init_external needs for these
+ * parameters and solid flags (host, ly*lx, or NULL): both population
+ * buffers, the per-block observable partials, the observables, the bottom
+ * temperature, the solid flags and the link masks, each part 256-byte
+ * aligned. Queries the current device (the launch geometry depends on it).
+ * Returns the byte count, or TLB_EINVAL for invalid parameters. */
+int64_t tlb_workspace_bytes(const tlb_params *p, const uint8_t *solid);
+
+/* tlb_init with the step path's device buffers placed in a caller's device
+ * allocation on the current device (`workspace`, workspace_bytes >=
+ * tlb_workspace_bytes(p, solid), 256-byte aligned), for callers whose
+ * framework owns device memory (a PyTorch tensor, say). The caller keeps
+ * the workspace alive and does not touch it until tlb_destroy, which does
+ * not free it. Analyses (fields, stress, droplets, the adjoint's tape) still
+ * allocate their own buffers on first use. Errors as tlb_init, and
+ * TLB_EINVAL for a NULL, misaligned or too small workspace. */
+int tlb_init_external(tlb_handle **out, const tlb_params *p, const double *rho_a,
+                      const double *rho_b, const double *temp, const double *ux0,
+                      const double *uy0, const uint8_t *solid, const double *t_bottom,
+                      void *hip_stream, void *workspace, int64_t workspace_bytes);
+
 /* Advance nsteps >= 0 time steps of Eqs. (1) and (16): per node, pull
  * streaming with bounce-back / anti-bounce-back at solid links, moments,
  * forces, velocity shift (Eq. (6)) and BGK collision. Enqueues only. With

@@ -21,7 +21,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "fp16dev": 2, "bf16dev": 3, "fix16dev": 4}
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = (
-    "tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_stress",
+    "tlb_init", "tlb_init_external", "tlb_workspace_bytes", "tlb_step", "tlb_observables",
+    "tlb_get_fields", "tlb_get_stress",
     "tlb_row_averages", "tlb_droplets", "tlb_droplets_noalloc", "tlb_get_populations",
     "tlb_set_bottom_temperature", "tlb_forward_taped", "tlb_adjoint_step", "tlb_time", "tlb_launch_info", "tlb_destroy",
     "tlb_last_error",
@@ -100,6 +101,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     vp = ctypes.c_void_p
     lib.tlb_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), dp, dp, dp, dp, dp,
                              ctypes.POINTER(ctypes.c_uint8), dp, vp]
+    lib.tlb_init_external.argtypes = lib.tlb_init.argtypes + [vp, ctypes.c_int64]
+    lib.tlb_workspace_bytes.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_uint8)]
+    lib.tlb_workspace_bytes.restype = ctypes.c_int64
     lib.tlb_step.argtypes = [vp, ctypes.c_int64]
     lib.tlb_observables.argtypes = [vp, ctypes.POINTER(Obs)]
     lib.tlb_get_fields.argtypes = [vp, dp, dp, dp, dp, dp]
@@ -118,7 +122,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tlb_destroy.argtypes = [vp]
     lib.tlb_last_error.argtypes = [vp]
     lib.tlb_last_error.restype = ctypes.c_char_p
-    for name in ("tlb_init", "tlb_step", "tlb_observables", "tlb_get_fields", "tlb_get_stress",
+    for name in ("tlb_init", "tlb_init_external", "tlb_step", "tlb_observables",
+                 "tlb_get_fields", "tlb_get_stress",
                  "tlb_row_averages", "tlb_droplets", "tlb_droplets_noalloc",
                  "tlb_get_populations", "tlb_set_bottom_temperature",
                  "tlb_forward_taped", "tlb_adjoint_step", "tlb_launch_info", "tlb_destroy"):
@@ -162,6 +167,10 @@ class Simulation:
     Field arrays are (ly, lx) with x fastest. By default the work runs on
     torch's current stream.
 
+    ``device_memory``: "library" (the library allocates its device buffers)
+    or "torch" (the state and step buffers live in a uint8 tensor that
+    torch's caching allocator owns, through ``tlb_init_external``).
+
     ``launch`` (optional) sets the launch choices of ``tlb_params``: ``fused``
     ("auto", "never", "always"), ``fused_rows``, ``fused_strip``, ``fused_lanes``, ``rows``
     (0 or absent: chosen by the library), and the kernel-selection flags
@@ -169,7 +178,8 @@ class Simulation:
     """
 
     def __init__(self, params: dict, rho_a, rho_b, temp, *, solid=None, t_bottom=None,
-                 ux0=None, uy0=None, precision: str = "fp32", stream="torch", launch=None):
+                 ux0=None, uy0=None, precision: str = "fp32", stream="torch", launch=None,
+                 device_memory: str = "library"):
         self._lib = load_library()
         self._h = ctypes.c_void_p()
         rho_a = np.ascontiguousarray(np.asarray(rho_a, dtype=np.float64))
@@ -225,10 +235,23 @@ class Simulation:
         self._drop_cap = max(4096, lx * ly // 64)
         self._tape_generation = 0  # bumped by every forward_taped
         s = _current_stream() if stream == "torch" else stream
-        rc = self._lib.tlb_init(ctypes.byref(self._h), ctypes.byref(p), _dp(rho_a), _dp(rho_b),
-                                _dp(temp), _dp(ux0), _dp(uy0),
-                                None if sol is None else sol.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
-                                _dp(t_bottom), ctypes.c_void_p(s) if s else None)
+        sol_p = None if sol is None else sol.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        args = (ctypes.byref(self._h), ctypes.byref(p), _dp(rho_a), _dp(rho_b), _dp(temp),
+                _dp(ux0), _dp(uy0), sol_p, _dp(t_bottom), ctypes.c_void_p(s) if s else None)
+        if device_memory not in ("library", "torch"):
+            raise ValueError("device_memory must be 'library' or 'torch'")
+        self._workspace = None
+        if device_memory == "torch":
+            # the step path's buffers in a tensor torch's allocator owns
+            import torch
+            nbytes = self._lib.tlb_workspace_bytes(ctypes.byref(p), sol_p)
+            if nbytes < 0:
+                raise TlbError(int(nbytes), self._lib.tlb_last_error(None).decode())
+            self._workspace = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+            rc = self._lib.tlb_init_external(*args, ctypes.c_void_p(self._workspace.data_ptr()),
+                                             int(nbytes))
+        else:
+            rc = self._lib.tlb_init(*args)
         if rc != TLB_OK:
             raise TlbError(rc, self._lib.tlb_last_error(None).decode())
 
@@ -353,8 +376,9 @@ class Simulation:
     def close(self) -> None:
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            self._lib.tlb_destroy(h)
+            self._lib.tlb_destroy(h)  # synchronises the stream first
             self._h = ctypes.c_void_p()
+        self._workspace = None
 
     def __del__(self):
         try:

@@ -30,6 +30,8 @@ struct tlb_handle {
   int device = 0;                  // HIP device current at tlb_init
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  bool external = false;           // buf, partials, obs, t_bottom, solid, link in a
+                                   // caller's workspace (tlb_init_external)
   // the adjoint's second stream (segment recompute beside the reverse
   // sweep, default priority) and its events, created on first use
   hipStream_t side = nullptr;
@@ -522,16 +524,11 @@ int run_droplets(tlb_handle* h, const char* who, DropBuffers& b, bool grow, doub
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const double* rho_b,
-             const double* temp, const double* ux0, const double* uy0, const uint8_t* solid,
-             const double* t_bottom, void* hip_stream) {
-  g_init_error[0] = 0;
-  if (!out) return fail(nullptr, TLB_EINVAL, "tlb_init: out is NULL");
-  *out = nullptr;
-  if (!p || !rho_a || !rho_b || !temp || !t_bottom)
-    return fail(nullptr, TLB_EINVAL, "tlb_init: NULL params or field array");
+// Parameter checks shared by tlb_init, tlb_init_external and
+// tlb_workspace_bytes.
+int check_params(const tlb_params* p) {
   if (p->lx < 1 || p->ly < 1 || (long long)p->lx * p->ly > (1LL << 30))
     return fail(nullptr, TLB_EINVAL, "tlb_init: bad lattice size %d x %d", p->lx, p->ly);
   if (p->precision < TLB_FP64 || p->precision > TLB_FIX16_DEV)
@@ -553,6 +550,49 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
   if (!(p->tau > 0.5) || !(p->tau_g > 0.5) || !finite_positive(p->rho0) || !(p->dt_nominal != 0) ||
       !std::isfinite(p->dt_nominal))
     return fail(nullptr, TLB_EINVAL, "tlb_init: need tau > 1/2, tau_g > 1/2, rho0 > 0, dt_nominal != 0");
+  return TLB_OK;
+}
+
+// Layout of the step path's device buffers (each part 256-byte aligned):
+// both population buffers, the per-block observable partials, the
+// observables, the bottom temperature, the solid flags and the link masks.
+struct Workspace {
+  size_t buf = 0, partials = 0, obs = 0, t_bottom = 0, solid = 0, link = 0, total = 0;
+};
+
+Workspace workspace_layout(const tlb_params& p, size_t state_b, size_t nblocks) {
+  const size_t n = (size_t)p.lx * p.ly;
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  Workspace w;
+  w.buf = 0;
+  w.partials = 2 * up(state_b);
+  w.obs = w.partials + up(nblocks * tlbk::kObsSums * sizeof(double));
+  w.t_bottom = w.obs + up(8 * sizeof(double));
+  w.solid = w.t_bottom + up((size_t)p.lx * sizeof(double));
+  w.link = w.solid + up(n);
+  w.total = w.link + up(n * sizeof(uint16_t));
+  return w;
+}
+
+bool any_solid(const uint8_t* solid, size_t n) {
+  if (!solid) return false;
+  for (size_t q = 0; q < n; ++q)
+    if (solid[q] != 0) return true;
+  return false;
+}
+
+int init_impl(tlb_handle** out, const tlb_params* p, const double* rho_a, const double* rho_b,
+              const double* temp, const double* ux0, const double* uy0, const uint8_t* solid,
+              const double* t_bottom, void* hip_stream, void* workspace, size_t workspace_bytes) {
+  g_init_error[0] = 0;
+  if (!out) return fail(nullptr, TLB_EINVAL, "tlb_init: out is NULL");
+  *out = nullptr;
+  if (!p || !rho_a || !rho_b || !temp || !t_bottom)
+    return fail(nullptr, TLB_EINVAL, "tlb_init: NULL params or field array");
+  int prc = check_params(p);
+  if (prc != TLB_OK) return prc;
+  if (workspace && (reinterpret_cast<uintptr_t>(workspace) % 256) != 0)
+    return fail(nullptr, TLB_EINVAL, "tlb_init_external: workspace not 256-byte aligned");
 
   tlb_handle* h = new (std::nothrow) tlb_handle();
   if (!h) return fail(nullptr, TLB_ENOMEM, "tlb_init: host allocation failed");
@@ -639,31 +679,47 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
   } while (0)
 
   const size_t buf_bytes = state_bytes(h);
-  INIT_HIP(hipMalloc(&h->buf[0], buf_bytes));
-  INIT_HIP(hipMalloc(&h->buf[1], buf_bytes));
-  INIT_HIP(hipMemsetAsync(h->buf[0], 0, buf_bytes, h->stream));
-  INIT_HIP(hipMemsetAsync(h->buf[1], 0, buf_bytes, h->stream));
   const size_t nblocks = (size_t)h->launch.grid.x * h->launch.grid.y;
-  INIT_HIP(hipMalloc(&h->partials, nblocks * tlbk::kObsSums * sizeof(double)));
-  INIT_HIP(hipMalloc(&h->obs, 8 * sizeof(double)));
-  INIT_HIP(hipMalloc(&h->t_bottom, lx * (is_fp64(h) ? sizeof(double) : sizeof(float))));
-  INIT_HIP(hipMalloc(&h->solid, n));
+  if (workspace) {
+    const Workspace ws = workspace_layout(*p, buf_bytes, nblocks);
+    if (workspace_bytes < ws.total) {
+      fail(nullptr, TLB_EINVAL, "tlb_init_external: workspace of %zu bytes, %zu needed",
+           workspace_bytes, ws.total);
+      return cleanup_fail(TLB_EINVAL);
+    }
+    char* base = static_cast<char*>(workspace);
+    h->external = true;
+    h->buf[0] = base + ws.buf;
+    h->buf[1] = base + ws.buf + (ws.partials - ws.buf) / 2;
+    h->partials = reinterpret_cast<double*>(base + ws.partials);
+    h->obs = reinterpret_cast<double*>(base + ws.obs);
+    h->t_bottom = base + ws.t_bottom;
+    h->solid = reinterpret_cast<uint8_t*>(base + ws.solid);
+    if (h->has_solid) h->link = reinterpret_cast<uint16_t*>(base + ws.link);
+  } else {
+    INIT_HIP(hipMalloc(&h->buf[0], buf_bytes));
+    INIT_HIP(hipMalloc(&h->buf[1], buf_bytes));
+    INIT_HIP(hipMalloc(&h->partials, nblocks * tlbk::kObsSums * sizeof(double)));
+    INIT_HIP(hipMalloc(&h->obs, 8 * sizeof(double)));
+    INIT_HIP(hipMalloc(&h->t_bottom, lx * (is_fp64(h) ? sizeof(double) : sizeof(float))));
+    INIT_HIP(hipMalloc(&h->solid, n));
+    if (h->has_solid) INIT_HIP(hipMalloc(&h->link, n * sizeof(uint16_t)));
+  }
+  INIT_HIP(hipMemsetAsync(h->buf[1], 0, buf_bytes, h->stream));
   INIT_HIP(hipMemcpyAsync(h->solid, sol.data(), n, hipMemcpyHostToDevice, h->stream));
-  if (h->has_solid) {
-    INIT_HIP(hipMalloc(&h->link, n * sizeof(uint16_t)));
+  if (h->has_solid)
     INIT_HIP(hipMemcpyAsync(h->link, link.data(), n * sizeof(uint16_t), hipMemcpyHostToDevice,
                             h->stream));
-  }
   rc = tlb_set_bottom_temperature(h, t_bottom);
   if (rc != TLB_OK) {
     snprintf(g_init_error, sizeof g_init_error, "%s", h->err);
     return cleanup_fail(rc);
   }
 
-  // initial fields -> f(0) in buf[1] -> f*(0) in buf[0]
-  double* d_fields = nullptr;
+  // initial fields (staged in buf[0], which holds at least 40 bytes per
+  // node) -> f(0) in buf[1] -> f*(0) in buf[0]
+  double* d_fields = static_cast<double*>(h->buf[0]);
   const int nf = (ux0 && uy0) ? 5 : 3;
-  INIT_HIP(hipMalloc(&d_fields, nf * n * sizeof(double)));
   const double* srcs[5] = {rho_a, rho_b, temp, ux0, uy0};
   for (int k = 0; k < nf; ++k)
     INIT_HIP(hipMemcpyAsync(d_fields + k * n, srcs[k], n * sizeof(double), hipMemcpyHostToDevice,
@@ -678,16 +734,53 @@ int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const d
     });
   }
   INIT_HIP(hipGetLastError());
+  INIT_HIP(hipMemsetAsync(h->buf[0], 0, buf_bytes, h->stream));
   launch_pass(h, tlbh::Pass::kInitStep, h->buf[1], h->buf[0]);
   INIT_HIP(hipGetLastError());
   h->obs_t = 0;
   INIT_HIP(hipStreamSynchronize(h->stream));
-  INIT_HIP(hipFree(d_fields));
 #undef INIT_HIP
   h->cur = 0;
   h->t = 0;
   *out = h;
   return TLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tlb_init(tlb_handle** out, const tlb_params* p, const double* rho_a, const double* rho_b,
+             const double* temp, const double* ux0, const double* uy0, const uint8_t* solid,
+             const double* t_bottom, void* hip_stream) {
+  return init_impl(out, p, rho_a, rho_b, temp, ux0, uy0, solid, t_bottom, hip_stream, nullptr, 0);
+}
+
+int tlb_init_external(tlb_handle** out, const tlb_params* p, const double* rho_a,
+                      const double* rho_b, const double* temp, const double* ux0,
+                      const double* uy0, const uint8_t* solid, const double* t_bottom,
+                      void* hip_stream, void* workspace, int64_t workspace_bytes) {
+  if (!workspace || workspace_bytes <= 0) {
+    g_init_error[0] = 0;
+    if (out) *out = nullptr;
+    return fail(nullptr, TLB_EINVAL, "tlb_init_external: NULL or empty workspace");
+  }
+  return init_impl(out, p, rho_a, rho_b, temp, ux0, uy0, solid, t_bottom, hip_stream, workspace,
+                   (size_t)workspace_bytes);
+}
+
+int64_t tlb_workspace_bytes(const tlb_params* p, const uint8_t* solid) {
+  if (!p) return fail(nullptr, TLB_EINVAL, "tlb_workspace_bytes: NULL params");
+  int rc = check_params(p);
+  if (rc != TLB_OK) return rc;
+  const size_t n = (size_t)p->lx * p->ly;
+  const bool has_solid = any_solid(solid, n);
+  const long long pitch = (p->lx + 63) / 64 * 64;
+  const size_t state_b = buffer_planes(p->precision) * (size_t)(pitch * p->ly) *
+                         storage_bytes(p->precision);
+  const bool tau_one = p->tau == 1.0 && p->tau_g == 1.0 && !(p->launch_flags & TLB_LAUNCH_GENERAL_PATH);
+  const tlbh::Geometry g = choose_launch(*p, state_b, has_solid, tau_one);
+  return (int64_t)workspace_layout(*p, state_b, (size_t)g.grid.x * g.grid.y).total;
 }
 
 int tlb_step(tlb_handle* h, int64_t nsteps) {
@@ -1182,6 +1275,12 @@ int64_t tlb_time(const tlb_handle* h) { return h ? h->t : -1; }
 int tlb_destroy(tlb_handle* h) {
   if (!h) return TLB_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->external) {  // the caller's workspace
+    h->buf[0] = h->buf[1] = h->t_bottom = nullptr;
+    h->link = nullptr;
+    h->solid = nullptr;
+    h->partials = h->obs = nullptr;
+  }
   void* ptrs[] = {h->buf[0],   h->buf[1],     h->link,       h->solid,      h->t_bottom,
                   h->partials, h->obs,        h->fields,     h->rows,       h->export_buf,
                   h->ckpt,     h->tape,       h->mtape,      h->adj,        h->adj_scalars,

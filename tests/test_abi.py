@@ -157,3 +157,20 @@ def test_binding_validates_shapes_before_calling():
         tlb.Simulation(w["params"], w["rho_a"], w["rho_b"][:, :5], w["temp"])
     with pytest.raises(ValueError):
         tlb.Simulation(w["params"], w["rho_a"], w["rho_b"], w["temp"], precision="fp8")
+
+
+def test_init_external_rejects_a_missing_workspace_without_device():
+    lib = tlb.load_library()
+    p = _params()
+    f = np.ones(p.lx * p.ly)
+    tb = np.ones(p.lx)
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    h = ctypes.c_void_p(123)
+    for ws, nbytes in ((None, 1 << 20), (ctypes.c_void_p(4096), 0)):
+        rc = lib.tlb_init_external(ctypes.byref(h), ctypes.byref(p), dp(f), dp(f), dp(f), None, None,
+                                   None, dp(tb), None, ws, nbytes)
+        assert rc == tlb.TLB_EINVAL
+        assert h.value is None
+        assert "workspace" in lib.tlb_last_error(None).decode()
+    bad = _params(tau=0.4)
+    assert lib.tlb_workspace_bytes(ctypes.byref(bad), None) == tlb.TLB_EINVAL
