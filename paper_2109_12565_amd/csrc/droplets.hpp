@@ -182,24 +182,33 @@ __global__ __launch_bounds__(256) void drop_local(DropArgs a) {
 // Global union pass over the links the tiles did not cover: from a tile's
 // last column (or the lattice's, across the periodic seam) to the right, and
 // from a tile's top row upwards.
-__global__ __launch_bounds__(256) void drop_union_border(DropArgs a) {
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= a.n || a.parent[q] < 0) return;
-  const int x = q % a.lx, y = q / a.lx;
-  if (x % kLocalW == kLocalW - 1 || x == a.lx - 1) {
-    const int right = y * a.lx + (x + 1 == a.lx ? 0 : x + 1);
-    if (right != q && a.parent[right] >= 0) unite(a.parent, q, right, a.n + 1, a.error);
-  }
-  if (y % kLocalH == kLocalH - 1 && y + 1 < a.ly) {
-    const int up = q + a.lx;
-    if (a.parent[up] >= 0) unite(a.parent, q, up, a.n + 1, a.error);
-  }
+// Threads of drop_union_border: one per node of a tile's last column
+// (its right link; the last tile's is the periodic seam), then one per
+// node of a tile's last row below the top row (its upper link).
+__host__ __device__ inline int border_columns(int lx) { return (lx + kLocalW - 1) / kLocalW; }
+__host__ __device__ inline int border_rows(int ly) { return (ly - 1) / kLocalH; }
+__host__ __device__ inline long long border_links(int lx, int ly) {
+  return (long long)border_columns(lx) * ly + (long long)border_rows(ly) * lx;
 }
 
-__global__ __launch_bounds__(256) void drop_compress(DropArgs a) {
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= a.n || a.parent[q] < 0) return;
-  atomicMin(a.parent + q, find_root(a.parent, q, a.n + 1, a.error));
+__global__ __launch_bounds__(256) void drop_union_border(DropArgs a) {
+  long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long nv = (long long)border_columns(a.lx) * a.ly;
+  if (e < nv) {
+    const int k = (int)(e / a.ly), y = (int)(e - (long long)k * a.ly);
+    const int x = min((k + 1) * kLocalW, a.lx) - 1;
+    const int q = y * a.lx + x;
+    const int right = y * a.lx + (x + 1 == a.lx ? 0 : x + 1);
+    if (right != q && a.parent[q] >= 0 && a.parent[right] >= 0)
+      unite(a.parent, q, right, a.n + 1, a.error);
+    return;
+  }
+  e -= nv;
+  if (e >= (long long)border_rows(a.ly) * a.lx) return;
+  const int r = (int)(e / a.lx), x = (int)(e - (long long)r * a.lx);
+  const int y = (r + 1) * kLocalH - 1;  // below ly - 1
+  const int q = y * a.lx + x;
+  if (a.parent[q] >= 0 && a.parent[q + a.lx] >= 0) unite(a.parent, q, q + a.lx, a.n + 1, a.error);
 }
 
 // Roots per tile of kDropTile nodes.
@@ -337,7 +346,8 @@ __global__ __launch_bounds__(256) void drop_accumulate(DropArgs a) {
     const int y = ys + k;
     if (x >= a.lx || y >= a.ly) break;
     const int q = y * a.lx + x;
-    const int32_t root = a.parent[q];
+    // the cluster root (the walk halves the path, as in unite)
+    const int32_t root = a.parent[q] >= 0 ? find_root(a.parent, q, a.n + 1, a.error) : -1;
     const int lab = root >= 0 ? a.rid[root] : -1;
     a.label[q] = lab;
     const int d = lab < a.capacity ? lab : -1;  // droplets beyond the room: not summed

@@ -460,14 +460,14 @@ int run_droplets(tlb_handle* h, const char* who, DropBuffers& b, bool grow, doub
   a.lx = lx;
   a.ly = ly;
   a.n = n;
-  const dim3 nodes((n + 255) / 256), block(256);
+  const dim3 block(256);
   const dim3 local_tiles((lx + tlbk::kLocalW - 1) / tlbk::kLocalW,
                          (ly + tlbk::kLocalH - 1) / tlbk::kLocalH);
   const dim3 acc_tiles((lx + tlbk::kLocalW - 1) / tlbk::kLocalW,
                        (ly + tlbk::kAccRows - 1) / tlbk::kAccRows);
   hipLaunchKernelGGL(tlbk::drop_local, local_tiles, block, 0, h->stream, a);
-  hipLaunchKernelGGL(tlbk::drop_union_border, nodes, block, 0, h->stream, a);
-  hipLaunchKernelGGL(tlbk::drop_compress, nodes, block, 0, h->stream, a);
+  const dim3 borders((unsigned)((tlbk::border_links(lx, ly) + 255) / 256));
+  if (borders.x > 0) hipLaunchKernelGGL(tlbk::drop_union_border, borders, block, 0, h->stream, a);
   hipLaunchKernelGGL(tlbk::drop_count_roots, dim3(tiles), block, 0, h->stream, a);
   hipLaunchKernelGGL(tlbk::drop_scan_tiles, dim3(1), block, 0, h->stream, b.tiles, tiles);
   a.total = b.tiles + tiles;
