@@ -246,7 +246,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--config", default="large", choices=sorted(workloads.CONFIGS))
     ap.add_argument("--precision", default="fp32", choices=sorted(BYTES_PER_UPDATE))
-    ap.add_argument("--cpu-steps", type=int, default=25,
+    ap.add_argument("--cpu-steps", type=int, default=40,
                     help="oracle steps for the CPU baseline on all host threads (0 to skip)")
     ap.add_argument("--cpu-steps-1t", type=int, default=2,
                     help="oracle steps for the one-thread CPU baseline (0 to skip)")
