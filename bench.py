@@ -267,7 +267,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the step runs on one GPU only (no multi-GPU halo exchange); --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         return 2
 

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -174,3 +175,14 @@ def test_init_external_rejects_a_missing_workspace_without_device():
         assert "workspace" in lib.tlb_last_error(None).decode()
     bad = _params(tau=0.4)
     assert lib.tlb_workspace_bytes(ctypes.byref(bad), None) == tlb.TLB_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asked for more it says so and exits
+    with status 2 before touching a device."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = r.stdout.strip().splitlines()[-1]
+    assert "one GPU only" in line and '"n_gpus": 2' in line
