@@ -132,12 +132,19 @@ def test_dev16_fused_launch_from_gpu_state(precision, name, u_wall, rows, lanes)
     case["params"] = dict(case["params"], u_wall=u_wall)
     sim, info = make(case, precision, True, rows, lanes=lanes)
     assert info["fused_rows"] > 0 and info["fused_lanes"] == (lanes or 128)
-    sim.step(4)
+    check_dev16_launch(sim, case, precision, f"{name} rows {rows}")
+
+
+def check_dev16_launch(sim, case, precision, label, warm=4):
+    """`warm` steps, then tlb_step(3) against 3 oracle steps from the decoded
+    state, with the bound of 16 half ulps of the largest moving deviation
+    (plus FP32 arithmetic) on each density and the temperature."""
+    sim.step(warm)
     state = sim.populations()
     sim.step(3)
     ora = Oracle(ModelParams(**case["params"]), case["rho_a"], case["rho_b"], case["temp"],
                  solid=case.get("solid"), t_bottom=case.get("t_bottom"))
-    ora.load_post_collision(state, 5).step(2)   # streams f*(4): the state of time 5
+    ora.load_post_collision(state, warm + 1).step(2)   # streams f*(warm): time warm + 1
     got, ref = sim.fields(), ora.fields()
     pr = sim.params
     solid = case.get("solid")
@@ -152,8 +159,21 @@ def test_dev16_fused_launch_from_gpu_state(precision, name, u_wall, rows, lanes)
         hu = 0.5 * 2.0 ** (np.floor(np.log2(max(big, 2.0 ** emin))) - mant)
         err = np.abs(got[key] - ref[key])[fluid].max()
         bound = 16 * hu + 1e-5 * np.abs(ref[key]).max()
-        print(precision, name, rows, key, "err", err, "bound", bound, flush=True)
+        print(precision, label, key, "err", err, "bound", bound, flush=True)
         assert err <= bound, (key, err, bound)
+
+
+@pytest.mark.parametrize("precision", sorted(HALF_ULP_BITS))
+def test_full_size_dev16_fused_launch_from_gpu_state(precision):
+    """The 16-bit storages on 4096 x 2048 with posts in the launch
+    configuration the library picks there (256-lane blocks, as the benchmark
+    times them): one fused launch and a single step from the GPU's state
+    after 20 steps, against the oracle, to the bound above."""
+    w = workloads.large()
+    sim, info = make(w, precision, True)
+    assert info["fused_rows"] > 0 and info["fused_lanes"] == 256
+    check_dev16_launch(sim, w, precision, "large", warm=20)
+    sim.close()
 
 
 def test_fp64_fused_matches_oracle():
