@@ -28,6 +28,7 @@ import workloads  # noqa: E402
 
 METRIC = "MLUPS and % HBM roofline (FP32 vs FP16-storage); adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
+ANALYSIS_CALLS = 5   # steady-state calls of the row averages and the droplet analysis
 # Algorithmic bytes per node update: the 27 populations read once and
 # written once (FP16 / BF16 deviations: 24 16-bit moving populations and 3
 # FP32 rest populations), plus one byte of solid flag when the lattice has
@@ -311,23 +312,28 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     # The first calls of the two analyses below allocate their buffers: one
-    # call each (the droplets' one timed as first_call_ms), then the timed
-    # steady-state calls.
+    # call each (the droplets' one timed as first_call_ms), then the
+    # steady-state calls, best of ANALYSIS_CALLS wall-clock times each.
     sim.row_averages()
     t_drop_first = time.perf_counter()
     sim.droplets(0.8)
     t_drop_first = time.perf_counter() - t_drop_first
+
+    def best_of(fn):
+        best, out = float("inf"), None
+        for _ in range(ANALYSIS_CALLS):
+            t = time.perf_counter()
+            out = fn()
+            best = min(best, time.perf_counter() - t)
+        return best, out
+
     # stress fields + row averages of the same time level (Couette rheology
     # observables): one pass of the step kernel without store, then the row
     # reduction and the copy of 2 * ly doubles (synchronising)
-    t_rows = time.perf_counter()
-    rows = sim.row_averages()
-    t_rows = time.perf_counter() - t_rows
+    t_rows, rows = best_of(sim.row_averages)
     # droplet detection of the same time level: fields pass, labelling,
     # exact per-droplet sums, droplet Nusselt numbers, copy of the results
-    t_drop = time.perf_counter()
-    drops = sim.droplets(0.8)
-    t_drop = time.perf_counter() - t_drop
+    t_drop, drops = best_of(lambda: sim.droplets(0.8))
     total_ms = e0.elapsed_time(e2)         # whole job: steps + observables
 
     # Launch durations, measured directly with HIP events on the library's
@@ -445,9 +451,10 @@ def main() -> int:
         "roofline": roof,
         "check": {"mass_a": obs["mass_a"], "mass_b": obs["mass_b"], "nu": obs["nu"],
                   "wall_s": round(wall, 3)},
-        "row_averages": {"ms": round(t_rows * 1e3, 3), "pxy_av_mean": float(np.mean(rows["pxy_av"])),
+        "row_averages": {"ms": round(t_rows * 1e3, 3), "calls": ANALYSIS_CALLS, "pxy_av_mean": float(np.mean(rows["pxy_av"])),
                          "u_av_top": float(rows["u_av"][-1])},
-        "droplets": {"ms": round(t_drop * 1e3, 3), "first_call_ms": round(t_drop_first * 1e3, 3),
+        "droplets": {"ms": round(t_drop * 1e3, 3), "calls": ANALYSIS_CALLS,
+                     "first_call_ms": round(t_drop_first * 1e3, 3),
                      "count": int(len(drops["root"])),
                      "threshold": 0.8, "nu_mean": float(np.mean(drops["nu"])) if len(drops["nu"]) else None},
     }
