@@ -103,7 +103,8 @@ def adjoint_ratio(steps: int, ckpt: int, precision: str, config: str = "mid") ->
     recompute included) over the time of the plain forward, for the same
     `steps` steps of an emulsion with a noisy bottom temperature: the
     1024x512 lattice (its gradient is zero: in 500 steps no signal crosses
-    512 rows) or the 1024x64 strip (a live gradient). ckpt = 1 keeps the
+    512 rows), the 1024x64 strip (a live gradient) or the 4096x2048 lattice
+    with flat walls. ckpt = 1 keeps the
     moments of every step's pulled state in HBM (no recompute); tape_gib is
     the device memory of the tape (moments, checkpoints, recompute buffers). Steady state: a first taped run and
     reverse sweep on the handle (from the initial state; their loss and
@@ -254,6 +255,9 @@ def main() -> int:
     ap.add_argument("--study", choices=["precision"], default=None,
                     help="instead of the benchmark, print the precision study (storages vs the "
                          "FP64 oracle on the 512x256 crop)")
+    ap.add_argument("--adjoint-large-steps", type=int, default=0,
+                    help="also time the adjoint on the 4096x2048 lattice with flat walls over "
+                         "this many steps, moment tape and checkpoints every 25 (0 to skip)")
     ap.add_argument("--adjoint-steps", type=int, default=500,
                     help="steps of the adjoint/forward time ratio on the 1024x512 emulsion "
                          "(FP32, checkpoints every 25; 0 to skip)")
@@ -467,6 +471,9 @@ def main() -> int:
         out["adjoint"] = adjoint_ratio(args.adjoint_steps, 1, "fp32")
         out["adjoint_ckpt"] = adjoint_ratio(args.adjoint_steps, 25, "fp32")
         out["adjoint_strip"] = adjoint_ratio(args.adjoint_steps, 1, "fp32", "strip")
+    if args.adjoint_large_steps > 0:
+        out["adjoint_large"] = adjoint_ratio(args.adjoint_large_steps, 1, "fp32", "large-flat")
+        out["adjoint_large_ckpt"] = adjoint_ratio(args.adjoint_large_steps, 25, "fp32", "large-flat")
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.cpu_steps_1t)
     print(json.dumps(out), flush=True)

@@ -161,6 +161,14 @@ def large(seed: int = 3, steps: int = 1000) -> dict:
                 params=dict(BASE_PARAMS))
 
 
+def large_flat(seed: int = 3, steps: int = 500) -> dict:
+    """4096 x 2048 with the ``large`` recipe but flat walls (no posts): the
+    full-size lattice for the adjoint, which takes flat walls only."""
+    d = _emulsion(4096, 2048, seed, 167, 84, 10.0, 0.01, 1e-3, posts=False)
+    return dict(d, name="large-flat-4096x2048", lx=4096, ly=2048, seed=seed, steps=steps,
+                params=dict(BASE_PARAMS))
+
+
 def crop(seed: int = 4, steps: int = 5000) -> dict:
     """512 x 256 lattice built with the 'large' recipe (21 x 10 discs)."""
     d = _emulsion(512, 256, seed, 21, 10, 10.0, 0.01, 1e-3, posts=True)
@@ -198,4 +206,5 @@ def single_droplet(lx: int, ly: int, radius: float) -> dict:
                 temp=np.zeros((ly, lx)))
 
 
-CONFIGS = {"small": small, "mid": mid, "large": large, "crop": crop, "strip": adjoint_strip}
+CONFIGS = {"small": small, "mid": mid, "large": large, "large-flat": large_flat, "crop": crop,
+           "strip": adjoint_strip}
